@@ -1,0 +1,189 @@
+/*
+ * amber_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct CPU implementation of the single-pulse
+ * search hot path (delay table, brute-force dedispersion, sliding boxcar
+ * integration, S/N peak).  Only the test suite, the smoke entry point and the
+ * CPU-baseline leg of the benchmark may load it; the product library shares
+ * no code with it and never calls it.
+ *
+ * Every function writes out the definition it follows, in FP64 where floating
+ * point is involved, with no blocking, fusion or reordering.  The only
+ * concession to speed is an OpenMP loop over independent DM trials / rows,
+ * which does not change any arithmetic.
+ *
+ * Where the paper is silent (it prints no delay formula, smoothing definition
+ * or S/N formula) the reading used here is stated at each function.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Cold-plasma dispersion constant, seconds * MHz^2 / (pc cm^-3). */
+#define ORACLE_KDM 4.148808e3
+
+static int oracle_threads(int n_threads)
+{
+#ifdef _OPENMP
+    return n_threads > 0 ? n_threads : omp_get_max_threads();
+#else
+    (void)n_threads;
+    return 1;
+#endif
+}
+
+/*
+ * Dispersion delay table.
+ *
+ * Section 1 of the paper names dedispersion as the shift and integration of
+ * frequency channels that removes the frequency dispersion of a pulse.  The
+ * paper prints no formula; this is the textbook delay of a cold-plasma pulse
+ * at frequency f relative to the highest channel frequency f_top:
+ *
+ *     delay[i][c] = round( K * DM_i * (1/f_c^2 - 1/f_top^2) / t_samp )
+ *
+ * with DM_i = dm_first + i * dm_step (by multiplication, Table 2's
+ * DM_FIRST / DM_STEP), K = 4.148808e3 s MHz^2 pc^-1 cm^3, rounding half away
+ * from zero.  f_top is the largest entry of freq_mhz, so the top channel has
+ * delay 0 and lower channels arrive later (positive delays).
+ *
+ * Returns 0, or -1 on bad arguments (non-positive sizes, sampling time or
+ * frequencies).  max_delay receives the largest entry.
+ */
+int oracle_delay_table(int n_chan, const double *freq_mhz, double t_samp_s,
+                       int n_dm, double dm_first, double dm_step,
+                       int32_t *delays, int32_t *max_delay)
+{
+    if (n_chan <= 0 || n_dm <= 0 || !(t_samp_s > 0.0) || !freq_mhz || !delays)
+        return -1;
+    double f_top = freq_mhz[0];
+    for (int c = 0; c < n_chan; ++c) {
+        if (!(freq_mhz[c] > 0.0))
+            return -1;
+        if (freq_mhz[c] > f_top)
+            f_top = freq_mhz[c];
+    }
+    int32_t dmax = INT32_MIN;
+    for (int i = 0; i < n_dm; ++i) {
+        double dm = dm_first + (double)i * dm_step;
+        for (int c = 0; c < n_chan; ++c) {
+            double f = freq_mhz[c];
+            double x = ((ORACLE_KDM * dm) * (1.0 / (f * f) - 1.0 / (f_top * f_top))) / t_samp_s;
+            int32_t d = (int32_t)llround(x);
+            delays[(size_t)i * n_chan + c] = d;
+            if (d > dmax)
+                dmax = d;
+        }
+    }
+    if (max_delay)
+        *max_delay = dmax;
+    return 0;
+}
+
+/*
+ * Brute-force incoherent dedispersion (the one-step dedispersion the paper
+ * contrasts with its two-step subband scheme in Section 5):
+ *
+ *     dd[i][t] = sum over c of in[c][t + delay[i][c]],   0 <= t < n_out
+ *
+ * in is channel-major uint8 with row stride `stride` bytes; dd is int32 with
+ * row stride n_out.  Every sample read must exist: 0 <= delay and
+ * n_out + delay <= n_in, otherwise -1 is returned and nothing is written.
+ */
+int oracle_dedisperse(const int32_t *delays, int n_dm, int n_chan,
+                      const uint8_t *in, int64_t stride, int64_t n_in,
+                      int64_t n_out, int32_t *dd, int n_threads)
+{
+    if (n_dm <= 0 || n_chan <= 0 || n_out < 0 || n_in < 0 || stride < n_in)
+        return -1;
+    for (size_t k = 0; k < (size_t)n_dm * n_chan; ++k)
+        if (delays[k] < 0 || n_out + delays[k] > n_in)
+            return -1;
+    int nt = oracle_threads(n_threads);
+    #pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
+    for (int i = 0; i < n_dm; ++i) {
+        const int32_t *drow = delays + (size_t)i * n_chan;
+        for (int64_t t = 0; t < n_out; ++t) {
+            int32_t sum = 0;
+            for (int c = 0; c < n_chan; ++c)
+                sum += in[(size_t)c * stride + (size_t)(t + drow[c])];
+            dd[(size_t)i * n_out + t] = sum;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Sliding boxcar integration of one dedispersed series ("smoothing" of the
+ * dedispersed time series, Section 2), for a single width w:
+ *
+ *     box[t] = sum over k < w of dd[t + k],   0 <= t < n_out - w + 1
+ *
+ * rows of dd have stride n_out; rows of box have stride n_out - w + 1 and are
+ * int64.  Returns -1 unless 1 <= w <= n_out.
+ */
+int oracle_boxcar(const int32_t *dd, int n_dm, int64_t n_out, int w,
+                  int64_t *box, int n_threads)
+{
+    if (n_dm <= 0 || w < 1 || w > n_out)
+        return -1;
+    int64_t nw = n_out - w + 1;
+    int nt = oracle_threads(n_threads);
+    #pragma omp parallel for num_threads(nt) schedule(static)
+    for (int i = 0; i < n_dm; ++i) {
+        const int32_t *row = dd + (size_t)i * n_out;
+        for (int64_t t = 0; t < nw; ++t) {
+            int64_t s = 0;
+            for (int k = 0; k < w; ++k)
+                s += row[t + k];
+            box[(size_t)i * nw + t] = s;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Signal-to-noise of the peak of each series (the S/N step of Section 2):
+ *
+ *     mu    = (1/N) sum x[t]
+ *     sigma = sqrt( (1/N) sum (x[t] - mu)^2 )          (population, two-pass)
+ *     snr   = (max x - mu) / sigma,   or 0 when sigma == 0
+ *     peak  = smallest t with x[t] == max x
+ *
+ * over the N values of each row (stride N).  All arithmetic in FP64.
+ */
+int oracle_snr(const int64_t *x, int n_rows, int64_t n, double *snr,
+               int32_t *peak, int n_threads)
+{
+    if (n_rows <= 0 || n < 1)
+        return -1;
+    int nt = oracle_threads(n_threads);
+    #pragma omp parallel for num_threads(nt) schedule(static)
+    for (int r = 0; r < n_rows; ++r) {
+        const int64_t *row = x + (size_t)r * n;
+        double sum = 0.0;
+        int64_t best = row[0];
+        int64_t best_t = 0;
+        for (int64_t t = 0; t < n; ++t) {
+            sum += (double)row[t];
+            if (row[t] > best) {
+                best = row[t];
+                best_t = t;
+            }
+        }
+        double mu = sum / (double)n;
+        double ss = 0.0;
+        for (int64_t t = 0; t < n; ++t) {
+            double d = (double)row[t] - mu;
+            ss += d * d;
+        }
+        double sigma = sqrt(ss / (double)n);
+        snr[r] = sigma > 0.0 ? ((double)best - mu) / sigma : 0.0;
+        peak[r] = (int32_t)best_t; /* all values equal when sigma == 0: t = 0 */
+    }
+    return 0;
+}

@@ -1,0 +1,267 @@
+"""Pins of the CPU oracle against what the physics and mathematics fix.
+
+None of these compare the oracle with itself: each check uses an independent
+route -- physical constants, exact (extended-precision) evaluation margins,
+invariants, special cases that reduce to a plain channel sum or a library
+routine, brute force on tiny inputs, or a closed-form S/N prediction.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _codata():
+    vals = {}
+    with open(os.path.join(GOLDEN, "codata_2018.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = float(v)
+    return vals
+
+
+# --- delay table ---------------------------------------------------------------
+
+def test_delay_constant_matches_physics():
+    """The delay of DM = 1 pc cm^-3 at 1 GHz against an (effectively) infinite
+    reference frequency is e^2 / (8 pi^2 eps0 m_e c) * DM / f^2, derived here
+    from CODATA constants (tests/golden/codata_2018.txt)."""
+    c = _codata()
+    k_si = c["elementary_charge_C"] ** 2 / (8 * math.pi ** 2 * c["vacuum_permittivity_F_m"]
+                                            * c["electron_mass_kg"] * c["speed_of_light_m_s"])
+    pc_m = 648000.0 / math.pi * c["astronomical_unit_m"]
+    k_mhz = k_si * (pc_m * 1e6) * 1e-12          # s MHz^2 / (pc cm^-3)
+    t_samp = 1e-9
+    d, mx = oracle.delay_table(np.array([1000.0, 1e9]), t_samp, 2, 0.0, 1.0)
+    expected = k_mhz * 1.0 / 1000.0 ** 2 / t_samp
+    assert d[1, 1] == 0 and d[0, 0] == 0
+    assert abs(d[1, 0] - expected) / expected < 2e-6
+    assert mx == d[1, 0]
+
+
+def test_delay_inverse_square_law():
+    """Against a far reference, halving the frequency multiplies the delay by 4."""
+    f = np.array([600.0, 1200.0, 1e9])
+    d, _ = oracle.delay_table(f, 1e-6, 3, 0.0, 100.0)
+    for i in range(3):
+        assert abs(int(d[i, 0]) - 4 * int(d[i, 1])) <= 4
+    assert d[2, 1] > 1000
+
+
+def test_delay_linear_in_dm_and_inverse_in_tsamp():
+    g = workloads.small().geom
+    f = g.freqs()
+    d1, _ = oracle.delay_table(f, g.t_samp_s, 64, 0.0, 1.0)
+    d2, _ = oracle.delay_table(f, g.t_samp_s, 64, 0.0, 2.0)
+    assert np.all(np.abs(d2.astype(np.int64) - 2 * d1) <= 1)
+    dh, _ = oracle.delay_table(f, g.t_samp_s / 2, 64, 0.0, 1.0)
+    assert np.all(np.abs(dh.astype(np.int64) - 2 * d1) <= 1)
+    # dm_first offsets the grid by multiplication, not accumulation
+    do, _ = oracle.delay_table(f, g.t_samp_s, 32, 32.0, 1.0)
+    assert np.array_equal(do, d1[32:])
+
+
+def test_delay_relative_to_highest_channel():
+    """Delays are measured against the highest frequency present: removing the
+    top channel re-references the others by the old delay of the new top."""
+    f = np.array([1250.0, 1400.0, 1550.0])
+    d3, _ = oracle.delay_table(f, 81.92e-6, 50, 0.0, 10.0)
+    d2, _ = oracle.delay_table(f[:2], 81.92e-6, 50, 0.0, 10.0)
+    assert np.all(d3[:, 2] == 0) and np.all(d2[:, 1] == 0)
+    assert np.all(np.abs(d3[:, 0].astype(np.int64) - d3[:, 1] - d2[:, 0]) <= 1)
+    # channel order does not matter: f_top is the maximum, wherever it sits
+    dp, _ = oracle.delay_table(f[::-1].copy(), 81.92e-6, 50, 0.0, 10.0)
+    assert np.array_equal(dp, d3[:, ::-1])
+
+
+@pytest.mark.parametrize("wl", [workloads.small(), workloads.beam()], ids=lambda w: w.name)
+def test_delay_invariants_and_tie_margin(wl):
+    g = wl.geom
+    f = g.freqs()
+    d, mx = oracle.delay_table(f, g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+    assert d.shape == (g.n_dm, g.n_chan)
+    assert np.all(d[0] == 0)                      # DM = 0
+    assert np.all(d[:, -1] == 0)                  # top channel
+    assert np.all(np.diff(d, axis=0) >= 0)        # non-decreasing in DM
+    assert np.all(np.diff(d, axis=1) <= 0)        # non-increasing in frequency
+    assert mx == d.max() == d[-1, 0]
+    # Evaluate the same real number in 80-bit extended precision: no entry may
+    # sit within 1e-9 of a rounding tie, and rounding the extended value must
+    # give the oracle's table (so FP64 evaluation order cannot matter).
+    fl = f.astype(np.longdouble)
+    ftop = fl.max()
+    dm = (np.longdouble(g.dm_first) + np.arange(g.n_dm, dtype=np.longdouble) * np.longdouble(g.dm_step))
+    x = (np.longdouble(4.148808e3) * dm[:, None]) * (1 / (fl * fl) - 1 / (ftop * ftop))[None, :] / np.longdouble(g.t_samp_s)
+    frac = x - np.floor(x)
+    assert np.min(np.abs(frac - 0.5)) > 1e-9
+    assert np.array_equal(np.floor(x + 0.5).astype(np.int64), d.astype(np.int64))
+
+
+def test_delay_rejects_bad_args():
+    with pytest.raises(ValueError):
+        oracle.delay_table(np.array([1000.0, -1.0]), 1e-4, 4, 0.0, 1.0)
+    with pytest.raises(ValueError):
+        oracle.delay_table(np.array([1000.0]), 0.0, 4, 0.0, 1.0)
+
+
+# --- dedispersion ---------------------------------------------------------------
+
+def test_dedisperse_dm0_is_channel_sum():
+    x = workloads.noise(64, 700, 768, seed=3)
+    d = np.zeros((1, 64), dtype=np.int32)
+    dd = oracle.dedisperse(d, x, 700, 700)
+    assert np.array_equal(dd[0], x[:, :700].astype(np.int64).sum(axis=0))
+
+
+def test_dedisperse_impulse_response():
+    """A single unit sample at (c, tau) lands at t = tau - delay[i][c] (sign and
+    index of the shift), and nowhere else."""
+    rng = np.random.default_rng(11)
+    n_chan, n_dm, n_out = 7, 5, 40
+    delays = rng.integers(0, 9, size=(n_dm, n_chan)).astype(np.int32)
+    n_in = n_out + int(delays.max())
+    for c, tau in [(0, 0), (3, 12), (6, n_in - 1), (2, 25)]:
+        x = np.zeros((n_chan, n_in), dtype=np.uint8)
+        x[c, tau] = 1
+        dd = oracle.dedisperse(delays, x, n_in, n_out)
+        for i in range(n_dm):
+            t = tau - delays[i, c]
+            expect = np.zeros(n_out, dtype=np.int64)
+            if 0 <= t < n_out:
+                expect[t] = 1
+            assert np.array_equal(dd[i], expect)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_dedisperse_brute_force_tiny(seed):
+    delays, x, n_in = workloads.tiny(n_chan=8, n_dm=8, n_out=64, seed=seed)
+    dd = oracle.dedisperse(delays, x, n_in, 64)
+    ref = np.zeros((8, 64), dtype=np.int64)
+    for i in range(8):
+        for t in range(64):
+            s = 0
+            for c in range(8):
+                s += int(x[c, t + delays[i, c]])
+            ref[i, t] = s
+    assert np.array_equal(dd, ref)
+
+
+def test_dedisperse_linearity_and_permutation():
+    delays, x, n_in = workloads.tiny(n_chan=16, n_dm=6, n_out=100, seed=9)
+    a = (x // 2).astype(np.uint8)
+    b = (x - a).astype(np.uint8)
+    assert np.array_equal(oracle.dedisperse(delays, a, n_in, 100) + oracle.dedisperse(delays, b, n_in, 100),
+                          oracle.dedisperse(delays, x, n_in, 100))
+    perm = np.random.default_rng(4).permutation(16)
+    assert np.array_equal(oracle.dedisperse(delays[:, perm], x[perm], n_in, 100),
+                          oracle.dedisperse(delays, x, n_in, 100))
+
+
+def test_dedisperse_rejects_out_of_range():
+    delays, x, n_in = workloads.tiny(n_chan=4, n_dm=3, n_out=20, seed=5)
+    with pytest.raises(ValueError):
+        oracle.dedisperse(delays, x, n_in - 1, 20)
+    bad = delays.copy()
+    bad[1, 2] = -1
+    with pytest.raises(ValueError):
+        oracle.dedisperse(bad, x, n_in, 20)
+
+
+# --- boxcar -----------------------------------------------------------------------
+
+def test_boxcar_identity_doubling_and_convolve():
+    rng = np.random.default_rng(21)
+    dd = rng.integers(0, 400000, size=(5, 300)).astype(np.int32)
+    assert np.array_equal(oracle.boxcar(dd, 1), dd.astype(np.int64))
+    for w in (1, 2, 4, 8, 16, 32):
+        bw = oracle.boxcar(dd, w)
+        b2 = oracle.boxcar(dd, 2 * w)
+        n2 = 300 - 2 * w + 1
+        assert np.array_equal(b2, bw[:, :n2] + bw[:, w:w + n2])
+    for w in (3, 7, 64, 300):
+        bw = oracle.boxcar(dd, w)
+        for i in range(5):
+            assert np.array_equal(bw[i], np.convolve(dd[i].astype(np.int64), np.ones(w, dtype=np.int64), "valid"))
+    with pytest.raises(ValueError):
+        oracle.boxcar(dd, 301)
+
+
+# --- S/N ----------------------------------------------------------------------------
+
+def test_snr_matches_numpy_routine():
+    rng = np.random.default_rng(5)
+    x = rng.integers(-1000, 100000, size=(7, 999)).astype(np.int64)
+    s, p = oracle.snr(x)
+    for r in range(7):
+        xf = x[r].astype(np.float64)
+        assert s[r] == pytest.approx((xf.max() - xf.mean()) / xf.std(ddof=0), rel=1e-12)
+        assert p[r] == int(np.argmax(x[r]))
+
+
+def test_snr_closed_form_and_invariance():
+    for n, m, h in [(8192, 1, 7), (1000, 10, 123456), (12, 3, 2)]:
+        x = np.zeros(n, dtype=np.int64)
+        x[n // 3:n // 3 + m] = h
+        s, p = oracle.snr(x)
+        assert s[0] == pytest.approx(math.sqrt((n - m) / m), rel=1e-12)
+        assert p[0] == n // 3
+    rng = np.random.default_rng(6)
+    x = rng.integers(0, 1000, size=(1, 500)).astype(np.int64)
+    s0, p0 = oracle.snr(x)
+    s1, p1 = oracle.snr(3 * x + 17)
+    assert s1[0] == pytest.approx(s0[0], rel=1e-12) and p1[0] == p0[0]
+
+
+def test_snr_single_spike_value():
+    x = np.zeros(8192, dtype=np.int64)
+    x[100] = 5
+    assert oracle.snr(x)[0][0] == pytest.approx(90.5041, abs=1e-4)
+
+
+def test_snr_degenerate_cases():
+    s, p = oracle.snr(np.full((2, 50), 42, dtype=np.int64))
+    assert np.all(s == 0.0) and np.all(p == 0)
+    x = np.array([[1, 5, 2, 5, 5]], dtype=np.int64)
+    assert oracle.snr(x)[1][0] == 1              # first of equal maxima
+    s, p = oracle.snr(np.array([[9]], dtype=np.int64))
+    assert s[0] == 0.0 and p[0] == 0              # one sample: sigma = 0
+
+
+# --- the injected pulse --------------------------------------------------------------
+
+def _predicted_snr(n_chan, amp, pulse_w, t0, n_out, w, sigma):
+    """Closed-form S/N of a noise-free boxcar pulse seen through a sliding window
+    of width w, with the noise variance sigma^2 * n_chan * w plus the pulse's own
+    variance across the series (the pulse is part of the statistics)."""
+    n = n_out - w + 1
+    t = np.arange(n)
+    overlap = np.clip(np.minimum(t + w, t0 + pulse_w) - np.maximum(t, t0), 0, None)
+    s = amp * n_chan * overlap.astype(np.float64)
+    return (s.max() - s.mean()) / math.sqrt(sigma ** 2 * n_chan * w + s.var())
+
+
+def test_injected_pulse_recovered_small():
+    wl = workloads.small()
+    g = wl.geom
+    delays, mx = oracle.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+    x, n_in = workloads.make_input(wl, delays, mx)
+    dd, s, p = oracle.search(delays, x, n_in, wl.n_out, wl.widths)
+    pulse = wl.pulses[0]
+    i, k, best = oracle.best_candidate(s)
+    assert (i, wl.widths[k]) == (pulse.dm_index, pulse.width)
+    sigma = math.sqrt(16.0 ** 2 + 1.0 / 12.0)
+    for kk, w in enumerate(wl.widths):
+        pred = _predicted_snr(g.n_chan, pulse.amp, pulse.width, pulse.t0, wl.n_out, w, sigma)
+        assert abs(s[kk, pulse.dm_index] - pred) < 2.0, (w, s[kk, pulse.dm_index], pred)
+        # the peak sits where the window overlaps the pulse
+        assert pulse.t0 - w < p[kk, pulse.dm_index] < pulse.t0 + pulse.width
+    # off the pulse's DM the detection is weaker
+    assert s[:, pulse.dm_index].max() > s[:, pulse.dm_index + 2].max() + 5
