@@ -1,0 +1,188 @@
+/*
+ * amber.h -- C ABI of the MI355X (gfx950) single-pulse search hot path.
+ *
+ * The hot path follows the pipeline the paper tunes (Section 2: dedispersion,
+ * smoothing of the dedispersed series, S/N computation), with brute-force
+ * one-step dedispersion (Section 5 names it beside the two-step subband
+ * scheme) and a sliding boxcar as the smoothing step:
+ *
+ *   amber_delay_table   host, FP64: integer delay per (DM trial, channel)
+ *   amber_dedisperse    device: dd[i][t] = sum_c in[c][t + delay[i][c]]
+ *   amber_integrate     device: box_w[i][t] = sum_{k<w} dd[i][t+k]
+ *   amber_snr           device: per (w, i) peak, first argmax, mean, std -> S/N
+ *   amber_integrate_snr device: the previous two fused, box never stored
+ *   amber_tune          genetic-algorithm tile search (Section 3), fitness =
+ *                       measured time of dedisperse + integrate + S/N
+ *
+ * Conventions
+ * - Every buffer is owned by the caller.  "d_" pointers are device (HBM)
+ *   pointers, everything else is host memory.  The library never frees or
+ *   reallocates caller memory.
+ * - Device work is enqueued on `stream` (a hipStream_t, NULL = the default
+ *   stream) and returns without synchronising, except amber_tune, which
+ *   must time kernels.
+ * - Arguments are validated before any launch; a failed call returns a
+ *   negative amber_status, launches nothing, and sets a thread-local message
+ *   readable with amber_last_error().  The library never aborts the process.
+ * - Layouts are row-major.  The input is channel-major uint8: row c holds the
+ *   samples of channel c, contiguous in time, rows `in_stride` bytes apart.
+ */
+#ifndef AMBER_H
+#define AMBER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AMBER_OK = 0,
+    AMBER_E_ARG = -1,     /* bad pointer, size or value */
+    AMBER_E_SHAPE = -2,   /* buffers too small for the requested work */
+    AMBER_E_CONFIG = -3,  /* tile configuration outside the kernel's space */
+    AMBER_E_DEVICE = -4,  /* HIP runtime or launch error */
+    AMBER_E_NOMEM = -5,   /* device allocation failed */
+    AMBER_E_TIMEOUT = -6  /* a timed evaluation exceeded its limit */
+} amber_status;
+
+#define AMBER_MAX_WIDTHS 16
+
+/* Message of the last failed call on this thread ("" if none).  Valid until
+ * the next amber_* call on the same thread. */
+const char *amber_last_error(void);
+
+/* Library version string. */
+const char *amber_version(void);
+
+/* Observation geometry, the analogue of the paper's Table 2 fixed parameters
+ * (channels, frequencies, sampling time, DM_FIRST / DM_STEP / DMS). */
+typedef struct {
+    int32_t n_chan;
+    const double *freq_mhz;   /* [n_chan] channel frequencies, any order, > 0 */
+    double t_samp_s;          /* sampling time, seconds, > 0 */
+    int32_t n_dm;             /* number of DM trials, > 0 */
+    double dm_first;          /* first DM trial, pc cm^-3, >= 0 */
+    double dm_step;           /* DM trial spacing, pc cm^-3, >= 0 */
+} amber_geometry;
+
+/* Summary of a delay table, filled by amber_delay_table and required by
+ * amber_dedisperse to size its LDS windows and validate its reads. */
+typedef struct {
+    int32_t n_dm;
+    int32_t n_chan;
+    int32_t max_delay;  /* largest entry (all entries are >= 0) */
+    int32_t max_step;   /* largest delay[i+1][c] - delay[i][c]; entries never
+                           decrease along i */
+} amber_delay_info;
+
+/* Tunable tile parameters, the analogue of the paper's Table 3 user-controlled
+ * parameters, re-derived for gfx950 (64-wide wavefronts):
+ *   threads_per_dm     work-items along time per DM trial
+ *                      (nrSamplesPerBlock); a multiple of 64, <= 1024
+ *   samples_per_thread output samples per work-item (nrSamplesPerThread);
+ *                      2, 4, 8 or 16
+ *   dms_per_block      DM trials per work-group (nrDMsPerBlock), >= 1, with
+ *                      threads_per_dm * dms_per_block <= 1024
+ *   channel_unroll     channels staged in LDS per step (unroll); 1..16, power
+ *                      of two
+ *   snr_threads        work-items per work-group of the boxcar / S/N kernels
+ *                      (nrThreadsD0); 64..1024, power of two
+ *   boxcar_step[k]     consecutive outputs per work-item for width k of the
+ *                      boxcar / S/N kernels (nrItemsD0, one per width as the
+ *                      paper has one per downsampling factor); 1, 2, 4 or 8
+ * The LDS footprint of the dedispersion tile must fit in 160 KiB. */
+typedef struct {
+    int32_t threads_per_dm;
+    int32_t samples_per_thread;
+    int32_t dms_per_block;
+    int32_t channel_unroll;
+    int32_t snr_threads;
+    int32_t boxcar_step[AMBER_MAX_WIDTHS];
+} amber_tiles;
+
+/* Fill `tiles` with the library's default configuration. */
+amber_status amber_default_tiles(amber_tiles *tiles);
+
+/* Check `tiles` against the kernels' space for a problem of this shape;
+ * AMBER_OK or AMBER_E_CONFIG (with the reason in amber_last_error). */
+amber_status amber_validate_tiles(const amber_tiles *tiles, const amber_delay_info *info,
+                                  int32_t n_widths);
+
+/* Dispersion delay table (host, FP64).
+ *
+ * Dedispersion shifts each frequency channel by the dispersion delay of its
+ * frequency and sums the channels (Section 1).  The paper prints no formula;
+ * the library uses the cold-plasma delay relative to the highest channel
+ * frequency f_top:
+ *     delay[i][c] = round(4.148808e3 * DM_i * (f_c^-2 - f_top^-2) / t_samp)
+ * with DM_i = dm_first + i * dm_step, frequencies in MHz, t_samp in seconds,
+ * rounding half away from zero.
+ *
+ * delays: host int32 [n_dm][n_chan], caller-owned, fully overwritten.
+ * info:   filled with the table's summary (may be NULL).
+ * Errors: AMBER_E_ARG for NULL pointers, non-positive sizes, t_samp or
+ * frequencies, negative dm_first / dm_step, or delays beyond int32. */
+amber_status amber_delay_table(const amber_geometry *g, int32_t *delays, amber_delay_info *info);
+
+/* Brute-force dedispersion on the device:
+ *     dd[i][t] = sum over c < n_chan of in[c][t + delay[i][c]],  t < n_out
+ * integer sums, exact (int32).
+ *
+ * d_delays:  device int32 [info->n_dm][info->n_chan], the table described by
+ *            info (as written by amber_delay_table).
+ * d_in:      device uint8 [n_chan][in_stride]; in_stride >= n_in and a
+ *            multiple of 4; n_in >= n_out + info->max_delay.
+ * d_dd:      device int32 [n_dm][dd_stride]; dd_stride >= n_out.  Columns
+ *            >= n_out are not written.
+ * tiles:     NULL = library default.
+ * Reads stay inside the n_chan * in_stride input bytes and the LDS tile even
+ * if the table does not match info; results are then meaningless but the call
+ * cannot fault. */
+amber_status amber_dedisperse(const int32_t *d_delays, const amber_delay_info *info,
+                              const uint8_t *d_in, int64_t in_stride, int64_t n_in,
+                              int32_t *d_dd, int64_t dd_stride, int64_t n_out,
+                              const amber_tiles *tiles, void *stream);
+
+/* Sliding boxcar integration ("smoothing" of each dedispersed series):
+ *     box[k][i][t] = sum over j < widths[k] of dd[i][t + j],
+ *     t < n_out - widths[k] + 1
+ * d_dd:  device int32 [n_dm][dd_stride].
+ * d_box: device int32 [n_widths][n_dm][box_stride], box_stride >= n_out;
+ *        columns >= n_out - widths[k] + 1 are not written.
+ * widths: host int32 [n_widths], 1 <= widths[k] <= min(n_out, 1024),
+ *        n_widths <= AMBER_MAX_WIDTHS.  Sums must fit int32: the caller
+ *        guarantees |dd| * max(widths) < 2^31 (true for uint8 input when
+ *        n_chan * 255 * max(widths) < 2^31). */
+amber_status amber_integrate(const int32_t *d_dd, int32_t n_dm, int64_t dd_stride, int64_t n_out,
+                             const int32_t *widths, int32_t n_widths,
+                             int32_t *d_box, int64_t box_stride,
+                             const amber_tiles *tiles, void *stream);
+
+/* S/N of each boxcar series, over its N = n_out - widths[k] + 1 values:
+ *     mean = sum x / N,  std = sqrt(sum (x - mean)^2 / N)   (population)
+ *     snr[k][i] = (max x - mean) / std, or 0 when std == 0
+ *     peak_t[k][i] = smallest t with x[t] == max x
+ * Moments are accumulated in FP64 about a per-row integer reference, the
+ * finish is FP64, snr is stored as float32.
+ * d_box:    device int32 [n_widths][n_dm][box_stride] (as amber_integrate).
+ * d_snr:    device float [n_widths][n_dm].
+ * d_peak_t: device int32 [n_widths][n_dm], or NULL. */
+amber_status amber_snr(const int32_t *d_box, int32_t n_dm, int64_t box_stride, int64_t n_out,
+                       const int32_t *widths, int32_t n_widths,
+                       float *d_snr, int32_t *d_peak_t,
+                       const amber_tiles *tiles, void *stream);
+
+/* amber_integrate followed by amber_snr in one kernel: each dedispersed row is
+ * read once and its boxcar series live only in LDS and registers.  Same
+ * arguments and results as the pair, without d_box. */
+amber_status amber_integrate_snr(const int32_t *d_dd, int32_t n_dm, int64_t dd_stride, int64_t n_out,
+                                 const int32_t *widths, int32_t n_widths,
+                                 float *d_snr, int32_t *d_peak_t,
+                                 const amber_tiles *tiles, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMBER_H */

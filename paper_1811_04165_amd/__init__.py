@@ -1,0 +1,195 @@
+"""MI355X (gfx950) single-pulse search hot path: Python binding of libamber.so.
+
+Argument marshalling only: every step runs in the library's HIP kernels (or,
+for the delay table, in its FP64 host code).  Device buffers are torch CUDA
+(HIP) tensors passed by pointer; work is enqueued on the current torch stream
+unless a stream is given.  Importing this package without a built
+libamber.so raises ImportError: there is no fallback path.
+
+Steps (see include/amber.h for the exact contracts):
+    delay_table    -> (int32 [n_dm, n_chan] host array, DelayInfo)
+    dedisperse     -> int32 [n_dm, n_out]      dd[i][t] = sum_c x[c][t + delay[i][c]]
+    integrate      -> int32 [n_w, n_dm, n_out] sliding boxcars (valid prefix per width)
+    snr            -> (float32 [n_w, n_dm], int32 [n_w, n_dm]) from boxcar series
+    integrate_snr  -> the previous two fused
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from ._lib import (AMBER_MAX_WIDTHS, AmberError, DelayInfo, Geometry, Tiles, check, load)
+
+__all__ = ["AmberError", "DelayInfo", "Tiles", "default_tiles", "make_tiles", "delay_table", "dedisperse",
+           "integrate", "snr", "integrate_snr", "validate_tiles", "version", "Search"]
+
+load()  # fail loudly at import if the native library is missing
+
+
+def version() -> str:
+    return load().amber_version().decode()
+
+
+def default_tiles() -> Tiles:
+    t = Tiles()
+    check(load().amber_default_tiles(ctypes.byref(t)))
+    return t
+
+
+def make_tiles(threads_per_dm=None, samples_per_thread=None, dms_per_block=None, channel_unroll=None,
+               snr_threads=None, boxcar_step=None) -> Tiles:
+    """Default tiles with the given fields replaced; boxcar_step is an int or a per-width list."""
+    t = default_tiles()
+    for name, v in (("threads_per_dm", threads_per_dm), ("samples_per_thread", samples_per_thread),
+                    ("dms_per_block", dms_per_block), ("channel_unroll", channel_unroll),
+                    ("snr_threads", snr_threads)):
+        if v is not None:
+            setattr(t, name, int(v))
+    if boxcar_step is not None:
+        steps = [boxcar_step] * AMBER_MAX_WIDTHS if np.isscalar(boxcar_step) else list(boxcar_step)
+        for k in range(AMBER_MAX_WIDTHS):
+            t.boxcar_step[k] = int(steps[k] if k < len(steps) else steps[-1])
+    return t
+
+
+def validate_tiles(tiles: Tiles, info: DelayInfo, n_widths: int) -> None:
+    check(load().amber_validate_tiles(ctypes.byref(tiles), ctypes.byref(info), int(n_widths)))
+
+
+def delay_table(freq_mhz, t_samp_s: float, n_dm: int, dm_first: float, dm_step: float):
+    """FP64 host delay table.  Returns (int32 [n_dm, n_chan], DelayInfo)."""
+    f = np.ascontiguousarray(freq_mhz, dtype=np.float64)
+    g = Geometry(n_chan=f.size, freq_mhz=f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                 t_samp_s=float(t_samp_s), n_dm=int(n_dm), dm_first=float(dm_first), dm_step=float(dm_step))
+    out = np.empty((int(n_dm), f.size), dtype=np.int32)
+    info = DelayInfo()
+    check(load().amber_delay_table(ctypes.byref(g), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   ctypes.byref(info)))
+    return out, info
+
+
+# --- device steps -------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_dev(t, dtype, name: str, ndim: int):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if t.dim() != ndim or t.stride(-1) != 1:
+        raise ValueError("%s must be %d-D with unit stride along its last dimension" % (name, ndim))
+
+
+def _tiles_ref(tiles: Optional[Tiles]):
+    return ctypes.byref(tiles) if tiles is not None else None
+
+
+def dedisperse(delays, info: DelayInfo, x, n_in: int, n_out: int, tiles: Optional[Tiles] = None, out=None,
+               stream=None):
+    """delays: int32 CUDA [n_dm, n_chan]; x: uint8 CUDA [n_chan, stride].  Returns int32 [n_dm, n_out]."""
+    torch = _torch()
+    _check_dev(delays, torch.int32, "delays", 2)
+    _check_dev(x, torch.uint8, "x", 2)
+    if not delays.is_contiguous() or tuple(delays.shape) != (info.n_dm, info.n_chan):
+        raise ValueError("delays must be contiguous [n_dm, n_chan] matching info")
+    if x.shape[0] != info.n_chan or x.shape[1] < n_in:
+        raise ValueError("x must be [n_chan, >= n_in]")
+    if out is None:
+        out = torch.empty((info.n_dm, n_out), dtype=torch.int32, device=x.device)
+    _check_dev(out, torch.int32, "out", 2)
+    if out.shape[0] != info.n_dm or out.shape[1] < n_out:
+        raise ValueError("out must be [n_dm, >= n_out]")
+    check(load().amber_dedisperse(delays.data_ptr(), ctypes.byref(info), x.data_ptr(), x.stride(0), int(n_in),
+                                  out.data_ptr(), out.stride(0), int(n_out), _tiles_ref(tiles),
+                                  _stream_handle(stream)))
+    return out
+
+
+def _widths_arr(widths: Sequence[int]):
+    w = np.ascontiguousarray(list(widths), dtype=np.int32)
+    return w, w.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def integrate(dd, n_out: int, widths: Sequence[int], tiles: Optional[Tiles] = None, out=None, stream=None):
+    """dd: int32 CUDA [n_dm, >= n_out].  Returns int32 [n_w, n_dm, n_out] (row k valid up to n_out - w_k + 1)."""
+    torch = _torch()
+    _check_dev(dd, torch.int32, "dd", 2)
+    w, wp = _widths_arr(widths)
+    n_dm = dd.shape[0]
+    if out is None:
+        out = torch.empty((len(w), n_dm, n_out), dtype=torch.int32, device=dd.device)
+    _check_dev(out, torch.int32, "out", 3)
+    if out.shape[0] != len(w) or out.shape[1] != n_dm or out.stride(1) < n_out or out.stride(0) != n_dm * out.stride(1):
+        raise ValueError("out must be [n_w, n_dm, stride] with packed rows")
+    check(load().amber_integrate(dd.data_ptr(), n_dm, dd.stride(0), int(n_out), wp, len(w), out.data_ptr(),
+                                 out.stride(1), _tiles_ref(tiles), _stream_handle(stream)))
+    return out
+
+
+def snr(box, n_out: int, widths: Sequence[int], tiles: Optional[Tiles] = None, stream=None):
+    """box: int32 CUDA [n_w, n_dm, stride] as written by integrate.  Returns (float32 [n_w, n_dm], int32 [n_w, n_dm])."""
+    torch = _torch()
+    _check_dev(box, torch.int32, "box", 3)
+    w, wp = _widths_arr(widths)
+    n_dm = box.shape[1]
+    if box.shape[0] != len(w) or box.stride(0) != n_dm * box.stride(1):
+        raise ValueError("box must be [n_w, n_dm, stride] with packed rows")
+    s = torch.empty((len(w), n_dm), dtype=torch.float32, device=box.device)
+    p = torch.empty((len(w), n_dm), dtype=torch.int32, device=box.device)
+    check(load().amber_snr(box.data_ptr(), n_dm, box.stride(1), int(n_out), wp, len(w), s.data_ptr(), p.data_ptr(),
+                           _tiles_ref(tiles), _stream_handle(stream)))
+    return s, p
+
+
+def integrate_snr(dd, n_out: int, widths: Sequence[int], tiles: Optional[Tiles] = None, stream=None, out=None):
+    """Fused boxcar + S/N.  dd: int32 CUDA [n_dm, >= n_out].  Returns (snr float32, peak int32), [n_w, n_dm] each."""
+    torch = _torch()
+    _check_dev(dd, torch.int32, "dd", 2)
+    w, wp = _widths_arr(widths)
+    n_dm = dd.shape[0]
+    if out is None:
+        s = torch.empty((len(w), n_dm), dtype=torch.float32, device=dd.device)
+        p = torch.empty((len(w), n_dm), dtype=torch.int32, device=dd.device)
+    else:
+        s, p = out
+    check(load().amber_integrate_snr(dd.data_ptr(), n_dm, dd.stride(0), int(n_out), wp, len(w), s.data_ptr(),
+                                     p.data_ptr(), _tiles_ref(tiles), _stream_handle(stream)))
+    return s, p
+
+
+class Search:
+    """One beam geometry with its delay table resident on the device.
+
+    run(x) executes dedispersion and the fused boxcar + S/N on x (uint8 CUDA
+    [n_chan, stride]) and returns (dd, snr, peak).
+    """
+
+    def __init__(self, freq_mhz, t_samp_s, n_dm, dm_first, dm_step, n_out, widths, tiles=None, device="cuda"):
+        torch = _torch()
+        self.delays_host, self.info = delay_table(freq_mhz, t_samp_s, n_dm, dm_first, dm_step)
+        self.delays = torch.from_numpy(self.delays_host).to(device)
+        self.n_out = int(n_out)
+        self.n_in = self.n_out + self.info.max_delay
+        self.widths = tuple(int(w) for w in widths)
+        self.tiles = tiles
+        self.dd = torch.empty((self.info.n_dm, self.n_out), dtype=torch.int32, device=device)
+        self.snr = torch.empty((len(self.widths), self.info.n_dm), dtype=torch.float32, device=device)
+        self.peak = torch.empty((len(self.widths), self.info.n_dm), dtype=torch.int32, device=device)
+
+    def run(self, x, stream=None):
+        dedisperse(self.delays, self.info, x, self.n_in, self.n_out, self.tiles, out=self.dd, stream=stream)
+        integrate_snr(self.dd, self.n_out, self.widths, self.tiles, stream=stream, out=(self.snr, self.peak))
+        return self.dd, self.snr, self.peak

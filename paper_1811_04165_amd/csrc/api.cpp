@@ -1,0 +1,272 @@
+// Host side of the C ABI: error reporting, the FP64 delay table, tile
+// validation and argument checking in front of the device launchers.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+namespace amber {
+
+namespace {
+thread_local std::string g_error;
+
+// Cold-plasma dispersion constant, s MHz^2 / (pc cm^-3).
+constexpr double kDispersion = 4.148808e3;
+
+amber_tiles make_default_tiles()
+{
+    amber_tiles t{};
+    t.threads_per_dm = 64;
+    t.samples_per_thread = 16;
+    t.dms_per_block = 8;
+    t.channel_unroll = 8;
+    t.snr_threads = 256;
+    for (int k = 0; k < AMBER_MAX_WIDTHS; ++k) t.boxcar_step[k] = 4;
+    return t;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+}  // namespace
+
+amber_status fail(amber_status status, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return status;
+}
+
+void clear_error() { g_error.clear(); }
+
+amber_status hip_fail(hipError_t err, const char *what)
+{
+    return fail(AMBER_E_DEVICE, "%s: %s", what, hipGetErrorString(err));
+}
+
+const amber_tiles &default_tiles()
+{
+    static const amber_tiles t = make_default_tiles();
+    return t;
+}
+
+amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info, DedispPlan *out)
+{
+    DedispPlan p{};
+    p.tpd = t.threads_per_dm;
+    p.spt = t.samples_per_thread;
+    p.dpb = t.dms_per_block;
+    p.cu = t.channel_unroll;
+    if (p.tpd < kWave || p.tpd > kMaxThreads || p.tpd % kWave != 0)
+        return fail(AMBER_E_CONFIG, "threads_per_dm=%d must be a multiple of 64 in [64, 1024]", p.tpd);
+    if (p.spt != 2 && p.spt != 4 && p.spt != 8 && p.spt != 16)
+        return fail(AMBER_E_CONFIG, "samples_per_thread=%d must be 2, 4, 8 or 16", p.spt);
+    if (p.dpb < 1 || (int64_t)p.dpb * p.tpd > kMaxThreads)
+        return fail(AMBER_E_CONFIG, "dms_per_block=%d with threads_per_dm=%d exceeds 1024 work-items", p.dpb,
+                    p.tpd);
+    if (!is_pow2(p.cu) || p.cu > 16)
+        return fail(AMBER_E_CONFIG, "channel_unroll=%d must be a power of two <= 16", p.cu);
+    if (info.max_step < 0 || info.max_delay < 0)
+        return fail(AMBER_E_ARG, "delay info has negative max_step or max_delay");
+    p.threads = p.tpd * p.dpb;
+    p.tile_t = p.tpd * p.spt;
+    int64_t win = (int64_t)p.tile_t + (int64_t)(p.dpb - 1) * info.max_step + 4;
+    win = (win + 15) / 16 * 16;
+    int64_t lds = 2 * (int64_t)p.cu * win * 2;
+    if (lds > kMaxLdsBytes)
+        return fail(AMBER_E_CONFIG, "dedispersion tile needs %lld B of LDS (limit %lld): reduce "
+                    "channel_unroll, dms_per_block or the time tile", (long long)lds, (long long)kMaxLdsBytes);
+    p.win = (int)win;
+    p.omax = (int)(win - p.tile_t);
+    p.lds_bytes = lds;
+    *out = p;
+    return AMBER_OK;
+}
+
+amber_status plan_boxcar(const amber_tiles &t, const int32_t *widths, int32_t n_widths, int64_t n_out,
+                         BoxcarPlan *out)
+{
+    BoxcarPlan p{};
+    if (!widths || n_widths < 1 || n_widths > AMBER_MAX_WIDTHS)
+        return fail(AMBER_E_ARG, "n_widths=%d must be in [1, %d]", n_widths, AMBER_MAX_WIDTHS);
+    int maxw = 0;
+    for (int k = 0; k < n_widths; ++k) {
+        if (widths[k] < 1 || widths[k] > 1024 || widths[k] > n_out)
+            return fail(AMBER_E_ARG, "widths[%d]=%d must be in [1, min(n_out=%lld, 1024)]", k, widths[k],
+                        (long long)n_out);
+        if (widths[k] > maxw) maxw = widths[k];
+        int s = t.boxcar_step[k];
+        if (s != 1 && s != 2 && s != 4 && s != 8)
+            return fail(AMBER_E_CONFIG, "boxcar_step[%d]=%d must be 1, 2, 4 or 8", k, s);
+    }
+    if (!is_pow2(t.snr_threads) || t.snr_threads < 64 || t.snr_threads > 1024)
+        return fail(AMBER_E_CONFIG, "snr_threads=%d must be a power of two in [64, 1024]", t.snr_threads);
+    p.threads = t.snr_threads;
+    p.chunk = p.threads * 16;
+    p.maxw = maxw;
+    p.lds_bytes = (int64_t)(p.chunk + maxw + 16) * 4;
+    *out = p;
+    return AMBER_OK;
+}
+
+}  // namespace amber
+
+using namespace amber;
+
+extern "C" {
+
+const char *amber_last_error(void) { return g_error.c_str(); }
+
+const char *amber_version(void) { return "amber-mi355x 0.1 (gfx950)"; }
+
+amber_status amber_default_tiles(amber_tiles *tiles)
+{
+    clear_error();
+    if (!tiles) return fail(AMBER_E_ARG, "tiles is NULL");
+    *tiles = default_tiles();
+    return AMBER_OK;
+}
+
+amber_status amber_validate_tiles(const amber_tiles *tiles, const amber_delay_info *info, int32_t n_widths)
+{
+    clear_error();
+    if (!tiles || !info) return fail(AMBER_E_ARG, "tiles or info is NULL");
+    DedispPlan dp;
+    amber_status s = plan_dedisperse(*tiles, *info, &dp);
+    if (s != AMBER_OK) return s;
+    int32_t w[AMBER_MAX_WIDTHS];
+    if (n_widths < 1 || n_widths > AMBER_MAX_WIDTHS)
+        return fail(AMBER_E_ARG, "n_widths=%d must be in [1, %d]", n_widths, AMBER_MAX_WIDTHS);
+    for (int k = 0; k < n_widths; ++k) w[k] = 1;
+    BoxcarPlan bp;
+    return plan_boxcar(*tiles, w, n_widths, 1, &bp);
+}
+
+amber_status amber_delay_table(const amber_geometry *g, int32_t *delays, amber_delay_info *info)
+{
+    clear_error();
+    if (!g || !delays || !g->freq_mhz) return fail(AMBER_E_ARG, "NULL geometry, frequencies or output");
+    if (g->n_chan < 1 || g->n_dm < 1) return fail(AMBER_E_ARG, "n_chan=%d and n_dm=%d must be >= 1", g->n_chan, g->n_dm);
+    if (!(g->t_samp_s > 0.0) || !std::isfinite(g->t_samp_s)) return fail(AMBER_E_ARG, "t_samp must be > 0");
+    if (!(g->dm_first >= 0.0) || !(g->dm_step >= 0.0) || !std::isfinite(g->dm_first) || !std::isfinite(g->dm_step))
+        return fail(AMBER_E_ARG, "dm_first and dm_step must be finite and >= 0");
+    double f_top = 0.0;
+    for (int c = 0; c < g->n_chan; ++c) {
+        double f = g->freq_mhz[c];
+        if (!(f > 0.0) || !std::isfinite(f)) return fail(AMBER_E_ARG, "freq_mhz[%d]=%g must be > 0", c, f);
+        if (f > f_top) f_top = f;
+    }
+    const double inv_top2 = 1.0 / (f_top * f_top);
+    const int n_chan = g->n_chan;
+    int32_t max_delay = 0, max_step = 0;
+    for (int i = 0; i < g->n_dm; ++i) {
+        const double kdm = kDispersion * (g->dm_first + (double)i * g->dm_step);
+        int32_t *row = delays + (size_t)i * n_chan;
+        for (int c = 0; c < n_chan; ++c) {
+            const double f = g->freq_mhz[c];
+            const double x = (kdm * (1.0 / (f * f) - inv_top2)) / g->t_samp_s;
+            if (!(x < 2147483647.0)) return fail(AMBER_E_ARG, "delay of DM trial %d, channel %d exceeds int32", i, c);
+            const int32_t d = (int32_t)std::llround(x);
+            row[c] = d;
+            if (d > max_delay) max_delay = d;
+            if (i > 0) {
+                const int32_t step = d - row[c - (ptrdiff_t)n_chan];
+                if (step > max_step) max_step = step;
+            }
+        }
+    }
+    if (info) {
+        info->n_dm = g->n_dm;
+        info->n_chan = g->n_chan;
+        info->max_delay = max_delay;
+        info->max_step = max_step;
+    }
+    return AMBER_OK;
+}
+
+amber_status amber_dedisperse(const int32_t *d_delays, const amber_delay_info *info, const uint8_t *d_in,
+                              int64_t in_stride, int64_t n_in, int32_t *d_dd, int64_t dd_stride, int64_t n_out,
+                              const amber_tiles *tiles, void *stream)
+{
+    clear_error();
+    if (!d_delays || !info || !d_in || !d_dd) return fail(AMBER_E_ARG, "NULL pointer argument");
+    if (info->n_dm < 1 || info->n_chan < 1) return fail(AMBER_E_ARG, "info has n_dm=%d n_chan=%d", info->n_dm, info->n_chan);
+    if (n_out < 0 || n_in < 0) return fail(AMBER_E_ARG, "n_out and n_in must be >= 0");
+    if (n_out > (int64_t)1 << 30) return fail(AMBER_E_ARG, "n_out=%lld exceeds 2^30", (long long)n_out);
+    if (in_stride < n_in || in_stride % 4 != 0 || in_stride < 32)
+        return fail(AMBER_E_SHAPE, "in_stride=%lld must be >= n_in=%lld, >= 32 and a multiple of 4",
+                    (long long)in_stride, (long long)n_in);
+    if (((uintptr_t)d_in & 3) != 0) return fail(AMBER_E_ARG, "d_in must be 4-byte aligned");
+    if (n_in < n_out + info->max_delay)
+        return fail(AMBER_E_SHAPE, "n_in=%lld < n_out=%lld + max_delay=%d", (long long)n_in, (long long)n_out,
+                    info->max_delay);
+    if (dd_stride < n_out) return fail(AMBER_E_SHAPE, "dd_stride=%lld < n_out=%lld", (long long)dd_stride, (long long)n_out);
+    if ((int64_t)info->n_chan * 255 >= ((int64_t)1 << 31))
+        return fail(AMBER_E_ARG, "n_chan=%d can overflow int32 sums", info->n_chan);
+    DedispPlan plan;
+    amber_status s = plan_dedisperse(tiles ? *tiles : default_tiles(), *info, &plan);
+    if (s != AMBER_OK) return s;
+    if (n_out == 0) return AMBER_OK;
+    return launch_dedisperse(plan, d_delays, info->n_dm, info->n_chan, d_in, in_stride, n_in, d_dd, dd_stride, n_out,
+                             (hipStream_t)stream);
+}
+
+static amber_status check_rows(const void *p, int32_t n_dm, int64_t stride, int64_t n_out, const char *name)
+{
+    if (!p) return fail(AMBER_E_ARG, "%s is NULL", name);
+    if (n_dm < 1) return fail(AMBER_E_ARG, "n_dm=%d must be >= 1", n_dm);
+    if (n_out < 1 || n_out > (int64_t)1 << 30) return fail(AMBER_E_ARG, "n_out=%lld must be in [1, 2^30]", (long long)n_out);
+    if (stride < n_out) return fail(AMBER_E_SHAPE, "%s stride %lld < n_out=%lld", name, (long long)stride, (long long)n_out);
+    if (((uintptr_t)p & 3) != 0) return fail(AMBER_E_ARG, "%s must be 4-byte aligned", name);
+    return AMBER_OK;
+}
+
+amber_status amber_integrate(const int32_t *d_dd, int32_t n_dm, int64_t dd_stride, int64_t n_out, const int32_t *widths,
+                             int32_t n_widths, int32_t *d_box, int64_t box_stride, const amber_tiles *tiles,
+                             void *stream)
+{
+    clear_error();
+    amber_status s = check_rows(d_dd, n_dm, dd_stride, n_out, "d_dd");
+    if (s != AMBER_OK) return s;
+    if ((s = check_rows(d_box, n_dm, box_stride, n_out, "d_box")) != AMBER_OK) return s;
+    const amber_tiles &t = tiles ? *tiles : default_tiles();
+    BoxcarPlan plan;
+    if ((s = plan_boxcar(t, widths, n_widths, n_out, &plan)) != AMBER_OK) return s;
+    return launch_integrate(plan, t, d_dd, n_dm, dd_stride, n_out, widths, n_widths, d_box, box_stride,
+                            (hipStream_t)stream);
+}
+
+amber_status amber_snr(const int32_t *d_box, int32_t n_dm, int64_t box_stride, int64_t n_out, const int32_t *widths,
+                       int32_t n_widths, float *d_snr, int32_t *d_peak_t, const amber_tiles *tiles, void *stream)
+{
+    clear_error();
+    amber_status s = check_rows(d_box, n_dm, box_stride, n_out, "d_box");
+    if (s != AMBER_OK) return s;
+    if (!d_snr) return fail(AMBER_E_ARG, "d_snr is NULL");
+    const amber_tiles &t = tiles ? *tiles : default_tiles();
+    BoxcarPlan plan;
+    if ((s = plan_boxcar(t, widths, n_widths, n_out, &plan)) != AMBER_OK) return s;
+    return launch_snr(plan, t, d_box, n_dm, box_stride, n_out, widths, n_widths, d_snr, d_peak_t,
+                      (hipStream_t)stream);
+}
+
+amber_status amber_integrate_snr(const int32_t *d_dd, int32_t n_dm, int64_t dd_stride, int64_t n_out,
+                                 const int32_t *widths, int32_t n_widths, float *d_snr, int32_t *d_peak_t,
+                                 const amber_tiles *tiles, void *stream)
+{
+    clear_error();
+    amber_status s = check_rows(d_dd, n_dm, dd_stride, n_out, "d_dd");
+    if (s != AMBER_OK) return s;
+    if (!d_snr) return fail(AMBER_E_ARG, "d_snr is NULL");
+    const amber_tiles &t = tiles ? *tiles : default_tiles();
+    BoxcarPlan plan;
+    if ((s = plan_boxcar(t, widths, n_widths, n_out, &plan)) != AMBER_OK) return s;
+    return launch_integrate_snr(plan, t, d_dd, n_dm, dd_stride, n_out, widths, n_widths, d_snr, d_peak_t,
+                                (hipStream_t)stream);
+}
+
+}  // extern "C"

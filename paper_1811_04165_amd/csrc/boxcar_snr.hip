@@ -1,0 +1,381 @@
+// Boxcar integration and S/N on gfx950.
+//
+// A dedispersed row is processed in LDS chunks.  Each chunk holds the
+// exclusive prefix sum Q of `chunk` consecutive samples (uint32, modulo 2^32);
+// a boxcar of width w starting at local index u is then Q[u + w] - Q[u],
+// exact in int32 because the true sum fits (wrap-around cancels).  Chunks
+// overlap by H >= max width samples so every output of a chunk finds its whole
+// window inside it; all widths are served from the same prefix array.
+//
+// S/N statistics per (width, row): the maximum with its first index, packed
+// as one int64 key (value << 32 | ~t) so that a plain max keeps the earliest
+// peak, and FP64 sums of (x - r) and (x - r)^2 about an integer reference r
+// close to the series mean, reduced across wavefronts through LDS and
+// finished in FP64.
+#include "internal.h"
+
+#include <cfloat>
+#include <climits>
+
+namespace amber {
+namespace {
+
+struct WidthSet {
+    int32_t w[AMBER_MAX_WIDTHS];
+    int32_t step[AMBER_MAX_WIDTHS];
+    int32_t n;
+};
+
+struct Stat {
+    long long key;
+    double s1, s2;
+};
+
+__device__ __forceinline__ long long pack_key(int32_t x, int64_t t)
+{
+    // high half: the signed value; low half: ~t, so equal values prefer the earlier t
+    return (long long)(((uint64_t)(int64_t)x << 32) | (uint64_t)(0xffffffffu - (uint32_t)t));
+}
+
+__device__ __forceinline__ void stat_init(Stat &s)
+{
+    s.key = LLONG_MIN;
+    s.s1 = 0.0;
+    s.s2 = 0.0;
+}
+
+__device__ __forceinline__ void stat_add(Stat &s, int32_t x, int64_t t, double r)
+{
+    const long long k = pack_key(x, t);
+    s.key = k > s.key ? k : s.key;
+    const double d = (double)x - r;
+    s.s1 += d;
+    s.s2 = fma(d, d, s.s2);
+}
+
+__device__ __forceinline__ Stat wave_reduce(Stat s)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const long long k = __shfl_xor(s.key, off, 64);
+        s.key = k > s.key ? k : s.key;
+        s.s1 += __shfl_xor(s.s1, off, 64);
+        s.s2 += __shfl_xor(s.s2, off, 64);
+    }
+    return s;
+}
+
+// Writes (snr, peak) of one series of N values from its reduced statistics.
+__device__ __forceinline__ void finish(const Stat &s, int64_t n, double r, float *snr, int32_t *peak)
+{
+    const int32_t vmax = (int32_t)(s.key >> 32);
+    const uint32_t t = 0xffffffffu - (uint32_t)(s.key & 0xffffffffll);
+    const double m1 = s.s1 / (double)n;
+    double var = s.s2 / (double)n - m1 * m1;
+    var = var > 0.0 ? var : 0.0;
+    const double sigma = sqrt(var);
+    const double excess = ((double)vmax - r) - m1;
+    *snr = sigma > 0.0 ? (float)(excess / sigma) : 0.0f;
+    if (peak) *peak = (int32_t)t;
+}
+
+// Block reduction of per-thread stats for NW widths; thread k < n_w receives
+// width k's total.  scratch holds NW * 16 Stats.
+template <int NW>
+__device__ __forceinline__ void block_reduce(Stat (&st)[NW], int n_w, Stat *scratch)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, waves = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        if (k < n_w) {
+            Stat r = wave_reduce(st[k]);
+            if (lane == 0) scratch[k * 16 + wave] = r;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < n_w) {
+        const int k = threadIdx.x;
+        Stat tot = scratch[k * 16];
+        for (int w = 1; w < waves; ++w) {
+            const Stat o = scratch[k * 16 + w];
+            tot.key = o.key > tot.key ? o.key : tot.key;
+            tot.s1 += o.s1;
+            tot.s2 += o.s2;
+        }
+        scratch[k * 16] = tot;
+    }
+    __syncthreads();
+}
+
+// Loads samples [cs, cs + chunk) of one row (zero past n_out) and writes the
+// exclusive prefix Q[0..chunk] to LDS.  16 contiguous samples per thread.
+__device__ __forceinline__ void load_prefix(const int32_t *__restrict__ row, int64_t cs, int64_t n_out, bool vec_ok,
+                                            uint32_t *Q, uint32_t *wave_tot)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, waves = blockDim.x >> 6;
+    const int64_t base = cs + (int64_t)tid * 16;
+    uint32_t v[16];
+    if (vec_ok && base + 16 <= n_out) {
+        const int4 *p = reinterpret_cast<const int4 *>(row + base);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int4 x = p[q];
+            v[4 * q + 0] = (uint32_t)x.x; v[4 * q + 1] = (uint32_t)x.y;
+            v[4 * q + 2] = (uint32_t)x.z; v[4 * q + 3] = (uint32_t)x.w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v[e] = (base + e < n_out) ? (uint32_t)row[base + e] : 0u;
+    }
+#pragma unroll
+    for (int e = 1; e < 16; ++e) v[e] += v[e - 1];
+    // inclusive scan of thread totals within the wave
+    uint32_t incl = v[15];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wave_tot[wave] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < waves; ++w) {
+            const uint32_t x = wave_tot[w];
+            wave_tot[w] = run;
+            run += x;
+        }
+    }
+    __syncthreads();
+    const uint32_t excl = incl - v[15] + wave_tot[wave];
+    uint32_t *q = Q + tid * 16 + 1;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) q[e] = v[e] + excl;
+    if (tid == 0) Q[0] = 0u;
+    __syncthreads();
+}
+
+// Accumulates width w over the chunk's outputs [cs, cs + outs) with S
+// consecutive outputs per thread per step.
+template <int S>
+__device__ __forceinline__ void width_stats(const uint32_t *Q, int w, int outs, int64_t cs, int64_t n_valid, double r,
+                                            Stat &st)
+{
+    for (int g = threadIdx.x; g * S < outs; g += blockDim.x) {
+        const int u = g * S;
+        uint32_t a[S], b[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            a[s] = Q[u + s];
+            b[s] = Q[u + s + w];
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int64_t t = cs + u + s;
+            if (u + s < outs && t < n_valid) stat_add(st, (int32_t)(b[s] - a[s]), t, r);
+        }
+    }
+}
+
+__device__ __forceinline__ void width_stats_any(int step, const uint32_t *Q, int w, int outs, int64_t cs,
+                                                int64_t n_valid, double r, Stat &st)
+{
+    switch (step) {
+    case 1: width_stats<1>(Q, w, outs, cs, n_valid, r, st); break;
+    case 2: width_stats<2>(Q, w, outs, cs, n_valid, r, st); break;
+    case 4: width_stats<4>(Q, w, outs, cs, n_valid, r, st); break;
+    default: width_stats<8>(Q, w, outs, cs, n_valid, r, st); break;
+    }
+}
+
+// ---- fused boxcar + S/N: one work-group per dedispersed row ----------------
+template <int NW>
+__global__ __launch_bounds__(1024) void integrate_snr_kernel(const int32_t *__restrict__ dd, int n_dm,
+                                                             int64_t dd_stride, int64_t n_out, WidthSet ws, int chunk,
+                                                             int halo, int vec_ok, float *__restrict__ snr,
+                                                             int32_t *__restrict__ peak)
+{
+    extern __shared__ uint4 lds4[];
+    uint32_t *Q = reinterpret_cast<uint32_t *>(lds4);
+    Stat *scratch = reinterpret_cast<Stat *>(lds4);  // reused after the last chunk
+    __shared__ uint32_t wave_tot[16];
+    const int i = blockIdx.x;
+    const int32_t *__restrict__ row = dd + (size_t)i * dd_stride;
+    const int outs = chunk - halo;
+    const double d0 = (double)row[0];
+
+    Stat st[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) stat_init(st[k]);
+
+    for (int64_t cs = 0; cs < n_out; cs += outs) {
+        load_prefix(row, cs, n_out, vec_ok != 0, Q, wave_tot);
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            if (k < ws.n) {
+                const int w = ws.w[k];
+                width_stats_any(ws.step[k], Q, w, outs, cs, n_out - w + 1, d0 * w, st[k]);
+            }
+        }
+        __syncthreads();
+    }
+    block_reduce<NW>(st, ws.n, scratch);
+    if ((int)threadIdx.x < ws.n) {
+        const int k = threadIdx.x;
+        const int w = ws.w[k];
+        finish(scratch[k * 16], n_out - w + 1, d0 * w, snr + (size_t)k * n_dm + i,
+               peak ? peak + (size_t)k * n_dm + i : nullptr);
+    }
+}
+
+// ---- materialised boxcar: one work-group per (chunk, row) ------------------
+__global__ __launch_bounds__(1024) void integrate_kernel(const int32_t *__restrict__ dd, int n_dm, int64_t dd_stride,
+                                                         int64_t n_out, WidthSet ws, int chunk, int halo, int vec_ok,
+                                                         int32_t *__restrict__ box, int64_t box_stride)
+{
+    extern __shared__ uint4 lds4[];
+    uint32_t *Q = reinterpret_cast<uint32_t *>(lds4);
+    __shared__ uint32_t wave_tot[16];
+    const int i = blockIdx.y;
+    const int outs = chunk - halo;
+    const int64_t cs = (int64_t)blockIdx.x * outs;
+    load_prefix(dd + (size_t)i * dd_stride, cs, n_out, vec_ok != 0, Q, wave_tot);
+    for (int k = 0; k < ws.n; ++k) {
+        const int w = ws.w[k];
+        const int64_t n_valid = n_out - w + 1;
+        int32_t *__restrict__ out = box + ((size_t)k * n_dm + i) * box_stride;
+        for (int u = threadIdx.x; u < outs; u += blockDim.x) {
+            const int64_t t = cs + u;
+            if (t < n_valid) out[t] = (int32_t)(Q[u + w] - Q[u]);
+        }
+    }
+}
+
+// ---- S/N of materialised boxcar series: one work-group per (row, width) ----
+template <int S>
+__global__ __launch_bounds__(1024) void snr_kernel(const int32_t *__restrict__ box, int n_dm, int64_t box_stride,
+                                                   int64_t n_out, WidthSet ws, float *__restrict__ snr,
+                                                   int32_t *__restrict__ peak)
+{
+    __shared__ Stat scratch[16];
+    const int i = blockIdx.x, k = blockIdx.y;
+    const int w = ws.w[k];
+    const int64_t n = n_out - w + 1;
+    const int32_t *__restrict__ row = box + ((size_t)k * n_dm + i) * box_stride;
+    const double r = (double)row[0];
+    Stat st;
+    stat_init(st);
+    for (int64_t base = (int64_t)threadIdx.x * S; base < n; base += (int64_t)blockDim.x * S) {
+        int32_t v[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) v[s] = (base + s < n) ? row[base + s] : 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (base + s < n) stat_add(st, v[s], base + s, r);
+    }
+    Stat arr[1] = {st};
+    block_reduce<1>(arr, 1, scratch);
+    if (threadIdx.x == 0)
+        finish(scratch[0], n, r, snr + (size_t)k * n_dm + i, peak ? peak + (size_t)k * n_dm + i : nullptr);
+}
+
+WidthSet make_widths(const amber_tiles &t, const int32_t *widths, int n)
+{
+    WidthSet ws{};
+    for (int k = 0; k < n; ++k) {
+        ws.w[k] = widths[k];
+        ws.step[k] = t.boxcar_step[k];
+    }
+    ws.n = n;
+    return ws;
+}
+
+int halo_of(const BoxcarPlan &p) { return (p.maxw + 15) / 16 * 16; }
+
+amber_status check_chunk(const BoxcarPlan &p)
+{
+    if (p.chunk < 2 * halo_of(p))
+        return fail(AMBER_E_CONFIG, "snr_threads=%d gives chunks of %d samples, too short for width %d", p.threads,
+                    p.chunk, p.maxw);
+    return AMBER_OK;
+}
+
+template <typename F>
+amber_status allow_lds(F fn, int64_t bytes, const char *what)
+{
+    if (bytes > 64 * 1024)
+        AMBER_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)bytes),
+                  what);
+    return AMBER_OK;
+}
+
+}  // namespace
+
+amber_status launch_integrate_snr(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_dd, int n_dm,
+                                  int64_t dd_stride, int64_t n_out, const int32_t *widths, int n_widths,
+                                  float *d_snr, int32_t *d_peak, hipStream_t stream)
+{
+    amber_status s = check_chunk(p);
+    if (s != AMBER_OK) return s;
+    const WidthSet ws = make_widths(t, widths, n_widths);
+    const int halo = halo_of(p);
+    const int vec_ok = (dd_stride % 4 == 0) && (((uintptr_t)d_dd & 15) == 0);
+    // the stats scratch reuses the prefix buffer after the last chunk
+    int64_t lds = p.lds_bytes;
+    const int64_t need = (int64_t)AMBER_MAX_WIDTHS * 16 * sizeof(Stat);
+    if (lds < need) lds = need;
+    if (n_widths <= 4) {
+        if ((s = allow_lds(integrate_snr_kernel<4>, lds, "hipFuncSetAttribute(integrate_snr)")) != AMBER_OK) return s;
+        hipLaunchKernelGGL(integrate_snr_kernel<4>, dim3(n_dm), dim3(p.threads), (size_t)lds, stream, d_dd, n_dm,
+                           dd_stride, n_out, ws, p.chunk, halo, vec_ok, d_snr, d_peak);
+    } else if (n_widths <= 8) {
+        if ((s = allow_lds(integrate_snr_kernel<8>, lds, "hipFuncSetAttribute(integrate_snr)")) != AMBER_OK) return s;
+        hipLaunchKernelGGL(integrate_snr_kernel<8>, dim3(n_dm), dim3(p.threads), (size_t)lds, stream, d_dd, n_dm,
+                           dd_stride, n_out, ws, p.chunk, halo, vec_ok, d_snr, d_peak);
+    } else {
+        if ((s = allow_lds(integrate_snr_kernel<16>, lds, "hipFuncSetAttribute(integrate_snr)")) != AMBER_OK) return s;
+        hipLaunchKernelGGL(integrate_snr_kernel<16>, dim3(n_dm), dim3(p.threads), (size_t)lds, stream, d_dd, n_dm,
+                           dd_stride, n_out, ws, p.chunk, halo, vec_ok, d_snr, d_peak);
+    }
+    AMBER_HIP(hipGetLastError(), "integrate_snr launch");
+    return AMBER_OK;
+}
+
+amber_status launch_integrate(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_dd, int n_dm,
+                              int64_t dd_stride, int64_t n_out, const int32_t *widths, int n_widths, int32_t *d_box,
+                              int64_t box_stride, hipStream_t stream)
+{
+    amber_status s = check_chunk(p);
+    if (s != AMBER_OK) return s;
+    const WidthSet ws = make_widths(t, widths, n_widths);
+    const int halo = halo_of(p);
+    const int outs = p.chunk - halo;
+    const int64_t n_chunks = (n_out + outs - 1) / outs;
+    const int vec_ok = (dd_stride % 4 == 0) && (((uintptr_t)d_dd & 15) == 0);
+    if ((s = allow_lds(integrate_kernel, p.lds_bytes, "hipFuncSetAttribute(integrate)")) != AMBER_OK) return s;
+    hipLaunchKernelGGL(integrate_kernel, dim3((unsigned)n_chunks, n_dm), dim3(p.threads), (size_t)p.lds_bytes, stream,
+                       d_dd, n_dm, dd_stride, n_out, ws, p.chunk, halo, vec_ok, d_box, box_stride);
+    AMBER_HIP(hipGetLastError(), "integrate launch");
+    return AMBER_OK;
+}
+
+amber_status launch_snr(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_box, int n_dm, int64_t box_stride,
+                        int64_t n_out, const int32_t *widths, int n_widths, float *d_snr, int32_t *d_peak,
+                        hipStream_t stream)
+{
+    const WidthSet ws = make_widths(t, widths, n_widths);
+    // the per-row kernel uses the first width's step as its items per thread
+    const int step = t.boxcar_step[0];
+    dim3 grid(n_dm, n_widths);
+    switch (step) {
+    case 1: hipLaunchKernelGGL(snr_kernel<1>, grid, dim3(p.threads), 0, stream, d_box, n_dm, box_stride, n_out, ws, d_snr, d_peak); break;
+    case 2: hipLaunchKernelGGL(snr_kernel<2>, grid, dim3(p.threads), 0, stream, d_box, n_dm, box_stride, n_out, ws, d_snr, d_peak); break;
+    case 4: hipLaunchKernelGGL(snr_kernel<4>, grid, dim3(p.threads), 0, stream, d_box, n_dm, box_stride, n_out, ws, d_snr, d_peak); break;
+    default: hipLaunchKernelGGL(snr_kernel<8>, grid, dim3(p.threads), 0, stream, d_box, n_dm, box_stride, n_out, ws, d_snr, d_peak); break;
+    }
+    AMBER_HIP(hipGetLastError(), "snr launch");
+    return AMBER_OK;
+}
+
+}  // namespace amber

@@ -1,0 +1,72 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+
+#include "amber.h"
+
+namespace amber {
+
+// Records a formatted message for amber_last_error() and returns `status`.
+amber_status fail(amber_status status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+// Maps a HIP error to AMBER_E_DEVICE with the runtime's message.
+amber_status hip_fail(hipError_t err, const char *what);
+
+#define AMBER_HIP(call, what)                          \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return ::amber::hip_fail(e_, what); \
+    } while (0)
+
+constexpr int kWave = 64;
+constexpr int kMaxThreads = 1024;
+constexpr int64_t kMaxLdsBytes = 160 * 1024;
+
+// Dedispersion tile geometry derived from the tile genes and the table summary.
+struct DedispPlan {
+    int tpd, spt, dpb, cu;
+    int threads;        // tpd * dpb
+    int tile_t;         // output samples per tile: tpd * spt
+    int win;            // LDS window length in samples per channel (multiple of 16)
+    int omax;           // largest sample offset a DM may read at inside the window
+    int64_t lds_bytes;  // dynamic LDS per work-group
+};
+
+amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info, DedispPlan *out);
+
+// Boxcar / S/N geometry.
+struct BoxcarPlan {
+    int threads;   // work-items per group
+    int chunk;     // outputs per LDS chunk (threads * 16)
+    int maxw;      // largest width
+    int64_t lds_bytes;
+};
+
+amber_status plan_boxcar(const amber_tiles &t, const int32_t *widths, int32_t n_widths, int64_t n_out,
+                         BoxcarPlan *out);
+
+const amber_tiles &default_tiles();
+
+// Launchers (device translation units).
+amber_status launch_dedisperse(const DedispPlan &p, const int32_t *d_delays, int n_dm, int n_chan,
+                               const uint8_t *d_in, int64_t in_stride, int64_t n_in, int32_t *d_dd,
+                               int64_t dd_stride, int64_t n_out, hipStream_t stream);
+
+amber_status launch_integrate(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_dd, int n_dm,
+                              int64_t dd_stride, int64_t n_out, const int32_t *widths, int n_widths,
+                              int32_t *d_box, int64_t box_stride, hipStream_t stream);
+
+amber_status launch_snr(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_box, int n_dm,
+                        int64_t box_stride, int64_t n_out, const int32_t *widths, int n_widths,
+                        float *d_snr, int32_t *d_peak, hipStream_t stream);
+
+amber_status launch_integrate_snr(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_dd, int n_dm,
+                                  int64_t dd_stride, int64_t n_out, const int32_t *widths, int n_widths,
+                                  float *d_snr, int32_t *d_peak, hipStream_t stream);
+
+}  // namespace amber

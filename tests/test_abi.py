@@ -1,0 +1,114 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every function include/amber.h declares, the FP64 delay table matches
+the oracle bit for bit, and arguments are validated before any launch."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if hdr.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", hdr)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^[A-Za-z_][\w \*]*?\b(amber_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1811_04165_amd as amber
+    from paper_1811_04165_amd import _lib
+    lib = _lib.load()
+    declared = _declared_functions()
+    assert len(declared) >= 9
+    for name in declared:
+        assert hasattr(lib, name), name
+    bound = {s[0] for s in _lib.SIGNATURES}
+    assert set(declared) <= bound, set(declared) - bound
+    assert "gfx950" in amber.version()
+
+
+@pytest.mark.parametrize("wl", [workloads.small(), workloads.beam()] + workloads.batch_beams(3),
+                         ids=lambda w: w.name)
+def test_delay_table_bit_exact_vs_oracle(wl):
+    import paper_1811_04165_amd as amber
+    g = wl.geom
+    d, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+    do, mx = oracle.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+    assert np.array_equal(d, do)
+    assert info.max_delay == mx and info.n_dm == g.n_dm and info.n_chan == g.n_chan
+    assert info.max_step == int(np.diff(do, axis=0).max())
+
+
+def test_delay_table_random_geometries():
+    import paper_1811_04165_amd as amber
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        n_chan = int(rng.integers(1, 64))
+        f = rng.uniform(100.0, 3000.0, size=n_chan)
+        t_samp = float(rng.uniform(1e-5, 1e-3))
+        n_dm = int(rng.integers(1, 40))
+        first, step = float(rng.uniform(0, 50)), float(rng.uniform(0, 3))
+        d, info = amber.delay_table(f, t_samp, n_dm, first, step)
+        do, mx = oracle.delay_table(f, t_samp, n_dm, first, step)
+        assert np.array_equal(d, do) and info.max_delay == max(mx, 0)
+
+
+def test_delay_table_rejects_bad_geometry():
+    import paper_1811_04165_amd as amber
+    with pytest.raises(amber.AmberError):
+        amber.delay_table(np.array([1000.0, 0.0]), 1e-4, 4, 0.0, 1.0)
+    with pytest.raises(amber.AmberError):
+        amber.delay_table(np.array([1000.0]), 1e-4, 4, -1.0, 1.0)
+    with pytest.raises(amber.AmberError):
+        amber.delay_table(np.array([1000.0]), 0.0, 4, 0.0, 1.0)
+
+
+def test_tile_validation():
+    import paper_1811_04165_amd as amber
+    info = amber.DelayInfo(n_dm=2048, n_chan=1536, max_delay=11593, max_step=6)
+    amber.validate_tiles(amber.default_tiles(), info, 7)
+    bad = [dict(threads_per_dm=32), dict(threads_per_dm=96), dict(samples_per_thread=3),
+           dict(samples_per_thread=1), dict(dms_per_block=32, threads_per_dm=64),
+           dict(channel_unroll=3), dict(channel_unroll=32), dict(snr_threads=48), dict(boxcar_step=3),
+           dict(threads_per_dm=1024, samples_per_thread=16, channel_unroll=16)]
+    for kw in bad:
+        with pytest.raises(amber.AmberError) as e:
+            amber.validate_tiles(amber.make_tiles(**kw), info, 7)
+        assert e.value.status == -3, kw
+
+
+def test_device_calls_validate_before_launch():
+    """Invalid arguments are refused on the host, so these never reach a GPU."""
+    from paper_1811_04165_amd import _lib
+    lib = _lib.load()
+    info = _lib.DelayInfo(n_dm=4, n_chan=8, max_delay=10, max_step=2)
+    fake = ctypes.c_void_p(0x1000)
+    # n_in < n_out + max_delay
+    rc = lib.amber_dedisperse(fake, ctypes.byref(info), fake, 128, 100, fake, 100, 95, None, None)
+    assert rc == -2 and b"max_delay" in lib.amber_last_error()
+    # stride not a multiple of 4
+    rc = lib.amber_dedisperse(fake, ctypes.byref(info), fake, 130, 120, fake, 100, 100, None, None)
+    assert rc == -2
+    # NULL input
+    rc = lib.amber_dedisperse(fake, ctypes.byref(info), None, 128, 120, fake, 100, 100, None, None)
+    assert rc == -1
+    w = (ctypes.c_int32 * 2)(1, 200)
+    rc = lib.amber_integrate_snr(fake, 4, 100, 100, w, 2, fake, fake, None, None)
+    assert rc == -1 and b"widths" in lib.amber_last_error()
+    rc = lib.amber_integrate(fake, 4, 50, 100, w, 1, fake, 100, None, None)
+    assert rc == -2
+    rc = lib.amber_snr(fake, 4, 100, 100, w, 0, fake, None, None, None)
+    assert rc == -1
+    assert lib.amber_last_error() != b""
+    rc = lib.amber_default_tiles(None)
+    assert rc == -1
