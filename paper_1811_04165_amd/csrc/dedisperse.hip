@@ -72,12 +72,21 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(
             if (c < n_chan) {
                 const int64_t start = t0 + dfirst[c];
                 const int64_t g0 = start & ~(int64_t)3;
-                int64_t off = (int64_t)c * in_stride + g0 + 16 * (int64_t)it;
-                off = off < 0 ? 0 : off;
-                off = off > in_bytes - 20 ? in_bytes - 20 : off;
-                const uint32_t *src = reinterpret_cast<const uint32_t *>(in + off);
+                const int64_t off = (int64_t)c * in_stride + g0 + 16 * (int64_t)it;
+                if (off >= 0 && off + 20 <= in_bytes) {
+                    const uint32_t *src = reinterpret_cast<const uint32_t *>(in + off);
 #pragma unroll
-                for (int k = 0; k < 5; ++k) w[k] = src[k];
+                    for (int k = 0; k < 5; ++k) w[k] = src[k];
+                } else {
+                    // only dwords outside the buffer are replaced (by zero): they lie
+                    // past the last row's samples, so no output < n_out reads them
+                    const uint32_t *src = reinterpret_cast<const uint32_t *>(in);
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) {
+                        const int64_t o = off + 4 * k;
+                        w[k] = (o >= 0 && o + 4 <= in_bytes) ? src[o >> 2] : 0u;
+                    }
+                }
             }
             uint4 *r0 = lds4 + ((j * win2) >> 2) + it * 2;
             uint4 *r1 = lds4 + (((CU + j) * win2) >> 2) + it * 2;
