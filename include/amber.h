@@ -81,17 +81,19 @@ typedef struct {
  *   threads_per_dm     work-items along time per DM trial
  *                      (nrSamplesPerBlock); a multiple of 64, <= 1024
  *   samples_per_thread output samples per work-item (nrSamplesPerThread);
- *                      2, 4, 8 or 16
+ *                      4, 8, 16 or 32 (even: samples go in pairs)
  *   dms_per_block      DM trials per work-group (nrDMsPerBlock), >= 1, with
  *                      threads_per_dm * dms_per_block <= 1024
- *   channel_unroll     channels staged in LDS per step (unroll); 1..16, power
+ *   channel_unroll     channels staged in LDS per step (unroll); 1..32, power
  *                      of two
  *   snr_threads        work-items per work-group of the boxcar / S/N kernels
  *                      (nrThreadsD0); 64..1024, power of two
  *   boxcar_step[k]     consecutive outputs per work-item for width k of the
  *                      boxcar / S/N kernels (nrItemsD0, one per width as the
  *                      paper has one per downsampling factor); 1, 2, 4 or 8
- * The LDS footprint of the dedispersion tile must fit in 160 KiB. */
+ * The LDS footprint of the dedispersion tile must fit in 160 KiB and its
+ * staging must need at most 4 items of 16 samples per work-item (3 when
+ * samples_per_thread >= 16). */
 typedef struct {
     int32_t threads_per_dm;
     int32_t samples_per_thread;

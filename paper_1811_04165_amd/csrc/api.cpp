@@ -19,9 +19,9 @@ amber_tiles make_default_tiles()
 {
     amber_tiles t{};
     t.threads_per_dm = 64;
-    t.samples_per_thread = 16;
-    t.dms_per_block = 8;
-    t.channel_unroll = 8;
+    t.samples_per_thread = 8;
+    t.dms_per_block = 16;
+    t.channel_unroll = 32;
     t.snr_threads = 256;
     for (int k = 0; k < AMBER_MAX_WIDTHS; ++k) t.boxcar_step[k] = 4;
     return t;
@@ -63,25 +63,38 @@ amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info,
     p.cu = t.channel_unroll;
     if (p.tpd < kWave || p.tpd > kMaxThreads || p.tpd % kWave != 0)
         return fail(AMBER_E_CONFIG, "threads_per_dm=%d must be a multiple of 64 in [64, 1024]", p.tpd);
-    if (p.spt != 2 && p.spt != 4 && p.spt != 8 && p.spt != 16)
-        return fail(AMBER_E_CONFIG, "samples_per_thread=%d must be 2, 4, 8 or 16", p.spt);
+    if (p.spt != 4 && p.spt != 8 && p.spt != 16 && p.spt != 32)
+        return fail(AMBER_E_CONFIG, "samples_per_thread=%d must be 4, 8, 16 or 32", p.spt);
     if (p.dpb < 1 || (int64_t)p.dpb * p.tpd > kMaxThreads)
         return fail(AMBER_E_CONFIG, "dms_per_block=%d with threads_per_dm=%d exceeds 1024 work-items", p.dpb,
                     p.tpd);
-    if (!is_pow2(p.cu) || p.cu > 16)
-        return fail(AMBER_E_CONFIG, "channel_unroll=%d must be a power of two <= 16", p.cu);
+    if (!is_pow2(p.cu) || p.cu > 32)
+        return fail(AMBER_E_CONFIG, "channel_unroll=%d must be a power of two <= 32", p.cu);
     if (info.max_step < 0 || info.max_delay < 0)
         return fail(AMBER_E_ARG, "delay info has negative max_step or max_delay");
     p.threads = p.tpd * p.dpb;
     p.tile_t = p.tpd * p.spt;
-    int64_t win = (int64_t)p.tile_t + (int64_t)(p.dpb - 1) * info.max_step + 4;
+    // Offsets a DM of the tile reads at, relative to the first DM's window
+    // start (which is rounded down to 4 samples): [0, omax].
+    const int64_t omax = (int64_t)(p.dpb - 1) * info.max_step + 3;
+    if (omax > (int64_t)1 << 24)
+        return fail(AMBER_E_CONFIG, "delay steps too large for one tile (max_step=%d)", info.max_step);
+    // a DM reads dwords up to (o >> 1) + tile_t / 2 - 1 of a copy; the copy
+    // with the one-sample shift reads one byte past its window
+    int64_t win = (int64_t)p.tile_t + 2 * (omax >> 1) + 2;
     win = (win + 15) / 16 * 16;
-    int64_t lds = 2 * (int64_t)p.cu * win * 2;
+    const int64_t lds = 2 * (int64_t)p.cu * win * 2;  // two 16-bit copies per channel
     if (lds > kMaxLdsBytes)
         return fail(AMBER_E_CONFIG, "dedispersion tile needs %lld B of LDS (limit %lld): reduce "
                     "channel_unroll, dms_per_block or the time tile", (long long)lds, (long long)kMaxLdsBytes);
+    const int64_t items = p.cu * (win / 16);
+    p.maxi = (int)((items + p.threads - 1) / p.threads);
+    const int maxi_cap = p.spt >= 16 ? 3 : 4;  // prefetch registers beside the accumulators
+    if (p.maxi > maxi_cap)
+        return fail(AMBER_E_CONFIG, "staging needs %d items per work-item (max %d): reduce channel_unroll or "
+                    "enlarge the work-group", p.maxi, maxi_cap);
     p.win = (int)win;
-    p.omax = (int)(win - p.tile_t);
+    p.omax = (int)omax;
     p.lds_bytes = lds;
     *out = p;
     return AMBER_OK;

@@ -2,127 +2,208 @@
 //
 //   dd[i][t] = sum over c of in[c][t + delay[i][c]]
 //
-// A work-group owns a tile of `dpb` consecutive DM trials by `tpd * spt`
-// consecutive output samples.  It walks the channels `cu` at a time: the
-// group stages, for each of those channels, the input window every DM of the
-// tile needs (it starts at the first DM's delay; later DMs read further in,
-// never by more than (dpb - 1) * max_step samples) into LDS, widened from
-// uint8 to 16 bits, in two copies shifted by one sample so that every DM can
-// read sample pairs as aligned dwords.  Each wavefront owns one DM trial and
-// 64 * spt samples; lane l accumulates sample pairs (2l + 128k, 2l + 128k + 1)
-// as two 16-bit lanes of one dword (a packed SWAR add: one dword read and one
-// add per two samples), flushing into 32-bit totals every 256 channels
-// (256 * 255 < 2^16).  The delay of the wave's DM for a channel is uniform
-// across the wave, so its LDS address is a scalar plus the lane offset.
+// Work decomposition.  A work-group owns `dpb` consecutive DM trials and
+// `tpd * spt` consecutive output samples; each wavefront owns one DM trial
+// and 64 * spt samples.  The group walks the channels `cu` at a time.
+//
+// Staging.  For each of the `cu` channels the group copies into LDS the input
+// window every DM of the tile needs: it starts at the first DM's delay (later
+// DMs read at most (dpb - 1) * max_step samples further in).  Samples are
+// widened from uint8 to 16 bits and stored twice, the second copy shifted by
+// one sample, so the two samples at any offset are one aligned dword of one of
+// the copies.  The global loads of the next channel group (input and delays)
+// are issued before the current group is summed, so their latency hides
+// behind the sums.
+//
+// Accumulation.  Sums of up to 256 channels fit 16 bits, so each dword holds
+// two running sums and one 32-bit add advances both; lane l owns the sample
+// pairs 64k + l of its wave (consecutive lanes read consecutive dwords, so
+// LDS reads are conflict-free and pair up as ds_read2st64).  Every 256
+// channels the packed sums are added into 32-bit totals.  The LDS offset of
+// each channel for the wave's DM is computed once per group by lane j for
+// channel j and broadcast with readlane, so the per-channel cost is one
+// readlane, one address add, the reads and the adds.
 #include "internal.h"
+
+#include <cstdlib>
 
 namespace amber {
 namespace {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// v_perm_b32 selectors: bytes of {hi:next, lo:cur}; 0x0c yields a zero byte.
-constexpr uint32_t kSel01 = 0x0c010c00u;  // [0 b1 0 b0]  samples 0,1
-constexpr uint32_t kSel23 = 0x0c030c02u;  // [0 b3 0 b2]  samples 2,3
-constexpr uint32_t kSel12 = 0x0c020c01u;  // [0 b2 0 b1]  samples 1,2
-constexpr uint32_t kSel34 = 0x0c040c03u;  // [0 b4 0 b3]  samples 3,4 (b4 = next dword's b0)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) u32x4 lds_w4;
+typedef __attribute__((address_space(3))) const uint32_t lds_u1;
 
-template <int SPT, int CU>
+// v_perm_b32 selector that widens bytes a and a + 1 of {hi, lo} into the two
+// 16-bit halves of a dword (selector byte 0x0c yields zero).
+__host__ __device__ constexpr uint32_t widen_sel(int a)
+{
+    return (uint32_t)a | 0x0c00u | ((uint32_t)(a + 1) << 16) | 0x0c000000u;
+}
+
+// Maps the round-robin dispatch of work-groups over the 8 XCDs onto tiles so
+// that the groups one XCD runs are consecutive DM blocks of the same time tile
+// and share their input windows in that XCD's L2.
+__device__ __forceinline__ void tile_of_block(int nx, int ny, int remap, int &tx, int &ty)
+{
+    const int id = blockIdx.x;
+    if (remap) {
+        const int nb = nx * ny;
+        const int xcd = id & 7, local = id >> 3;
+        const int per = nb >> 3, rem = nb & 7;
+        const int logical = xcd * per + (xcd < rem ? xcd : rem) + local;
+        ty = logical % ny;
+        tx = logical / ny;
+    } else {
+        tx = id % nx;
+        ty = id / nx;
+    }
+}
+
+struct StageArgs {
+    const uint8_t *in;
+    int64_t in_stride, in_bytes;
+    const int32_t *dfirst;
+    int64_t t0;
+    int n_chan, items_per_row, n_items;
+};
+
+// Loads the 20 input bytes (16 samples + 4 of lookahead) of staging item q of
+// the channel group starting at c0.  Dwords outside the buffer read as zero:
+// they lie past the last row's samples, so no output < n_out depends on them.
+__device__ __forceinline__ void stage_load(const StageArgs &a, int c0, int q, uint32_t (&w)[5])
+{
+#pragma unroll
+    for (int k = 0; k < 5; ++k) w[k] = 0u;
+    if (q >= a.n_items) return;
+    const int j = q / a.items_per_row;
+    const int it = q - j * a.items_per_row;
+    const int c = c0 + j;
+    if (c >= a.n_chan) return;
+    const int64_t g0 = (a.t0 + a.dfirst[c]) & ~(int64_t)3;
+    const int64_t off = (int64_t)c * a.in_stride + g0 + 16 * (int64_t)it;
+    if (off >= 0 && off + 20 <= a.in_bytes) {
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(a.in + off);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) w[k] = p[k];
+    } else {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(a.in);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const int64_t o = off + 4 * k;
+            w[k] = (o >= 0 && o + 4 <= a.in_bytes) ? src[o >> 2] : 0u;
+        }
+    }
+}
+
+// Writes staging item q (16 samples) widened to 16 bits into the two copies:
+// copy s, dword m of the item holds samples 2m + s and 2m + s + 1.
+template <int CU>
+__device__ __forceinline__ void stage_store(lds_w4 *lds, int win2, int items_per_row, int n_items, int q,
+                                            const uint32_t (&w)[5])
+{
+    if (q >= n_items) return;
+    const int j = q / items_per_row;
+    const int it = q - j * items_per_row;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        uint32_t d[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int p = 2 * m + s;  // first byte of the pair within the 20 bytes
+            d[m] = __builtin_amdgcn_perm(w[(p >> 2) + 1], w[p >> 2], widen_sel(p & 3));
+        }
+        lds_w4 *dst = lds + (((s * CU + j) * win2) >> 2) + 2 * it;
+        dst[0] = u32x4{d[0], d[1], d[2], d[3]};
+        dst[1] = u32x4{d[4], d[5], d[6], d[7]};
+    }
+}
+
+template <int M, int CU, int MAXI>
 __global__ __launch_bounds__(1024) void dedisperse_kernel(
     const int32_t *__restrict__ delays, int n_dm, int n_chan,
     const uint8_t *__restrict__ in, int64_t in_stride, int64_t in_bytes,
     int32_t *__restrict__ dd, int64_t dd_stride, int64_t n_out,
-    int tpd, int dpb, int win, int omax, int store_pairs)
+    int tpd, int dpb, int win, int omax, int tiles_t, int tiles_dm, int store_vec, int remap)
 {
-    constexpr int M = SPT / 2;  // sample pairs (dwords) per lane
-    extern __shared__ uint4 lds4[];
-    uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
+    static_assert(CU <= 64, "one lane per channel of a group");
+    extern __shared__ u32x4 lds_raw[];
+    lds_w4 *lds = (lds_w4 *)lds_raw;
 
-    const int win2 = win >> 1;        // dwords per staged row copy
-    const int items_per_row = win >> 4;  // staging items of 16 samples
+    const int win2 = win >> 1;  // dwords per staged row copy
     const int tid = threadIdx.x;
     const int nthreads = blockDim.x;
     const int wave = uniform(tid >> 6);
     const int lane = tid & 63;
     const int waves_per_dm = tpd >> 6;
     const int dm_local = uniform(wave / waves_per_dm);
-    const int wave_t = uniform((wave - dm_local * waves_per_dm) * 64 * SPT);
-    const int i0 = blockIdx.y * dpb;
+    const int wave_t = uniform((wave - dm_local * waves_per_dm) * 128 * M);  // first sample of the wave
+    int tx, ty;
+    tile_of_block(tiles_t, tiles_dm, remap, tx, ty);
+    const int i0 = ty * dpb;
     const int i = i0 + dm_local;
     const bool active = i < n_dm;
-    const int64_t t0 = (int64_t)blockIdx.x * tpd * SPT;
+    const int64_t t0 = (int64_t)tx * tpd * 2 * M;
 
-    const int32_t *__restrict__ dfirst = delays + (size_t)i0 * n_chan;
+    StageArgs sa;
+    sa.in = in;
+    sa.in_stride = in_stride;
+    sa.in_bytes = in_bytes;
+    sa.dfirst = delays + (size_t)i0 * n_chan;
+    sa.t0 = t0;
+    sa.n_chan = n_chan;
+    sa.items_per_row = win >> 4;
+    sa.n_items = CU * sa.items_per_row;
     const int32_t *__restrict__ dmine = delays + (size_t)(active ? i : i0) * n_chan;
-    const int n_items = CU * items_per_row;
 
-    uint32_t acc[M];
-    uint32_t lo[M], hi[M];
+    uint32_t acc[M], lo[M], hi[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) acc[k] = lo[k] = hi[k] = 0u;
 
+    // Prefetch of the first channel group: input items, and on lane j < CU the
+    // delays of channel j for this wave's DM and for the group's first DM.
+    uint32_t pre[MAXI][5];
+#pragma unroll
+    for (int m = 0; m < MAXI; ++m) stage_load(sa, 0, tid + m * nthreads, pre[m]);
+    const int cl = lane < CU ? lane : CU - 1;
+    int d_next = 0, f_next = 0;
+    {
+        const int c = cl < n_chan ? cl : n_chan - 1;
+        d_next = dmine[c];
+        f_next = sa.dfirst[c];
+    }
+
+    const uint32_t lane_off = 4u * (uint32_t)lane;
     int since_flush = 0;
     for (int c0 = 0; c0 < n_chan; c0 += CU) {
-        // ---- stage CU channel windows into LDS (two 16-bit copies) ----
-        for (int q = tid; q < n_items; q += nthreads) {
-            const int j = q / items_per_row;
-            const int it = q - j * items_per_row;
-            const int c = c0 + j;
-            uint32_t w[5] = {0u, 0u, 0u, 0u, 0u};
-            if (c < n_chan) {
-                const int64_t start = t0 + dfirst[c];
-                const int64_t g0 = start & ~(int64_t)3;
-                const int64_t off = (int64_t)c * in_stride + g0 + 16 * (int64_t)it;
-                if (off >= 0 && off + 20 <= in_bytes) {
-                    const uint32_t *src = reinterpret_cast<const uint32_t *>(in + off);
 #pragma unroll
-                    for (int k = 0; k < 5; ++k) w[k] = src[k];
-                } else {
-                    // only dwords outside the buffer are replaced (by zero): they lie
-                    // past the last row's samples, so no output < n_out reads them
-                    const uint32_t *src = reinterpret_cast<const uint32_t *>(in);
-#pragma unroll
-                    for (int k = 0; k < 5; ++k) {
-                        const int64_t o = off + 4 * k;
-                        w[k] = (o >= 0 && o + 4 <= in_bytes) ? src[o >> 2] : 0u;
-                    }
-                }
-            }
-            uint4 *r0 = lds4 + ((j * win2) >> 2) + it * 2;
-            uint4 *r1 = lds4 + (((CU + j) * win2) >> 2) + it * 2;
-            uint4 a, b, e, f;
-            a.x = __builtin_amdgcn_perm(w[1], w[0], kSel01); a.y = __builtin_amdgcn_perm(w[1], w[0], kSel23);
-            a.z = __builtin_amdgcn_perm(w[2], w[1], kSel01); a.w = __builtin_amdgcn_perm(w[2], w[1], kSel23);
-            b.x = __builtin_amdgcn_perm(w[3], w[2], kSel01); b.y = __builtin_amdgcn_perm(w[3], w[2], kSel23);
-            b.z = __builtin_amdgcn_perm(w[4], w[3], kSel01); b.w = __builtin_amdgcn_perm(w[4], w[3], kSel23);
-            e.x = __builtin_amdgcn_perm(w[1], w[0], kSel12); e.y = __builtin_amdgcn_perm(w[1], w[0], kSel34);
-            e.z = __builtin_amdgcn_perm(w[2], w[1], kSel12); e.w = __builtin_amdgcn_perm(w[2], w[1], kSel34);
-            f.x = __builtin_amdgcn_perm(w[3], w[2], kSel12); f.y = __builtin_amdgcn_perm(w[3], w[2], kSel34);
-            f.z = __builtin_amdgcn_perm(w[4], w[3], kSel12); f.w = __builtin_amdgcn_perm(w[4], w[3], kSel34);
-            r0[0] = a; r0[1] = b;
-            r1[0] = e; r1[1] = f;
-        }
+        for (int m = 0; m < MAXI; ++m) stage_store<CU>(lds, win2, sa.items_per_row, sa.n_items, tid + m * nthreads, pre[m]);
+        // LDS byte offset of channel `cl` for this wave's DM
+        int o = d_next - f_next + (f_next & 3);
+        o = o < 0 ? 0 : (o > omax ? omax : o);
+        const uint32_t chan_off = 4u * (uint32_t)(((o & 1) * CU + cl) * win2 + (o >> 1) + (wave_t >> 1));
         __syncthreads();
+        if (c0 + CU < n_chan) {
+#pragma unroll
+            for (int m = 0; m < MAXI; ++m) stage_load(sa, c0 + CU, tid + m * nthreads, pre[m]);
+            const int c = c0 + CU + cl < n_chan ? c0 + CU + cl : n_chan - 1;
+            d_next = dmine[c];
+            f_next = sa.dfirst[c];
+        }
 
-        // ---- accumulate: one dword read + one packed add per sample pair ----
         if (active) {
+            // channels past n_chan were staged as zeros; their offsets are in range
 #pragma unroll
             for (int j = 0; j < CU; ++j) {
-                const int c = c0 + j;
-                if (c < n_chan) {
-                    const int df = dfirst[c];
-                    const int d = dmine[c];
-                    const int lead = df & 3;
-                    int o = d - df + lead;
-                    o = o < 0 ? 0 : (o > omax ? omax : o);
-                    const int row = (o & 1) ? (CU + j) : j;
-                    const uint32_t *src = lds + row * win2 + (o >> 1) + (wave_t >> 1) + lane;
+                const uint32_t base = __builtin_amdgcn_readlane(chan_off, j);
+                lds_u1 *src = (lds_u1 *)((__attribute__((address_space(3))) const char *)lds + (base + lane_off));
 #pragma unroll
-                    for (int k = 0; k < M; ++k) acc[k] += src[64 * k];
-                }
+                for (int k = 0; k < M; ++k) acc[k] += src[64 * k];
             }
             since_flush += CU;
-            if (since_flush >= 256) {
+            if (since_flush >= 256 || c0 + CU >= n_chan) {
 #pragma unroll
                 for (int k = 0; k < M; ++k) {
                     lo[k] += acc[k] & 0xffffu;
@@ -140,42 +221,59 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const int64_t t = t0 + wave_t + 128 * k + 2 * lane;
-        const int32_t v0 = (int32_t)(lo[k] + (acc[k] & 0xffffu));
-        const int32_t v1 = (int32_t)(hi[k] + (acc[k] >> 16));
-        if (t + 1 < n_out && store_pairs) {
-            *reinterpret_cast<int2 *>(out + t) = make_int2(v0, v1);
+        if (store_vec && t + 2 <= n_out) {
+            *reinterpret_cast<int2 *>(out + t) = make_int2((int)lo[k], (int)hi[k]);
         } else {
-            if (t < n_out) out[t] = v0;
-            if (t + 1 < n_out) out[t + 1] = v1;
+            if (t < n_out) out[t] = (int32_t)lo[k];
+            if (t + 1 < n_out) out[t + 1] = (int32_t)hi[k];
         }
     }
 }
 
 using KernelFn = void (*)(const int32_t *, int, int, const uint8_t *, int64_t, int64_t, int32_t *, int64_t, int64_t,
-                          int, int, int, int, int);
+                          int, int, int, int, int, int, int, int);
 
-template <int SPT>
-KernelFn pick_cu(int cu)
+template <int M, int CU>
+KernelFn pick_items(int maxi)
 {
-    switch (cu) {
-    case 1: return dedisperse_kernel<SPT, 1>;
-    case 2: return dedisperse_kernel<SPT, 2>;
-    case 4: return dedisperse_kernel<SPT, 4>;
-    case 8: return dedisperse_kernel<SPT, 8>;
-    case 16: return dedisperse_kernel<SPT, 16>;
+    switch (maxi) {
+    case 1: return dedisperse_kernel<M, CU, 1>;
+    case 2: return dedisperse_kernel<M, CU, 2>;
+    case 3: return dedisperse_kernel<M, CU, 3>;
+    case 4: return M < 8 ? dedisperse_kernel<M, CU, (M < 8 ? 4 : 3)> : nullptr;
     }
     return nullptr;
 }
 
-KernelFn pick(int spt, int cu)
+template <int M>
+KernelFn pick_cu(int cu, int maxi)
 {
-    switch (spt) {
-    case 2: return pick_cu<2>(cu);
-    case 4: return pick_cu<4>(cu);
-    case 8: return pick_cu<8>(cu);
-    case 16: return pick_cu<16>(cu);
+    switch (cu) {
+    case 1: return pick_items<M, 1>(maxi);
+    case 2: return pick_items<M, 2>(maxi);
+    case 4: return pick_items<M, 4>(maxi);
+    case 8: return pick_items<M, 8>(maxi);
+    case 16: return pick_items<M, 16>(maxi);
+    case 32: return pick_items<M, 32>(maxi);
     }
     return nullptr;
+}
+
+KernelFn pick(int spt, int cu, int maxi)
+{
+    switch (spt) {
+    case 4: return pick_cu<2>(cu, maxi);
+    case 8: return pick_cu<4>(cu, maxi);
+    case 16: return pick_cu<8>(cu, maxi);
+    case 32: return pick_cu<16>(cu, maxi);
+    }
+    return nullptr;
+}
+
+int xcd_remap_setting()
+{
+    const char *e = getenv("AMBER_XCD_REMAP");
+    return e ? atoi(e) : 1;
 }
 
 }  // namespace
@@ -185,7 +283,7 @@ amber_status launch_dedisperse(const DedispPlan &p, const int32_t *d_delays, int
                                int64_t dd_stride, int64_t n_out, hipStream_t stream)
 {
     (void)n_in;
-    KernelFn fn = pick(p.spt, p.cu);
+    KernelFn fn = pick(p.spt, p.cu, p.maxi);
     if (!fn) return fail(AMBER_E_CONFIG, "no dedispersion kernel for spt=%d cu=%d", p.spt, p.cu);
     if (p.lds_bytes > 64 * 1024)
         AMBER_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
@@ -193,13 +291,13 @@ amber_status launch_dedisperse(const DedispPlan &p, const int32_t *d_delays, int
                   "hipFuncSetAttribute(dedisperse)");
     const int64_t tiles_t = (n_out + p.tile_t - 1) / p.tile_t;
     const int64_t tiles_dm = (n_dm + p.dpb - 1) / p.dpb;
-    if (tiles_t > 0x7fffffff || tiles_dm > 65535)
+    if (tiles_t * tiles_dm > 0x7fffffff)
         return fail(AMBER_E_SHAPE, "grid of %lld x %lld tiles is too large", (long long)tiles_t, (long long)tiles_dm);
-    const int store_pairs = (dd_stride % 2 == 0) && (((uintptr_t)d_dd & 7) == 0);
-    dim3 grid((unsigned)tiles_t, (unsigned)tiles_dm);
-    hipLaunchKernelGGL(fn, grid, dim3(p.threads), (size_t)p.lds_bytes, stream, d_delays, n_dm, n_chan, d_in,
-                       in_stride, (int64_t)n_chan * in_stride, d_dd, dd_stride, n_out, p.tpd, p.dpb, p.win, p.omax,
-                       store_pairs);
+    const int store_vec = (dd_stride % 2 == 0) && (((uintptr_t)d_dd & 7) == 0);
+    static const int remap = xcd_remap_setting();
+    hipLaunchKernelGGL(fn, dim3((unsigned)(tiles_t * tiles_dm)), dim3(p.threads), (size_t)p.lds_bytes, stream,
+                       d_delays, n_dm, n_chan, d_in, in_stride, (int64_t)n_chan * in_stride, d_dd, dd_stride, n_out,
+                       p.tpd, p.dpb, p.win, p.omax, (int)tiles_t, (int)tiles_dm, store_vec, remap);
     AMBER_HIP(hipGetLastError(), "dedisperse launch");
     return AMBER_OK;
 }

@@ -33,6 +33,7 @@ struct DedispPlan {
     int threads;        // tpd * dpb
     int tile_t;         // output samples per tile: tpd * spt
     int win;            // LDS window length in samples per channel (multiple of 16)
+    int maxi;           // staging items per work-item (prefetched in registers)
     int omax;           // largest sample offset a DM may read at inside the window
     int64_t lds_bytes;  // dynamic LDS per work-group
 };

@@ -4,6 +4,7 @@ the oracle bit for bit, and arguments are validated before any launch."""
 import ctypes
 import os
 import re
+import sys
 
 import numpy as np
 import pytest
@@ -12,6 +13,7 @@ import oracle
 import workloads
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
@@ -78,8 +80,8 @@ def test_tile_validation():
     info = amber.DelayInfo(n_dm=2048, n_chan=1536, max_delay=11593, max_step=6)
     amber.validate_tiles(amber.default_tiles(), info, 7)
     bad = [dict(threads_per_dm=32), dict(threads_per_dm=96), dict(samples_per_thread=3),
-           dict(samples_per_thread=1), dict(dms_per_block=32, threads_per_dm=64),
-           dict(channel_unroll=3), dict(channel_unroll=32), dict(snr_threads=48), dict(boxcar_step=3),
+           dict(samples_per_thread=2), dict(samples_per_thread=64), dict(channel_unroll=32, dms_per_block=1), dict(dms_per_block=32, threads_per_dm=64),
+           dict(channel_unroll=3), dict(channel_unroll=64), dict(snr_threads=48), dict(boxcar_step=3),
            dict(threads_per_dm=1024, samples_per_thread=16, channel_unroll=16)]
     for kw in bad:
         with pytest.raises(amber.AmberError) as e:
@@ -112,3 +114,21 @@ def test_device_calls_validate_before_launch():
     assert lib.amber_last_error() != b""
     rc = lib.amber_default_tiles(None)
     assert rc == -1
+
+
+def test_gpu_test_tiles_are_valid():
+    """Every tile configuration the GPU parity tests launch passes host
+    validation for the geometries it is used with."""
+    import paper_1811_04165_amd as amber
+    import test_parity_gpu as t
+    for wl in (workloads.small(), workloads.beam()):
+        g = wl.geom
+        _, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+        amber.validate_tiles(amber.default_tiles(), info, len(wl.widths))
+        for kw in t.TILE_SWEEP:
+            amber.validate_tiles(amber.make_tiles(**kw), info, len(wl.widths))
+    for n_chan, n_dm, n_out, step, pad in t.ODD:
+        freqs = t.odd_freqs(n_chan, n_dm)
+        _, info = amber.delay_table(freqs, 81.92e-6, n_dm, 1.5, step)
+        for kw in t.ODD_TILES:
+            amber.validate_tiles(amber.make_tiles(**kw) if kw else amber.default_tiles(), info, 1)

@@ -69,15 +69,19 @@ def test_dedisperse_small_default(amber, torch, small_case):
 
 
 TILE_SWEEP = [
-    dict(threads_per_dm=64, samples_per_thread=2, dms_per_block=1, channel_unroll=1),
+    dict(threads_per_dm=64, samples_per_thread=4, dms_per_block=1, channel_unroll=1),
     dict(threads_per_dm=64, samples_per_thread=4, dms_per_block=16, channel_unroll=16),
     dict(threads_per_dm=128, samples_per_thread=8, dms_per_block=4, channel_unroll=2),
     dict(threads_per_dm=256, samples_per_thread=16, dms_per_block=2, channel_unroll=4),
-    dict(threads_per_dm=1024, samples_per_thread=2, dms_per_block=1, channel_unroll=8),
-    dict(threads_per_dm=512, samples_per_thread=4, dms_per_block=2, channel_unroll=16),
+    dict(threads_per_dm=1024, samples_per_thread=4, dms_per_block=1, channel_unroll=2),
+    dict(threads_per_dm=512, samples_per_thread=8, dms_per_block=2, channel_unroll=1),
     dict(threads_per_dm=64, samples_per_thread=16, dms_per_block=8, channel_unroll=8),
-    dict(threads_per_dm=64, samples_per_thread=16, dms_per_block=16, channel_unroll=4),
+    dict(threads_per_dm=64, samples_per_thread=16, dms_per_block=16, channel_unroll=16),
     dict(threads_per_dm=192, samples_per_thread=8, dms_per_block=5, channel_unroll=4),
+    dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=3, channel_unroll=16),
+    dict(threads_per_dm=64, samples_per_thread=32, dms_per_block=8, channel_unroll=8),
+    dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=8, channel_unroll=32),
+    dict(threads_per_dm=128, samples_per_thread=32, dms_per_block=4, channel_unroll=4),
 ]
 
 
@@ -99,11 +103,20 @@ ODD = [
 ]
 
 
+ODD_TILES = [None, dict(threads_per_dm=64, samples_per_thread=4, dms_per_block=3, channel_unroll=16),
+             dict(threads_per_dm=128, samples_per_thread=16, dms_per_block=4, channel_unroll=8)]
+
+
+def odd_freqs(n_chan, n_dm):
+    rng = np.random.default_rng(n_chan * 1000 + n_dm)
+    return np.sort(rng.uniform(1100.0, 1700.0, size=n_chan))[::-1].copy()   # descending, non-uniform
+
+
 @pytest.mark.parametrize("case", ODD, ids=lambda c: "ch%d-dm%d-out%d" % c[:3])
 def test_dedisperse_odd_shapes(amber, torch, case):
     n_chan, n_dm, n_out, step, pad = case
-    rng = np.random.default_rng(n_chan * 1000 + n_dm)
-    freqs = np.sort(rng.uniform(1100.0, 1700.0, size=n_chan))[::-1].copy()   # descending, non-uniform
+    rng = np.random.default_rng(n_chan * 1000 + n_dm + 1)
+    freqs = odd_freqs(n_chan, n_dm)
     d, info = amber.delay_table(freqs, 81.92e-6, n_dm, 1.5, step)
     do, mx = oracle.delay_table(freqs, 81.92e-6, n_dm, 1.5, step)
     assert np.array_equal(d, do)
@@ -112,8 +125,7 @@ def test_dedisperse_odd_shapes(amber, torch, case):
     x = rng.integers(0, 256, size=(n_chan, stride)).astype(np.uint8)
     ref = oracle.dedisperse(do, x, n_in, n_out)
     dev, xd = torch.from_numpy(d).cuda(), torch.from_numpy(x).cuda()
-    for kw in (None, dict(threads_per_dm=64, samples_per_thread=2, dms_per_block=3, channel_unroll=16),
-               dict(threads_per_dm=128, samples_per_thread=16, dms_per_block=2, channel_unroll=8)):
+    for kw in ODD_TILES:
         say("dedisperse odd", case, kw)
         out = amber.dedisperse(dev, info, xd, n_in, n_out, tiles=amber.make_tiles(**kw) if kw else None)
         torch.cuda.synchronize()
