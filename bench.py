@@ -78,6 +78,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-rows", type=int, default=2048, help="DM trials in the CPU oracle sample (0 = skip)")
     ap.add_argument("--tiles", type=str, default="", help="JSON dict of tile overrides")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="also run a plain device-to-device copy of this many bytes 5 times (for scaling "
+                         "hardware byte counters read under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU (the hot path is measured at N=1); "
@@ -159,6 +162,13 @@ def main() -> int:
         },
         "hbm_frac_path": path_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS,
     }
+    if args.copy_calibration > 0:
+        src = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = args.copy_calibration
     if args.cpu_rows > 0:
         print("[bench] cpu oracle baseline (%d rows)" % args.cpu_rows, file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(x_host, n_in, wl, args.cpu_rows)

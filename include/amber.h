@@ -93,7 +93,7 @@ typedef struct {
  *                      paper has one per downsampling factor); 1, 2, 4 or 8
  * The LDS footprint of the dedispersion tile must fit in 160 KiB and its
  * staging must need at most 4 items of 16 samples per work-item (3 when
- * samples_per_thread >= 16). */
+ * samples_per_thread is 16, 2 when it is 32). */
 typedef struct {
     int32_t threads_per_dm;
     int32_t samples_per_thread;
@@ -105,6 +105,12 @@ typedef struct {
 
 /* Fill `tiles` with the library's default configuration. */
 amber_status amber_default_tiles(amber_tiles *tiles);
+
+/* The default configuration adapted to a delay table: channel_unroll, then
+ * dms_per_block, then samples_per_thread are halved until the dedispersion
+ * tile fits.  This is what the device calls use when passed tiles == NULL.
+ * AMBER_E_CONFIG if nothing fits. */
+amber_status amber_auto_tiles(const amber_delay_info *info, amber_tiles *tiles);
 
 /* Check `tiles` against the kernels' space for a problem of this shape;
  * AMBER_OK or AMBER_E_CONFIG (with the reason in amber_last_error). */
@@ -137,7 +143,7 @@ amber_status amber_delay_table(const amber_geometry *g, int32_t *delays, amber_d
  *            multiple of 4; n_in >= n_out + info->max_delay.
  * d_dd:      device int32 [n_dm][dd_stride]; dd_stride >= n_out.  Columns
  *            >= n_out are not written.
- * tiles:     NULL = library default.
+ * tiles:     NULL = amber_auto_tiles(info).
  * Reads stay inside the n_chan * in_stride input bytes and the LDS tile even
  * if the table does not match info; results are then meaningless but the call
  * cannot fault. */

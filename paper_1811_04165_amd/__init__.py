@@ -23,7 +23,7 @@ import numpy as np
 from ._lib import (AMBER_MAX_WIDTHS, AmberError, DelayInfo, Geometry, Tiles, check, load)
 
 __all__ = ["AmberError", "DelayInfo", "Tiles", "default_tiles", "make_tiles", "delay_table", "dedisperse",
-           "integrate", "snr", "integrate_snr", "validate_tiles", "version", "Search"]
+           "integrate", "snr", "integrate_snr", "validate_tiles", "auto_tiles", "version", "Search"]
 
 load()  # fail loudly at import if the native library is missing
 
@@ -51,6 +51,13 @@ def make_tiles(threads_per_dm=None, samples_per_thread=None, dms_per_block=None,
         steps = [boxcar_step] * AMBER_MAX_WIDTHS if np.isscalar(boxcar_step) else list(boxcar_step)
         for k in range(AMBER_MAX_WIDTHS):
             t.boxcar_step[k] = int(steps[k] if k < len(steps) else steps[-1])
+    return t
+
+
+def auto_tiles(info: DelayInfo) -> Tiles:
+    """The default tiles adapted to this delay table (what tiles=None uses)."""
+    t = Tiles()
+    check(load().amber_auto_tiles(ctypes.byref(info), ctypes.byref(t)))
     return t
 
 

@@ -54,6 +54,26 @@ const amber_tiles &default_tiles()
     return t;
 }
 
+// The default configuration, shrunk (channel_unroll first, then
+// dms_per_block, then the time tile) until its dedispersion tile is valid for
+// this delay table.
+amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out)
+{
+    amber_tiles t = default_tiles();
+    DedispPlan p;
+    for (;;) {
+        if (plan_dedisperse(t, info, &p) == AMBER_OK) {
+            clear_error();
+            *out = t;
+            return AMBER_OK;
+        }
+        if (t.channel_unroll > 1) t.channel_unroll /= 2;
+        else if (t.dms_per_block > 1) { t.dms_per_block /= 2; t.channel_unroll = default_tiles().channel_unroll; }
+        else if (t.samples_per_thread > 4) { t.samples_per_thread /= 2; t.channel_unroll = default_tiles().channel_unroll; }
+        else return fail(AMBER_E_CONFIG, "no dedispersion tile fits this delay table (max_step=%d)", info.max_step);
+    }
+}
+
 amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info, DedispPlan *out)
 {
     DedispPlan p{};
@@ -89,7 +109,7 @@ amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info,
                     "channel_unroll, dms_per_block or the time tile", (long long)lds, (long long)kMaxLdsBytes);
     const int64_t items = p.cu * (win / 16);
     p.maxi = (int)((items + p.threads - 1) / p.threads);
-    const int maxi_cap = p.spt >= 16 ? 3 : 4;  // prefetch registers beside the accumulators
+    const int maxi_cap = p.spt >= 32 ? 2 : (p.spt >= 16 ? 3 : 4);  // prefetch registers beside the accumulators
     if (p.maxi > maxi_cap)
         return fail(AMBER_E_CONFIG, "staging needs %d items per work-item (max %d): reduce channel_unroll or "
                     "enlarge the work-group", p.maxi, maxi_cap);
@@ -142,6 +162,13 @@ amber_status amber_default_tiles(amber_tiles *tiles)
     if (!tiles) return fail(AMBER_E_ARG, "tiles is NULL");
     *tiles = default_tiles();
     return AMBER_OK;
+}
+
+amber_status amber_auto_tiles(const amber_delay_info *info, amber_tiles *tiles)
+{
+    clear_error();
+    if (!tiles || !info) return fail(AMBER_E_ARG, "tiles or info is NULL");
+    return auto_tiles(*info, tiles);
 }
 
 amber_status amber_validate_tiles(const amber_tiles *tiles, const amber_delay_info *info, int32_t n_widths)
@@ -220,8 +247,11 @@ amber_status amber_dedisperse(const int32_t *d_delays, const amber_delay_info *i
     if (dd_stride < n_out) return fail(AMBER_E_SHAPE, "dd_stride=%lld < n_out=%lld", (long long)dd_stride, (long long)n_out);
     if ((int64_t)info->n_chan * 255 >= ((int64_t)1 << 31))
         return fail(AMBER_E_ARG, "n_chan=%d can overflow int32 sums", info->n_chan);
+    amber_tiles chosen;
+    amber_status s = tiles ? AMBER_OK : auto_tiles(*info, &chosen);
+    if (s != AMBER_OK) return s;
     DedispPlan plan;
-    amber_status s = plan_dedisperse(tiles ? *tiles : default_tiles(), *info, &plan);
+    s = plan_dedisperse(tiles ? *tiles : chosen, *info, &plan);
     if (s != AMBER_OK) return s;
     if (n_out == 0) return AMBER_OK;
     return launch_dedisperse(plan, d_delays, info->n_dm, info->n_chan, d_in, in_stride, n_in, d_dd, dd_stride, n_out,

@@ -39,6 +39,7 @@ struct DedispPlan {
 };
 
 amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info, DedispPlan *out);
+amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out);
 
 // Boxcar / S/N geometry.
 struct BoxcarPlan {

@@ -125,10 +125,11 @@ def test_gpu_test_tiles_are_valid():
         g = wl.geom
         _, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
         amber.validate_tiles(amber.default_tiles(), info, len(wl.widths))
+        assert amber.auto_tiles(info).as_dict() == amber.default_tiles().as_dict()
         for kw in t.TILE_SWEEP:
             amber.validate_tiles(amber.make_tiles(**kw), info, len(wl.widths))
     for n_chan, n_dm, n_out, step, pad in t.ODD:
         freqs = t.odd_freqs(n_chan, n_dm)
         _, info = amber.delay_table(freqs, 81.92e-6, n_dm, 1.5, step)
         for kw in t.ODD_TILES:
-            amber.validate_tiles(amber.make_tiles(**kw) if kw else amber.default_tiles(), info, 1)
+            amber.validate_tiles(amber.make_tiles(**kw) if kw else amber.auto_tiles(info), info, 1)

@@ -79,9 +79,9 @@ TILE_SWEEP = [
     dict(threads_per_dm=64, samples_per_thread=16, dms_per_block=16, channel_unroll=16),
     dict(threads_per_dm=192, samples_per_thread=8, dms_per_block=5, channel_unroll=4),
     dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=3, channel_unroll=16),
-    dict(threads_per_dm=64, samples_per_thread=32, dms_per_block=8, channel_unroll=8),
+    dict(threads_per_dm=64, samples_per_thread=32, dms_per_block=16, channel_unroll=4),
     dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=8, channel_unroll=32),
-    dict(threads_per_dm=128, samples_per_thread=32, dms_per_block=4, channel_unroll=4),
+    dict(threads_per_dm=128, samples_per_thread=32, dms_per_block=4, channel_unroll=2),
 ]
 
 
