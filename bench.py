@@ -71,6 +71,78 @@ def cpu_baseline(x, n_in, wl, budget_rows: int):
                 budget_rows, g.n_dm, wl.n_out, list(wl.widths), dt)}
 
 
+def time_configs(search, x, configs, reps: int):
+    """Median GPU time (HIP events) of dedisperse + fused boxcar/S/N for each
+    configuration, timed interleaved (round robin) so drifts hit all alike."""
+    import torch
+    import paper_1811_04165_amd as amber
+    times = [[] for _ in configs]
+    for _ in range(reps):
+        for k, t in enumerate(configs):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            amber.dedisperse(search.delays, search.info, x, search.n_in, search.n_out, t, out=search.dd)
+            amber.integrate_snr(search.dd, search.n_out, search.widths, t, out=(search.snr, search.peak))
+            b.record()
+            b.synchronize()
+            times[k].append(a.elapsed_time(b) / 1e3)
+    return [statistics.median(v) for v in times]
+
+
+def tune_report(seeds: int):
+    """GA (several seeds) vs exhaustive vs random (same budget as each GA run)
+    vs per-kernel brute force, on the 256-channel / 128-DM workload, with the
+    finalists re-timed interleaved."""
+    import torch
+    import paper_1811_04165_amd as amber
+    import workloads
+    wl = workloads.small()
+    g = wl.geom
+    search = amber.Search(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step, wl.n_out, wl.widths)
+    x_host, n_in = workloads.make_input(wl, search.delays_host, search.info.max_delay)
+    x = torch.from_numpy(x_host).cuda()
+    sp = amber.default_space(search.info, wl.widths, wl.n_out)
+    sp.set_gene_values(4, [256])    # the boxcar kernel's thread count is held; its steps are tuned
+    bufs = (search.dd, search.snr, search.peak)
+    out = {"workload": wl.name, "space_size": amber.space_size(sp), "genes": {
+        "threads_per_dm": sp.gene_values(0), "samples_per_thread": sp.gene_values(1),
+        "dms_per_block": sp.gene_values(2), "channel_unroll": sp.gene_values(3), "snr_threads": sp.gene_values(4),
+        "boxcar_step": sp.gene_values(5)}}
+
+    def run(kind, **kw):
+        print("[bench] tune %s %s" % (kind, kw), file=sys.stderr, flush=True)
+        r = amber.tune(sp, search.delays, x, n_in, amber.tune_params(kind, **kw), buffers=bufs)
+        return r
+
+    ga = [run("ga", seed=s) for s in range(1, seeds + 1)]
+    rnd = [run("random", seed=100 + s, max_evals=ga[s - 1].n_evals) for s in range(1, seeds + 1)]
+    pk = run("per_kernel")
+    ex = run("exhaustive", reps=1, warmup=1)
+    finalists = [r.best for r in ga] + [r.best for r in rnd] + [pk.best, ex.best]
+    print("[bench] interleaved re-timing of %d finalists" % len(finalists), file=sys.stderr, flush=True)
+    t = time_configs(search, x, finalists, reps=100)
+    n = seeds
+    t_ga, t_rnd, t_pk, t_ex = t[:n], t[n:2 * n], t[2 * n], t[2 * n + 1]
+    nw = len(wl.widths)
+    out.update({
+        "retimed_s": {"ga": t_ga, "random": t_rnd, "per_kernel": t_pk, "exhaustive": t_ex},
+        "ga_median_over_exhaustive": statistics.median(t_ga) / t_ex,
+        "ga_worst_over_exhaustive": max(t_ga) / t_ex,
+        "random_median_over_exhaustive": statistics.median(t_rnd) / t_ex,
+        "per_kernel_over_exhaustive": t_pk / t_ex,
+        "cost": {"ga_evals_median": statistics.median([r.n_evals for r in ga]),
+                 "ga_wall_s_median": statistics.median([r.wall_s for r in ga]),
+                 "random_evals_median": statistics.median([r.n_evals for r in rnd]),
+                 "per_kernel_evals": pk.n_evals, "per_kernel_wall_s": pk.wall_s,
+                 "exhaustive_evals": ex.n_evals, "exhaustive_wall_s": ex.wall_s},
+        "ga_cost_fraction_of_exhaustive": statistics.median([r.wall_s for r in ga]) / ex.wall_s,
+        "best": {"ga_seed1": ga[0].as_dict(nw)["best"], "exhaustive": ex.as_dict(nw)["best"],
+                 "per_kernel": pk.as_dict(nw)["best"]},
+        "default_tiles_s": time_configs(search, x, [amber.auto_tiles(search.info)], reps=100)[0],
+    })
+    return {"metric": "GA tune time", "unit": "s", "value": out["cost"]["ga_wall_s_median"], "tune": out}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +150,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-rows", type=int, default=2048, help="DM trials in the CPU oracle sample (0 = skip)")
     ap.add_argument("--tiles", type=str, default="", help="JSON dict of tile overrides")
+    ap.add_argument("--tune", action="store_true",
+                    help="instead of the throughput step: compare the GA tile search with exhaustive, random and "
+                         "per-kernel brute-force search on the 256-channel workload")
+    ap.add_argument("--tune-seeds", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run a plain device-to-device copy of this many bytes 5 times (for scaling "
                          "hardware byte counters read under a profiler)")
@@ -95,6 +171,9 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 3
+    if args.tune:
+        print(json.dumps(tune_report(args.tune_seeds)))
+        return 0
     wl = workloads.beam()
     g = wl.geom
     tiles = amber.make_tiles(**json.loads(args.tiles)) if args.tiles else amber.default_tiles()

@@ -189,6 +189,91 @@ amber_status amber_integrate_snr(const int32_t *d_dd, int32_t n_dm, int64_t dd_s
                                  float *d_snr, int32_t *d_peak_t,
                                  const amber_tiles *tiles, void *stream);
 
+/* ---- tile search (Section 3: genetic algorithm; Section 2: brute force) ---- */
+
+/* Genes: 0 threads_per_dm, 1 samples_per_thread, 2 dms_per_block,
+ * 3 channel_unroll (the dedispersion kernel's genes), 4 snr_threads,
+ * 5 + k boxcar_step[k] for k < n_widths (the boxcar / S/N kernel's genes). */
+#define AMBER_GENES_K1 4
+#define AMBER_MAX_GENES (5 + AMBER_MAX_WIDTHS)
+#define AMBER_MAX_GENE_VALUES 8
+
+/* The search space: allowed values of every gene (arrays built from the
+ * boundary conditions, as the paper's GA does before initialisation) and the
+ * problem a configuration must be valid for. */
+typedef struct {
+    int32_t n_genes;                                   /* 5 + n_widths */
+    int32_t n_values[AMBER_MAX_GENES];
+    int32_t values[AMBER_MAX_GENES][AMBER_MAX_GENE_VALUES];
+    amber_delay_info info;                             /* validity of dedispersion tiles */
+    int32_t n_widths;
+    int32_t widths[AMBER_MAX_WIDTHS];                  /* validity of boxcar tiles */
+    int64_t n_out;
+} amber_tune_space;
+
+typedef enum {
+    AMBER_SEARCH_GA = 0,          /* genetic algorithm over all genes jointly */
+    AMBER_SEARCH_EXHAUSTIVE = 1,  /* every valid joint configuration */
+    AMBER_SEARCH_RANDOM = 2,      /* independent random valid configurations */
+    AMBER_SEARCH_PER_KERNEL = 3   /* brute force of each kernel's genes separately */
+} amber_search_kind;
+
+typedef struct {
+    int32_t search;       /* amber_search_kind */
+    int32_t pop;          /* GA population N_pop (>= 2) */
+    int32_t generations;  /* GA generations */
+    int32_t crossover;    /* 0 uniform (coin toss per gene), 1 one-point */
+    double p_cross;       /* crossover probability per kernel */
+    double p_mut;         /* mutation probability per kernel */
+    double pool_frac;     /* tournament pool as a fraction of N_pop */
+    uint64_t seed;
+    int32_t warmup;       /* device evaluator: untimed runs per configuration */
+    int32_t reps;         /* device evaluator: timed runs (median) */
+    double eval_timeout_s;/* slower evaluations count as failures (fitness +inf) */
+    int64_t max_evals;    /* random search budget; cap for exhaustive (0 = none) */
+} amber_tune_params;
+
+typedef struct {
+    amber_tiles best;
+    double best_time_s;   /* fitness of `best` */
+    int64_t n_evals;      /* fitness evaluations performed (cache hits excluded) */
+    int64_t n_failed;     /* evaluations that failed or timed out */
+    int64_t space_size;   /* valid joint configurations in the space */
+    double wall_s;        /* wall time of the search */
+} amber_tune_result;
+
+/* Fitness callback: measured time in seconds of the configuration; a non-zero
+ * return marks a failed evaluation (fitness +inf, never selected). */
+typedef int32_t (*amber_fitness_fn)(const amber_tiles *tiles, void *user, double *seconds);
+
+/* The default search space for a problem (gene arrays of powers of two within
+ * the kernels' bounds). */
+amber_status amber_default_space(const amber_delay_info *info, const int32_t *widths, int32_t n_widths,
+                                 int64_t n_out, amber_tune_space *space);
+
+/* Number of valid joint configurations of a space. */
+amber_status amber_space_size(const amber_tune_space *space, int64_t *count);
+
+/* Runs the search of p->search over `space` with a caller-supplied fitness
+ * (host only; no GPU needed).  log_jsonl_path, if not NULL, receives one JSON
+ * line per GA generation (or per 1000 evaluations for the other searches). */
+amber_status amber_search_tiles(const amber_tune_space *space, const amber_tune_params *p, amber_fitness_fn fn,
+                                void *user, amber_tune_result *result, const char *log_jsonl_path);
+
+/* amber_search_tiles with the device evaluator: fitness = GPU time (HIP
+ * events, median of p->reps after p->warmup runs) of amber_dedisperse followed
+ * by amber_integrate_snr on the caller's buffers, i.e. the whole hot path.
+ * Synchronises `stream`.  Buffers as for those two calls; the widths and
+ * geometry are the space's. */
+amber_status amber_tune(const amber_tune_space *space, const int32_t *d_delays, const uint8_t *d_in,
+                        int64_t in_stride, int64_t n_in, int32_t *d_dd, int64_t dd_stride, float *d_snr,
+                        int32_t *d_peak_t, const amber_tune_params *p, amber_tune_result *result,
+                        const char *log_jsonl_path, void *stream);
+
+/* Default GA parameters (population 32, 40 generations, uniform crossover,
+ * p_cross 0.8, p_mut 0.1, pool 20 %, 1 warm-up and 3 timed runs). */
+amber_status amber_default_tune_params(amber_tune_params *p);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,9 +20,11 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-from ._lib import (AMBER_MAX_WIDTHS, AmberError, DelayInfo, Geometry, Tiles, check, load)
+from ._lib import (AMBER_MAX_WIDTHS, FITNESS_FN, SEARCH_KINDS, AmberError, DelayInfo, Geometry, Tiles, TuneParams,
+                   TuneResult, TuneSpace, check, load)
 
-__all__ = ["AmberError", "DelayInfo", "Tiles", "default_tiles", "make_tiles", "delay_table", "dedisperse",
+__all__ = ["AmberError", "DelayInfo", "Tiles", "TuneSpace", "TuneParams", "TuneResult", "default_space",
+           "space_size", "tune_params", "search_tiles", "tune", "default_tiles", "make_tiles", "delay_table", "dedisperse",
            "integrate", "snr", "integrate_snr", "validate_tiles", "auto_tiles", "version", "Search"]
 
 load()  # fail loudly at import if the native library is missing
@@ -200,3 +202,74 @@ class Search:
         dedisperse(self.delays, self.info, x, self.n_in, self.n_out, self.tiles, out=self.dd, stream=stream)
         integrate_snr(self.dd, self.n_out, self.widths, self.tiles, stream=stream, out=(self.snr, self.peak))
         return self.dd, self.snr, self.peak
+
+
+# --- tile search --------------------------------------------------------------------
+
+def default_space(info: DelayInfo, widths: Sequence[int], n_out: int) -> TuneSpace:
+    """The library's gene arrays for a problem (powers of two within the kernels' bounds)."""
+    w, wp = _widths_arr(widths)
+    sp = TuneSpace()
+    check(load().amber_default_space(ctypes.byref(info), wp, len(w), int(n_out), ctypes.byref(sp)))
+    return sp
+
+
+def space_size(space: TuneSpace) -> int:
+    n = ctypes.c_int64(0)
+    check(load().amber_space_size(ctypes.byref(space), ctypes.byref(n)))
+    return int(n.value)
+
+
+def tune_params(search: str = "ga", **kw) -> TuneParams:
+    """Default GA parameters with overrides; search is ga | exhaustive | random | per_kernel."""
+    p = TuneParams()
+    check(load().amber_default_tune_params(ctypes.byref(p)))
+    p.search = SEARCH_KINDS[search]
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError("TuneParams has no field %r" % k)
+        setattr(p, k, v)
+    return p
+
+
+def search_tiles(space: TuneSpace, params: TuneParams, fitness, log_path: Optional[str] = None) -> TuneResult:
+    """Host-only search with a Python fitness(tiles) -> seconds (raise or return None for a failure)."""
+    errors = []
+
+    def cb(tiles_p, user, out_p):
+        try:
+            v = fitness(tiles_p.contents)
+            if v is None:
+                return 1
+            out_p[0] = float(v)
+            return 0
+        except Exception as e:  # surfaced after the call
+            errors.append(e)
+            return 1
+
+    cfn = FITNESS_FN(cb)
+    res = TuneResult()
+    rc = load().amber_search_tiles(ctypes.byref(space), ctypes.byref(params), cfn, None, ctypes.byref(res),
+                                   log_path.encode() if log_path else None)
+    check(rc)
+    return res
+
+
+def tune(space: TuneSpace, delays, x, n_in: int, params: TuneParams, log_path: Optional[str] = None, stream=None,
+         buffers=None) -> TuneResult:
+    """Device search: fitness = GPU time of dedisperse + fused boxcar/S/N on x."""
+    torch = _torch()
+    _check_dev(delays, torch.int32, "delays", 2)
+    _check_dev(x, torch.uint8, "x", 2)
+    info, n_out, n_w = space.info, space.n_out, space.n_widths
+    if buffers is None:
+        dd = torch.empty((info.n_dm, n_out), dtype=torch.int32, device=x.device)
+        s = torch.empty((n_w, info.n_dm), dtype=torch.float32, device=x.device)
+        p = torch.empty((n_w, info.n_dm), dtype=torch.int32, device=x.device)
+    else:
+        dd, s, p = buffers
+    res = TuneResult()
+    check(load().amber_tune(ctypes.byref(space), delays.data_ptr(), x.data_ptr(), x.stride(0), int(n_in),
+                            dd.data_ptr(), dd.stride(0), s.data_ptr(), p.data_ptr(), ctypes.byref(params),
+                            ctypes.byref(res), log_path.encode() if log_path else None, _stream_handle(stream)))
+    return res

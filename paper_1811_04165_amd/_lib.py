@@ -43,6 +43,47 @@ class Tiles(ctypes.Structure):
         return "Tiles(%s)" % ", ".join("%s=%s" % kv for kv in d.items())
 
 
+AMBER_MAX_GENES = 5 + AMBER_MAX_WIDTHS
+AMBER_MAX_GENE_VALUES = 8
+SEARCH_KINDS = {"ga": 0, "exhaustive": 1, "random": 2, "per_kernel": 3}
+
+
+class TuneSpace(ctypes.Structure):
+    _fields_ = [("n_genes", ctypes.c_int32), ("n_values", ctypes.c_int32 * AMBER_MAX_GENES),
+                ("values", (ctypes.c_int32 * AMBER_MAX_GENE_VALUES) * AMBER_MAX_GENES), ("info", DelayInfo),
+                ("n_widths", ctypes.c_int32), ("widths", ctypes.c_int32 * AMBER_MAX_WIDTHS), ("n_out", ctypes.c_int64)]
+
+    def gene_values(self, i):
+        return [self.values[i][k] for k in range(self.n_values[i])]
+
+    def set_gene_values(self, i, vals):
+        if not 1 <= len(vals) <= AMBER_MAX_GENE_VALUES:
+            raise ValueError("a gene takes 1..%d values" % AMBER_MAX_GENE_VALUES)
+        self.n_values[i] = len(vals)
+        for k, v in enumerate(vals):
+            self.values[i][k] = int(v)
+
+
+class TuneParams(ctypes.Structure):
+    _fields_ = [("search", ctypes.c_int32), ("pop", ctypes.c_int32), ("generations", ctypes.c_int32),
+                ("crossover", ctypes.c_int32), ("p_cross", ctypes.c_double), ("p_mut", ctypes.c_double),
+                ("pool_frac", ctypes.c_double), ("seed", ctypes.c_uint64), ("warmup", ctypes.c_int32),
+                ("reps", ctypes.c_int32), ("eval_timeout_s", ctypes.c_double), ("max_evals", ctypes.c_int64)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("best", Tiles), ("best_time_s", ctypes.c_double), ("n_evals", ctypes.c_int64),
+                ("n_failed", ctypes.c_int64), ("space_size", ctypes.c_int64), ("wall_s", ctypes.c_double)]
+
+    def as_dict(self, n_widths=AMBER_MAX_WIDTHS):
+        best = self.best.as_dict()
+        best["boxcar_step"] = best["boxcar_step"][:n_widths]
+        return {"best": best, "best_time_s": self.best_time_s, "n_evals": self.n_evals, "n_failed": self.n_failed,
+                "space_size": self.space_size, "wall_s": self.wall_s}
+
+
+FITNESS_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.POINTER(Tiles), ctypes.c_void_p, ctypes.POINTER(ctypes.c_double))
+
 # (name, restype, argtypes) of every exported symbol the header declares.
 SIGNATURES = [
     ("amber_last_error", ctypes.c_char_p, []),
@@ -63,6 +104,16 @@ SIGNATURES = [
     ("amber_integrate_snr", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                            c_i32p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.POINTER(Tiles), ctypes.c_void_p]),
+    ("amber_default_space", ctypes.c_int, [ctypes.POINTER(DelayInfo), c_i32p, ctypes.c_int32, ctypes.c_int64,
+                                           ctypes.POINTER(TuneSpace)]),
+    ("amber_space_size", ctypes.c_int, [ctypes.POINTER(TuneSpace), ctypes.POINTER(ctypes.c_int64)]),
+    ("amber_default_tune_params", ctypes.c_int, [ctypes.POINTER(TuneParams)]),
+    ("amber_search_tiles", ctypes.c_int, [ctypes.POINTER(TuneSpace), ctypes.POINTER(TuneParams), FITNESS_FN,
+                                          ctypes.c_void_p, ctypes.POINTER(TuneResult), ctypes.c_char_p]),
+    ("amber_tune", ctypes.c_int, [ctypes.POINTER(TuneSpace), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.POINTER(TuneParams), ctypes.POINTER(TuneResult), ctypes.c_char_p,
+                                  ctypes.c_void_p]),
 ]
 
 _lib = None

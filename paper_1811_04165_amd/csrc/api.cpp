@@ -141,6 +141,11 @@ amber_status plan_boxcar(const amber_tiles &t, const int32_t *widths, int32_t n_
     p.threads = t.snr_threads;
     p.chunk = p.threads * 16;
     p.maxw = maxw;
+    // chunks overlap by the largest width rounded up to 16; they must be at
+    // least twice that long
+    if (p.chunk < 2 * ((maxw + 15) / 16 * 16))
+        return fail(AMBER_E_CONFIG, "snr_threads=%d gives chunks of %d samples, too short for width %d", p.threads,
+                    p.chunk, maxw);
     p.lds_bytes = (int64_t)(p.chunk + maxw + 16) * 4;
     *out = p;
     return AMBER_OK;

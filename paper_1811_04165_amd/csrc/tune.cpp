@@ -1,0 +1,599 @@
+// Tile search: the genetic algorithm of Section 3 (initialisation from gene
+// arrays built from the boundary conditions, tournament selection, pairing
+// without identical partners, per-kernel crossover and mutation, replacement
+// by the best half of parents and of offspring), plus exhaustive, random and
+// per-kernel brute-force searches over the same space, and the device
+// evaluator whose fitness is the measured time of the whole hot path.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+namespace amber {
+namespace {
+
+constexpr double kInf = std::numeric_limits<double>::infinity();
+constexpr int kGroupSplit = AMBER_GENES_K1 + 0;  // genes [0, 4): dedispersion; [4, n): boxcar / S/N
+
+// xoshiro256** (Blackman and Vigna), seeded through splitmix64.
+class Rng {
+public:
+    explicit Rng(uint64_t seed)
+    {
+        uint64_t x = seed;
+        for (auto &w : s_) {
+            x += 0x9e3779b97f4a7c15ull;
+            uint64_t z = x;
+            z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+            z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+            w = z ^ (z >> 31);
+        }
+    }
+    uint64_t next()
+    {
+        const uint64_t r = rotl(s_[1] * 5, 7) * 9;
+        const uint64_t t = s_[1] << 17;
+        s_[2] ^= s_[0];
+        s_[3] ^= s_[1];
+        s_[1] ^= s_[2];
+        s_[0] ^= s_[3];
+        s_[2] ^= t;
+        s_[3] = rotl(s_[3], 45);
+        return r;
+    }
+    double uniform() { return (double)(next() >> 11) * 0x1.0p-53; }  // [0, 1)
+    int below(int n) { return (int)(uniform() * n); }                 // [0, n)
+
+private:
+    static uint64_t rotl(uint64_t x, int k) { return (x << k) | (x >> (64 - k)); }
+    uint64_t s_[4];
+};
+
+using Genome = std::vector<int>;  // index into each gene's value array
+
+amber_tiles to_tiles(const amber_tune_space &sp, const Genome &g)
+{
+    amber_tiles t = default_tiles();
+    t.threads_per_dm = sp.values[0][g[0]];
+    t.samples_per_thread = sp.values[1][g[1]];
+    t.dms_per_block = sp.values[2][g[2]];
+    t.channel_unroll = sp.values[3][g[3]];
+    t.snr_threads = sp.values[4][g[4]];
+    for (int k = 0; k < sp.n_widths; ++k) t.boxcar_step[k] = sp.values[5 + k][g[5 + k]];
+    return t;
+}
+
+bool valid_tiles(const amber_tune_space &sp, const amber_tiles &t)
+{
+    DedispPlan dp;
+    BoxcarPlan bp;
+    const bool ok = plan_dedisperse(t, sp.info, &dp) == AMBER_OK &&
+                    plan_boxcar(t, sp.widths, sp.n_widths, sp.n_out, &bp) == AMBER_OK;
+    clear_error();
+    return ok;
+}
+
+std::string key_of(const Genome &g)
+{
+    std::string k;
+    for (int v : g) k.push_back((char)('a' + v));
+    return k;
+}
+
+std::string tiles_json(const amber_tiles &t, int n_widths)
+{
+    char buf[512];
+    int n = snprintf(buf, sizeof buf,
+                     "{\"threads_per_dm\":%d,\"samples_per_thread\":%d,\"dms_per_block\":%d,\"channel_unroll\":%d,"
+                     "\"snr_threads\":%d,\"boxcar_step\":[",
+                     t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll, t.snr_threads);
+    for (int k = 0; k < n_widths; ++k) n += snprintf(buf + n, sizeof buf - n, "%s%d", k ? "," : "", t.boxcar_step[k]);
+    snprintf(buf + n, sizeof buf - n, "]}");
+    return buf;
+}
+
+class Searcher {
+public:
+    Searcher(const amber_tune_space &sp, const amber_tune_params &p, amber_fitness_fn fn, void *user, FILE *log)
+        : sp_(sp), p_(p), fn_(fn), user_(user), log_(log), rng_(p.seed), t0_(clock_now())
+    {
+    }
+
+    amber_status run(amber_tune_result *res)
+    {
+        amber_status s;
+        switch (p_.search) {
+        case AMBER_SEARCH_GA: s = ga(); break;
+        case AMBER_SEARCH_EXHAUSTIVE: s = exhaustive(); break;
+        case AMBER_SEARCH_RANDOM: s = random_search(); break;
+        case AMBER_SEARCH_PER_KERNEL: s = per_kernel(); break;
+        default: return fail(AMBER_E_ARG, "unknown search kind %d", p_.search);
+        }
+        if (s != AMBER_OK) return s;
+        if (best_.empty() || !std::isfinite(best_fit_))
+            return fail(AMBER_E_CONFIG, "no configuration of the space could be evaluated");
+        res->best = to_tiles(sp_, best_);
+        res->best_time_s = best_fit_;
+        res->n_evals = n_evals_;
+        res->n_failed = n_failed_;
+        res->wall_s = elapsed();
+        return AMBER_OK;
+    }
+
+private:
+    static double clock_now()
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    }
+    double elapsed() const { return clock_now() - t0_; }
+    int n_genes() const { return sp_.n_genes; }
+    bool valid(const Genome &g) const { return valid_tiles(sp_, to_tiles(sp_, g)); }
+
+    double evaluate(const Genome &g)
+    {
+        const std::string k = key_of(g);
+        auto it = cache_.find(k);
+        if (it != cache_.end()) return it->second;
+        const amber_tiles t = to_tiles(sp_, g);
+        double sec = kInf;
+        const int32_t rc = fn_(&t, user_, &sec);
+        ++n_evals_;
+        if (rc != 0 || !std::isfinite(sec) || sec < 0.0 || (p_.eval_timeout_s > 0.0 && sec > p_.eval_timeout_s)) {
+            sec = kInf;
+            ++n_failed_;
+        }
+        cache_.emplace(k, sec);
+        if (sec < best_fit_) {
+            best_fit_ = sec;
+            best_ = g;
+        }
+        if (p_.search != AMBER_SEARCH_GA && log_ && n_evals_ % 1000 == 0) log_line(-1);
+        return sec;
+    }
+
+    void log_line(int generation)
+    {
+        if (!log_) return;
+        const std::string best = best_.empty() ? "null" : tiles_json(to_tiles(sp_, best_), sp_.n_widths);
+        fprintf(log_, "{\"generation\":%d,\"evals\":%lld,\"failed\":%lld,\"best_time_s\":%.9g,\"wall_s\":%.6f,\"best\":%s}\n",
+                generation, (long long)n_evals_, (long long)n_failed_, std::isfinite(best_fit_) ? best_fit_ : -1.0,
+                elapsed(), best.c_str());
+        fflush(log_);
+    }
+
+    bool random_genome(Genome &g)
+    {
+        g.assign(n_genes(), 0);
+        for (int attempt = 0; attempt < 100000; ++attempt) {
+            for (int i = 0; i < n_genes(); ++i) g[i] = rng_.below(sp_.n_values[i]);
+            if (valid(g)) return true;
+        }
+        return false;
+    }
+
+    // ---- genetic algorithm ------------------------------------------------
+    int tournament(const std::vector<double> &fit)
+    {
+        const int n = (int)fit.size();
+        int pool = (int)std::lround(p_.pool_frac * n);
+        pool = std::max(2, std::min(pool, n));
+        std::vector<int> idx(n);
+        for (int i = 0; i < n; ++i) idx[i] = i;
+        int win = -1;
+        for (int k = 0; k < pool; ++k) {  // pool drawn without replacement
+            const int j = k + rng_.below(n - k);
+            std::swap(idx[k], idx[j]);
+            const int c = idx[k];
+            if (win < 0 || fit[c] < fit[win] || (fit[c] == fit[win] && c < win)) win = c;
+        }
+        return win;
+    }
+
+    void crossover_group(Genome &a, Genome &b, int lo, int hi)
+    {
+        if (p_.crossover == 1) {  // one-point: genes after a random cut are swapped
+            if (hi - lo < 2) return;
+            const int cut = lo + 1 + rng_.below(hi - lo - 1);
+            Genome a2 = a, b2 = b;
+            for (int i = cut; i < hi; ++i) std::swap(a2[i], b2[i]);
+            if (valid(a2) && valid(b2)) {
+                a = a2;
+                b = b2;
+            }
+        } else {  // uniform: each gene swapped on a coin toss, kept only if both stay valid
+            for (int i = lo; i < hi; ++i) {
+                if (rng_.uniform() <= 0.5) continue;
+                std::swap(a[i], b[i]);
+                if (!valid(a) || !valid(b)) std::swap(a[i], b[i]);
+            }
+        }
+    }
+
+    // Changes gene i to another value of its array that keeps the genome valid,
+    // if there is one.
+    void mutate_gene(Genome &g, int i)
+    {
+        const int n = sp_.n_values[i];
+        if (n < 2) return;
+        const int old = g[i];
+        std::vector<int> cand;
+        for (int v = 0; v < n; ++v)
+            if (v != old) cand.push_back(v);
+        for (int left = (int)cand.size(); left > 0; --left) {
+            const int j = rng_.below(left);
+            g[i] = cand[j];
+            if (valid(g)) return;
+            std::swap(cand[j], cand[left - 1]);
+        }
+        g[i] = old;
+    }
+
+    void mutate(Genome &g)
+    {
+        // dedispersion kernel: one of its genes
+        if (rng_.uniform() < p_.p_mut) mutate_gene(g, rng_.below(kGroupSplit));
+        // boxcar / S/N kernel: one gene per width, chosen between the width's
+        // own step and the kernel's thread count
+        if (rng_.uniform() < p_.p_mut) {
+            for (int k = 0; k < sp_.n_widths; ++k) mutate_gene(g, rng_.uniform() < 0.5 ? 4 : 5 + k);
+        }
+    }
+
+    amber_status ga()
+    {
+        const int n = p_.pop;
+        if (n < 2 || p_.generations < 0) return fail(AMBER_E_ARG, "GA needs pop >= 2 and generations >= 0");
+        std::vector<Genome> pop(n);
+        std::vector<double> fit(n);
+        for (int i = 0; i < n; ++i) {
+            if (!random_genome(pop[i])) return fail(AMBER_E_CONFIG, "no valid configuration found to initialise");
+            fit[i] = evaluate(pop[i]);
+        }
+        log_line(0);
+        for (int gen = 1; gen <= p_.generations; ++gen) {
+            // selection: N_pop tournaments
+            std::vector<int> sel(n);
+            for (int i = 0; i < n; ++i) sel[i] = tournament(fit);
+            // pairing, avoiding identical partners where possible
+            for (int i = 0; i + 1 < n; i += 2) {
+                if (pop[sel[i]] != pop[sel[i + 1]]) continue;
+                for (int j = i + 2; j < n; ++j)
+                    if (pop[sel[j]] != pop[sel[i]]) {
+                        std::swap(sel[i + 1], sel[j]);
+                        break;
+                    }
+            }
+            std::vector<Genome> off(n);
+            for (int i = 0; i < n; ++i) off[i] = pop[sel[i]];
+            for (int i = 0; i + 1 < n; i += 2) {
+                if (rng_.uniform() < p_.p_cross) crossover_group(off[i], off[i + 1], 0, kGroupSplit);
+                if (rng_.uniform() < p_.p_cross) crossover_group(off[i], off[i + 1], kGroupSplit, n_genes());
+            }
+            std::vector<double> off_fit(n);
+            for (int i = 0; i < n; ++i) {
+                mutate(off[i]);
+                off_fit[i] = evaluate(off[i]);
+            }
+            // replacement: best half of the parents and best half of the offspring
+            std::vector<int> pi(n), oi(n);
+            for (int i = 0; i < n; ++i) pi[i] = oi[i] = i;
+            std::stable_sort(pi.begin(), pi.end(), [&](int a, int b) { return fit[a] < fit[b]; });
+            std::stable_sort(oi.begin(), oi.end(), [&](int a, int b) { return off_fit[a] < off_fit[b]; });
+            std::vector<Genome> next;
+            std::vector<double> next_fit;
+            const int keep_parents = (n + 1) / 2;
+            for (int i = 0; i < keep_parents; ++i) {
+                next.push_back(pop[pi[i]]);
+                next_fit.push_back(fit[pi[i]]);
+            }
+            for (int i = 0; i < n - keep_parents; ++i) {
+                next.push_back(off[oi[i]]);
+                next_fit.push_back(off_fit[oi[i]]);
+            }
+            pop.swap(next);
+            fit.swap(next_fit);
+            log_line(gen);
+        }
+        return AMBER_OK;
+    }
+
+    // ---- enumeration-based searches ------------------------------------------
+    // Calls f on every valid genome whose genes outside [lo, hi) equal `base`.
+    template <typename F>
+    void enumerate(const Genome &base, int lo, int hi, F f)
+    {
+        Genome g = base;
+        for (int i = lo; i < hi; ++i) g[i] = 0;
+        for (;;) {
+            if (valid(g)) f(g);
+            int i = lo;
+            while (i < hi && ++g[i] == sp_.n_values[i]) g[i++] = 0;
+            if (i == hi) return;
+        }
+    }
+
+    amber_status exhaustive()
+    {
+        int64_t count = 0;
+        enumerate(Genome(n_genes(), 0), 0, n_genes(), [&](const Genome &) { ++count; });
+        if (p_.max_evals > 0 && count > p_.max_evals)
+            return fail(AMBER_E_ARG, "exhaustive search of %lld configurations exceeds max_evals=%lld",
+                        (long long)count, (long long)p_.max_evals);
+        enumerate(Genome(n_genes(), 0), 0, n_genes(), [&](const Genome &g) { evaluate(g); });
+        log_line(-1);
+        return AMBER_OK;
+    }
+
+    amber_status random_search()
+    {
+        if (p_.max_evals <= 0) return fail(AMBER_E_ARG, "random search needs max_evals > 0");
+        Genome g;
+        for (int64_t draws = 0; n_evals_ < p_.max_evals && draws < 100 * p_.max_evals; ++draws) {
+            if (!random_genome(g)) return fail(AMBER_E_CONFIG, "no valid configuration found");
+            evaluate(g);
+        }
+        log_line(-1);
+        return AMBER_OK;
+    }
+
+    // Paper-style brute force: each kernel's genes exhaustively with the other
+    // kernel's genes held (first the dedispersion kernel with the library's
+    // default boxcar genes, then the boxcar / S/N kernel with the best
+    // dedispersion genes found).
+    amber_status per_kernel()
+    {
+        Genome base(n_genes(), 0);
+        const amber_tiles d = default_tiles();
+        const int defaults[AMBER_MAX_GENES] = {d.threads_per_dm, d.samples_per_thread, d.dms_per_block,
+                                               d.channel_unroll, d.snr_threads};
+        for (int i = 0; i < n_genes(); ++i) {
+            const int want = i < 5 ? defaults[i] : d.boxcar_step[i - 5];
+            for (int v = 0; v < sp_.n_values[i]; ++v)
+                if (sp_.values[i][v] == want) base[i] = v;
+        }
+        Genome best1;
+        double fit1 = kInf;
+        enumerate(base, 0, kGroupSplit, [&](const Genome &g) {
+            const double f = evaluate(g);
+            if (f < fit1) {
+                fit1 = f;
+                best1 = g;
+            }
+        });
+        if (best1.empty()) return fail(AMBER_E_CONFIG, "no valid dedispersion configuration with the default boxcar genes");
+        enumerate(best1, kGroupSplit, n_genes(), [&](const Genome &g) { evaluate(g); });
+        log_line(-1);
+        return AMBER_OK;
+    }
+
+    const amber_tune_space &sp_;
+    const amber_tune_params &p_;
+    amber_fitness_fn fn_;
+    void *user_;
+    FILE *log_;
+    Rng rng_;
+    double t0_;
+    std::unordered_map<std::string, double> cache_;
+    Genome best_;
+    double best_fit_ = kInf;
+    int64_t n_evals_ = 0, n_failed_ = 0;
+};
+
+amber_status check_space(const amber_tune_space *sp)
+{
+    if (!sp) return fail(AMBER_E_ARG, "space is NULL");
+    if (sp->n_widths < 1 || sp->n_widths > AMBER_MAX_WIDTHS || sp->n_genes != 5 + sp->n_widths)
+        return fail(AMBER_E_ARG, "space must have n_genes = 5 + n_widths with 1 <= n_widths <= %d", AMBER_MAX_WIDTHS);
+    for (int i = 0; i < sp->n_genes; ++i)
+        if (sp->n_values[i] < 1 || sp->n_values[i] > AMBER_MAX_GENE_VALUES)
+            return fail(AMBER_E_ARG, "gene %d has %d values (1..%d allowed)", i, sp->n_values[i], AMBER_MAX_GENE_VALUES);
+    return AMBER_OK;
+}
+
+// ---- device evaluator ---------------------------------------------------------
+struct DeviceEval {
+    const amber_tune_space *sp;
+    const int32_t *d_delays;
+    const uint8_t *d_in;
+    int64_t in_stride, n_in;
+    int32_t *d_dd;
+    int64_t dd_stride;
+    float *d_snr;
+    int32_t *d_peak;
+    int warmup, reps;
+    hipStream_t stream;
+    std::vector<hipEvent_t> ev;
+    amber_status error = AMBER_OK;
+};
+
+amber_status run_path(DeviceEval &e, const amber_tiles &t)
+{
+    amber_status s = amber_dedisperse(e.d_delays, &e.sp->info, e.d_in, e.in_stride, e.n_in, e.d_dd, e.dd_stride,
+                                      e.sp->n_out, &t, e.stream);
+    if (s != AMBER_OK) return s;
+    return amber_integrate_snr(e.d_dd, e.sp->info.n_dm, e.dd_stride, e.sp->n_out, e.sp->widths, e.sp->n_widths,
+                               e.d_snr, e.d_peak, &t, e.stream);
+}
+
+int32_t device_fitness(const amber_tiles *t, void *user, double *seconds)
+{
+    DeviceEval &e = *static_cast<DeviceEval *>(user);
+    for (int w = 0; w < e.warmup; ++w)
+        if (run_path(e, *t) != AMBER_OK) return 1;
+    std::vector<float> ms(e.reps);
+    for (int r = 0; r < e.reps; ++r) {
+        if (hipEventRecord(e.ev[2 * r], e.stream) != hipSuccess) return 1;
+        if (run_path(e, *t) != AMBER_OK) return 1;
+        if (hipEventRecord(e.ev[2 * r + 1], e.stream) != hipSuccess) return 1;
+    }
+    if (hipEventSynchronize(e.ev[2 * e.reps - 1]) != hipSuccess) {
+        e.error = AMBER_E_DEVICE;
+        return 1;
+    }
+    for (int r = 0; r < e.reps; ++r)
+        if (hipEventElapsedTime(&ms[r], e.ev[2 * r], e.ev[2 * r + 1]) != hipSuccess) return 1;
+    std::sort(ms.begin(), ms.end());
+    *seconds = 1e-3 * (double)ms[e.reps / 2];
+    return 0;
+}
+
+}  // namespace
+}  // namespace amber
+
+using namespace amber;
+
+extern "C" {
+
+amber_status amber_default_tune_params(amber_tune_params *p)
+{
+    clear_error();
+    if (!p) return fail(AMBER_E_ARG, "params is NULL");
+    *p = amber_tune_params{};
+    p->search = AMBER_SEARCH_GA;
+    p->pop = 32;
+    p->generations = 40;
+    p->crossover = 0;
+    p->p_cross = 0.8;
+    p->p_mut = 0.1;
+    p->pool_frac = 0.2;
+    p->seed = 1;
+    p->warmup = 1;
+    p->reps = 3;
+    p->eval_timeout_s = 1.0;
+    p->max_evals = 0;
+    return AMBER_OK;
+}
+
+amber_status amber_default_space(const amber_delay_info *info, const int32_t *widths, int32_t n_widths, int64_t n_out,
+                                 amber_tune_space *sp)
+{
+    clear_error();
+    if (!info || !widths || !sp) return fail(AMBER_E_ARG, "NULL argument");
+    if (n_widths < 1 || n_widths > AMBER_MAX_WIDTHS) return fail(AMBER_E_ARG, "n_widths=%d out of range", n_widths);
+    *sp = amber_tune_space{};
+    const std::vector<std::vector<int>> vals = {
+        {64, 128, 256, 512, 1024},  // threads_per_dm
+        {4, 8, 16, 32},             // samples_per_thread
+        {1, 2, 4, 8, 16},           // dms_per_block
+        {1, 2, 4, 8, 16, 32},       // channel_unroll
+        {64, 128, 256, 512, 1024},  // snr_threads
+    };
+    sp->n_genes = 5 + n_widths;
+    for (int i = 0; i < sp->n_genes; ++i) {
+        const std::vector<int> v = i < 5 ? vals[i] : std::vector<int>{1, 2, 4, 8};
+        sp->n_values[i] = (int32_t)v.size();
+        for (size_t k = 0; k < v.size(); ++k) sp->values[i][k] = v[k];
+    }
+    sp->info = *info;
+    sp->n_widths = n_widths;
+    for (int k = 0; k < n_widths; ++k) sp->widths[k] = widths[k];
+    sp->n_out = n_out;
+    return AMBER_OK;
+}
+
+amber_status amber_space_size(const amber_tune_space *sp, int64_t *count)
+{
+    clear_error();
+    amber_status s = check_space(sp);
+    if (s != AMBER_OK) return s;
+    if (!count) return fail(AMBER_E_ARG, "count is NULL");
+    // dedispersion and boxcar validity are independent: count each part
+    int64_t n1 = 0, n2 = 0;
+    std::vector<int> g(sp->n_genes, 0);
+    amber_tiles t = default_tiles();
+    for (;;) {
+        t.threads_per_dm = sp->values[0][g[0]];
+        t.samples_per_thread = sp->values[1][g[1]];
+        t.dms_per_block = sp->values[2][g[2]];
+        t.channel_unroll = sp->values[3][g[3]];
+        DedispPlan dp;
+        if (plan_dedisperse(t, sp->info, &dp) == AMBER_OK) ++n1;
+        int i = 0;
+        while (i < 4 && ++g[i] == sp->n_values[i]) g[i++] = 0;
+        if (i == 4) break;
+    }
+    for (;;) {
+        t.snr_threads = sp->values[4][g[4]];
+        for (int k = 0; k < sp->n_widths; ++k) t.boxcar_step[k] = sp->values[5 + k][g[5 + k]];
+        BoxcarPlan bp;
+        if (plan_boxcar(t, sp->widths, sp->n_widths, sp->n_out, &bp) == AMBER_OK) ++n2;
+        int i = 4;
+        while (i < sp->n_genes && ++g[i] == sp->n_values[i]) g[i++] = 0;
+        if (i == sp->n_genes) break;
+    }
+    clear_error();
+    *count = n1 * n2;
+    return AMBER_OK;
+}
+
+amber_status amber_search_tiles(const amber_tune_space *space, const amber_tune_params *p, amber_fitness_fn fn,
+                                void *user, amber_tune_result *result, const char *log_jsonl_path)
+{
+    clear_error();
+    amber_status s = check_space(space);
+    if (s != AMBER_OK) return s;
+    if (!p || !fn || !result) return fail(AMBER_E_ARG, "NULL params, fitness or result");
+    if (!(p->p_cross >= 0 && p->p_cross <= 1 && p->p_mut >= 0 && p->p_mut <= 1 && p->pool_frac > 0 && p->pool_frac <= 1))
+        return fail(AMBER_E_ARG, "probabilities must lie in [0, 1] and pool_frac in (0, 1]");
+    FILE *log = nullptr;
+    if (log_jsonl_path && *log_jsonl_path) {
+        log = fopen(log_jsonl_path, "a");
+        if (!log) return fail(AMBER_E_ARG, "cannot open log %s", log_jsonl_path);
+    }
+    *result = amber_tune_result{};
+    int64_t size = 0;
+    amber_space_size(space, &size);
+    Searcher srch(*space, *p, fn, user, log);
+    s = srch.run(result);
+    result->space_size = size;
+    if (log) fclose(log);
+    return s;
+}
+
+amber_status amber_tune(const amber_tune_space *space, const int32_t *d_delays, const uint8_t *d_in, int64_t in_stride,
+                        int64_t n_in, int32_t *d_dd, int64_t dd_stride, float *d_snr, int32_t *d_peak_t,
+                        const amber_tune_params *p, amber_tune_result *result, const char *log_jsonl_path, void *stream)
+{
+    clear_error();
+    amber_status s = check_space(space);
+    if (s != AMBER_OK) return s;
+    if (!p || !d_delays || !d_in || !d_dd || !d_snr || !result) return fail(AMBER_E_ARG, "NULL argument");
+    if (p->reps < 1 || p->reps > 64 || p->warmup < 0) return fail(AMBER_E_ARG, "reps must be in [1, 64], warmup >= 0");
+    DeviceEval e;
+    e.sp = space;
+    e.d_delays = d_delays;
+    e.d_in = d_in;
+    e.in_stride = in_stride;
+    e.n_in = n_in;
+    e.d_dd = d_dd;
+    e.dd_stride = dd_stride;
+    e.d_snr = d_snr;
+    e.d_peak = d_peak_t;
+    e.warmup = p->warmup;
+    e.reps = p->reps;
+    e.stream = (hipStream_t)stream;
+    e.ev.resize(2 * p->reps);
+    for (auto &ev : e.ev)
+        if (hipEventCreate(&ev) != hipSuccess) return fail(AMBER_E_DEVICE, "hipEventCreate failed");
+    // the default configuration must run: catches bad buffers before searching
+    double t0;
+    if (device_fitness(&default_tiles(), &e, &t0) != 0 && e.error != AMBER_OK) {
+        for (auto &ev : e.ev) (void)hipEventDestroy(ev);
+        return fail(AMBER_E_DEVICE, "the hot path failed on the default tiles");
+    }
+    s = amber_search_tiles(space, p, device_fitness, &e, result, log_jsonl_path);
+    std::string msg = s != AMBER_OK ? amber_last_error() : "";
+    for (auto &ev : e.ev) (void)hipEventDestroy(ev);
+    if (e.error != AMBER_OK) return fail(e.error, "device error during the search");
+    if (s != AMBER_OK) return fail(s, "%s", msg.c_str());
+    return AMBER_OK;
+}
+
+}  // extern "C"

@@ -308,3 +308,26 @@ def test_search_beam_sampled_snr(amber, torch):
         k = list(wl.widths).index(p.width)
         assert sn[k, p.dm_index] > 8.0
         assert abs(int(pk[k, p.dm_index]) - p.t0) <= p.width
+
+
+# --- tile search on the device ----------------------------------------------------------
+
+def test_tune_on_device_keeps_parity(amber, torch, small_case):
+    """A short GA on the device returns a valid configuration; the hot path run
+    with it still matches the oracle bit for bit (and S/N within 1e-5)."""
+    wl, d, mx, x, n_in, dd = small_case
+    g = wl.geom
+    dt, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+    sp = amber.default_space(info, wl.widths, wl.n_out)
+    dev, xd = torch.from_numpy(dt).cuda(), torch.from_numpy(x).cuda()
+    say("tune small GA pop 8 x 3 generations")
+    res = amber.tune(sp, dev, xd, n_in, amber.tune_params("ga", pop=8, generations=3, seed=11))
+    torch.cuda.synchronize()
+    assert res.n_evals > 0 and res.best_time_s > 0
+    amber.validate_tiles(res.best, info, len(wl.widths))
+    got = amber.dedisperse(dev, info, xd, n_in, wl.n_out, tiles=res.best)
+    s, p = amber.integrate_snr(got, wl.n_out, wl.widths, tiles=res.best)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), dd)
+    _, ref_s, ref_p = _oracle_box_snr(dd, wl.widths)
+    _check_snr(s.cpu().numpy(), p.cpu().numpy(), ref_s, ref_p)
