@@ -143,6 +143,98 @@ def tune_report(seeds: int):
     return {"metric": "GA tune time", "unit": "s", "value": out["cost"]["ga_wall_s_median"], "tune": out}
 
 
+def batched_report(n_beams: int, steps: int, warmup: int):
+    """Uneven beams (channels 384/768/1536, 4096-24576 samples, 512/1024/2048
+    DM trials) with GA-picked tiles per shape class: per-beam launches vs one
+    batch vs the batch replayed as a HIP graph."""
+    import numpy as np
+    import torch
+    import paper_1811_04165_amd as amber
+    import workloads
+    wls = workloads.batch_beams(n_beams)
+    widths = wls[0].widths
+    beams = []
+    for k, wl in enumerate(wls):
+        g = wl.geom
+        d, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+        x, n_in = workloads.make_input(wl, d, info.max_delay)
+        beams.append(dict(delays=torch.from_numpy(d).cuda(), info=info, x=torch.from_numpy(x).cuda(), n_in=n_in,
+                          n_out=wl.n_out, dd=torch.empty((g.n_dm, wl.n_out), dtype=torch.int32, device="cuda"),
+                          snr=torch.empty((len(widths), g.n_dm), dtype=torch.float32, device="cuda"),
+                          peak=torch.empty((len(widths), g.n_dm), dtype=torch.int32, device="cuda"),
+                          cls=(g.n_chan, g.n_dm), wl=wl))
+        print("[bench] beam %d/%d built" % (k + 1, len(wls)), file=sys.stderr, flush=True)
+    # GA-picked tiles per shape class, tuned on the class's first beam
+    class_tiles, tune_cost = {}, {}
+    for b in beams:
+        if b["cls"] in class_tiles:
+            continue
+        sp = amber.default_space(b["info"], widths, b["n_out"])
+        print("[bench] tuning class %s" % (b["cls"],), file=sys.stderr, flush=True)
+        r = amber.tune(sp, b["delays"], b["x"], b["n_in"], amber.tune_params("ga", pop=16, generations=12, seed=1),
+                       buffers=(b["dd"], b["snr"], b["peak"]))
+        class_tiles[b["cls"]] = amber.Tiles.from_buffer_copy(r.best)
+        tune_cost["%dch-%ddm" % b["cls"]] = {"evals": r.n_evals, "wall_s": r.wall_s, "best_s": r.best_time_s}
+    tiles = [class_tiles[b["cls"]] for b in beams]
+
+    def per_beam():
+        for b, t in zip(beams, tiles):
+            amber.dedisperse(b["delays"], b["info"], b["x"], b["n_in"], b["n_out"], t, out=b["dd"])
+            amber.integrate_snr(b["dd"], b["n_out"], widths, t, out=(b["snr"], b["peak"]))
+
+    stream = torch.cuda.Stream()
+    batch = amber.Batch(beams, widths, tiles=tiles)
+    with torch.cuda.stream(stream):
+        batch.capture(stream)
+
+    def timed(fn, s=None):
+        s = s or torch.cuda.current_stream()
+        with torch.cuda.stream(s):
+            for _ in range(warmup):
+                fn()
+            s.synchronize()
+            a, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            a.record(s)
+            for _ in range(steps):
+                fn()
+            b_.record(s)
+            s.synchronize()
+            wall = time.perf_counter() - t0
+        return a.elapsed_time(b_) / 1e3 / steps, wall / steps
+
+    print("[bench] timing", file=sys.stderr, flush=True)
+    t_plain, w_plain = timed(per_beam)
+    ref = [(b["dd"].clone(), b["snr"].clone(), b["peak"].clone()) for b in beams]
+    t_batch, w_batch = timed(lambda: batch.run(stream), stream)
+    same_eager = all(torch.equal(b["dd"], r[0]) and torch.equal(b["snr"], r[1]) and torch.equal(b["peak"], r[2])
+                     for b, r in zip(beams, ref))
+    t_graph, w_graph = timed(lambda: batch.launch(stream), stream)
+    same_graph = all(torch.equal(b["dd"], r[0]) and torch.equal(b["snr"], r[1]) and torch.equal(b["peak"], r[2])
+                     for b, r in zip(beams, ref))
+    found = 0
+    for b in beams:
+        p = b["wl"].pulses[0]
+        sn = b["snr"].cpu().numpy()
+        found += int(sn[list(widths).index(p.width), p.dm_index] > 8.0)
+    samples = sum(b["info"].n_dm * b["n_out"] for b in beams)
+    n_launch = batch.launches()
+    batch.close()
+    return {"metric": "DM-trial·samples/s per GPU", "unit": UNIT, "value": samples / t_graph,
+            "batched": {
+                "workload": "%d uneven beams (channels 384/768/1536, 4096-24576 samples, 512/1024/2048 DM trials)"
+                            % len(beams),
+                "dm_trial_samples": samples, "classes": len(class_tiles),
+                "per_beam_launches": {"gpu_s": t_plain, "wall_s": w_plain, "value": samples / t_plain,
+                                      "launches": 2 * len(beams)},
+                "batch_eager": {"gpu_s": t_batch, "wall_s": w_batch, "value": samples / t_batch,
+                                "launches": sum(n_launch)},
+                "batch_graph": {"gpu_s": t_graph, "wall_s": w_graph, "value": samples / t_graph, "graph_launches": 1},
+                "identical_to_per_beam": {"eager": same_eager, "graph": same_graph},
+                "pulses_found": found, "tiles_per_class": {"%dch-%ddm" % k: v.as_dict() for k, v in class_tiles.items()},
+                "tune_per_class": tune_cost}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +246,10 @@ def main() -> int:
                     help="instead of the throughput step: compare the GA tile search with exhaustive, random and "
                          "per-kernel brute-force search on the 256-channel workload")
     ap.add_argument("--tune-seeds", type=int, default=10)
+    ap.add_argument("--batched", action="store_true",
+                    help="instead of the single-beam step: 40 uneven beams, per-beam launches vs one batch vs "
+                         "the batch replayed as a HIP graph")
+    ap.add_argument("--beams", type=int, default=40)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run a plain device-to-device copy of this many bytes 5 times (for scaling "
                          "hardware byte counters read under a profiler)")
@@ -173,6 +269,9 @@ def main() -> int:
         return 3
     if args.tune:
         print(json.dumps(tune_report(args.tune_seeds)))
+        return 0
+    if args.batched:
+        print(json.dumps(batched_report(args.beams, args.steps, args.warmup)))
         return 0
     wl = workloads.beam()
     g = wl.geom

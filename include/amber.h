@@ -274,6 +274,51 @@ amber_status amber_tune(const amber_tune_space *space, const int32_t *d_delays, 
  * p_cross 0.8, p_mut 0.1, pool 20 %, 1 warm-up and 3 timed runs). */
 amber_status amber_default_tune_params(amber_tune_params *p);
 
+/* ---- batched beams: several independent beams in one graph launch ---------- */
+
+/* One beam of a batch: its delay table and buffers, as for amber_dedisperse
+ * and amber_integrate_snr.  Beams may differ in every size. */
+typedef struct {
+    const int32_t *d_delays;
+    amber_delay_info info;
+    const uint8_t *d_in;
+    int64_t in_stride, n_in;
+    int32_t *d_dd;
+    int64_t dd_stride, n_out;
+    float *d_snr;        /* [n_widths][n_dm] */
+    int32_t *d_peak_t;   /* [n_widths][n_dm] or NULL */
+} amber_beam;
+
+typedef struct amber_batch amber_batch;  /* opaque */
+
+/* Plans a batch: beams whose dedispersion tiles coincide share one launch
+ * (each work-group finds its beam in a job table), and beams whose boxcar /
+ * S/N tiles coincide share one launch; all beams use the same widths.
+ * tiles: per-beam array (e.g. a tuned configuration per shape class) or NULL
+ * for amber_auto_tiles of each beam.  The job tables live in device memory
+ * owned by the batch (allocated here, freed by amber_batch_destroy).
+ * Arguments are validated as the single-beam calls validate them. */
+amber_status amber_batch_create(const amber_beam *beams, int32_t n_beams, const int32_t *widths, int32_t n_widths,
+                                const amber_tiles *tiles, amber_batch **batch);
+
+/* Enqueues the batch's launches (dedispersion groups, then boxcar / S/N
+ * groups) on `stream`. */
+amber_status amber_batch_run(amber_batch *batch, void *stream);
+
+/* Captures amber_batch_run into a HIP graph (once; replaces a previous
+ * capture) so that amber_batch_launch replays every launch of the batch with
+ * one hipGraphLaunch.  `stream` must not be capturing already. */
+amber_status amber_batch_capture(amber_batch *batch, void *stream);
+
+/* Replays the captured graph on `stream` (AMBER_E_ARG if not captured). */
+amber_status amber_batch_launch(amber_batch *batch, void *stream);
+
+/* Number of kernel launches one run of the batch makes. */
+amber_status amber_batch_launches(const amber_batch *batch, int32_t *n_dedisperse, int32_t *n_snr);
+
+/* Frees the batch's device job tables and graph.  NULL is a no-op. */
+amber_status amber_batch_destroy(amber_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

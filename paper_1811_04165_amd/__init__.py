@@ -20,11 +20,11 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-from ._lib import (AMBER_MAX_WIDTHS, FITNESS_FN, SEARCH_KINDS, AmberError, DelayInfo, Geometry, Tiles, TuneParams,
+from ._lib import (AMBER_MAX_WIDTHS, FITNESS_FN, Beam, SEARCH_KINDS, AmberError, DelayInfo, Geometry, Tiles, TuneParams,
                    TuneResult, TuneSpace, check, load)
 
 __all__ = ["AmberError", "DelayInfo", "Tiles", "TuneSpace", "TuneParams", "TuneResult", "default_space",
-           "space_size", "tune_params", "search_tiles", "tune", "default_tiles", "make_tiles", "delay_table", "dedisperse",
+           "space_size", "tune_params", "search_tiles", "tune", "Batch", "default_tiles", "make_tiles", "delay_table", "dedisperse",
            "integrate", "snr", "integrate_snr", "validate_tiles", "auto_tiles", "version", "Search"]
 
 load()  # fail loudly at import if the native library is missing
@@ -273,3 +273,58 @@ def tune(space: TuneSpace, delays, x, n_in: int, params: TuneParams, log_path: O
                             dd.data_ptr(), dd.stride(0), s.data_ptr(), p.data_ptr(), ctypes.byref(params),
                             ctypes.byref(res), log_path.encode() if log_path else None, _stream_handle(stream)))
     return res
+
+
+# --- batched beams --------------------------------------------------------------------
+
+class Batch:
+    """Independent beams of uneven sizes run together.
+
+    beams: sequence of dicts with keys delays (int32 CUDA [n_dm, n_chan]),
+    info (DelayInfo), x (uint8 CUDA [n_chan, stride]), n_in, dd (int32 CUDA
+    [n_dm, >= n_out]), n_out, snr (float32 CUDA [n_w, n_dm]), peak (int32 CUDA
+    [n_w, n_dm]).  tiles: per-beam Tiles (or None for automatic tiles).
+    run() enqueues the launches; capture() records them into a HIP graph that
+    launch() replays with one graph launch.
+    """
+
+    def __init__(self, beams, widths: Sequence[int], tiles=None):
+        self._keep = list(beams)
+        arr = (Beam * len(beams))()
+        for k, b in enumerate(beams):
+            arr[k] = Beam(d_delays=b["delays"].data_ptr(), info=b["info"], d_in=b["x"].data_ptr(),
+                          in_stride=b["x"].stride(0), n_in=int(b["n_in"]), d_dd=b["dd"].data_ptr(),
+                          dd_stride=b["dd"].stride(0), n_out=int(b["n_out"]), d_snr=b["snr"].data_ptr(),
+                          d_peak_t=b["peak"].data_ptr())
+        self._w, wp = _widths_arr(widths)
+        tarr = None
+        if tiles is not None:
+            tarr = (Tiles * len(beams))(*tiles)
+        h = ctypes.c_void_p()
+        check(load().amber_batch_create(arr, len(beams), wp, len(self._w), tarr, ctypes.byref(h)))
+        self._h = h
+
+    def launches(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        check(load().amber_batch_launches(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def run(self, stream=None):
+        check(load().amber_batch_run(self._h, _stream_handle(stream)))
+
+    def capture(self, stream):
+        check(load().amber_batch_capture(self._h, _stream_handle(stream)))
+
+    def launch(self, stream=None):
+        check(load().amber_batch_launch(self._h, _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            check(load().amber_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

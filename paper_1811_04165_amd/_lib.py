@@ -82,6 +82,13 @@ class TuneResult(ctypes.Structure):
                 "space_size": self.space_size, "wall_s": self.wall_s}
 
 
+class Beam(ctypes.Structure):
+    _fields_ = [("d_delays", ctypes.c_void_p), ("info", DelayInfo), ("d_in", ctypes.c_void_p),
+                ("in_stride", ctypes.c_int64), ("n_in", ctypes.c_int64), ("d_dd", ctypes.c_void_p),
+                ("dd_stride", ctypes.c_int64), ("n_out", ctypes.c_int64), ("d_snr", ctypes.c_void_p),
+                ("d_peak_t", ctypes.c_void_p)]
+
+
 FITNESS_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.POINTER(Tiles), ctypes.c_void_p, ctypes.POINTER(ctypes.c_double))
 
 # (name, restype, argtypes) of every exported symbol the header declares.
@@ -110,6 +117,14 @@ SIGNATURES = [
     ("amber_default_tune_params", ctypes.c_int, [ctypes.POINTER(TuneParams)]),
     ("amber_search_tiles", ctypes.c_int, [ctypes.POINTER(TuneSpace), ctypes.POINTER(TuneParams), FITNESS_FN,
                                           ctypes.c_void_p, ctypes.POINTER(TuneResult), ctypes.c_char_p]),
+    ("amber_batch_create", ctypes.c_int, [ctypes.POINTER(Beam), ctypes.c_int32, c_i32p, ctypes.c_int32,
+                                          ctypes.POINTER(Tiles), ctypes.POINTER(ctypes.c_void_p)]),
+    ("amber_batch_run", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("amber_batch_capture", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("amber_batch_launch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("amber_batch_launches", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]),
+    ("amber_batch_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("amber_tune", ctypes.c_int, [ctypes.POINTER(TuneSpace), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                   ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.POINTER(TuneParams), ctypes.POINTER(TuneResult), ctypes.c_char_p,

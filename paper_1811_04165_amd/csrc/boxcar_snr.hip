@@ -189,18 +189,26 @@ __device__ __forceinline__ void width_stats_any(int step, const uint32_t *Q, int
 }
 
 // ---- fused boxcar + S/N: one work-group per dedispersed row ----------------
+// One beam per launch, or a table of beams whose rows are laid out back to
+// back in the grid.
 template <int NW>
-__global__ __launch_bounds__(1024) void integrate_snr_kernel(const int32_t *__restrict__ dd, int n_dm,
-                                                             int64_t dd_stride, int64_t n_out, WidthSet ws, int chunk,
-                                                             int halo, int vec_ok, float *__restrict__ snr,
-                                                             int32_t *__restrict__ peak)
+__global__ __launch_bounds__(1024) void integrate_snr_kernel(BoxJob single, const BoxJob *__restrict__ jobs, int n_jobs,
+                                                             WidthSet ws, int chunk, int halo)
 {
     extern __shared__ uint4 lds4[];
     uint32_t *Q = reinterpret_cast<uint32_t *>(lds4);
     Stat *scratch = reinterpret_cast<Stat *>(lds4);  // reused after the last chunk
     __shared__ uint32_t wave_tot[16];
-    const int i = blockIdx.x;
-    const int32_t *__restrict__ row = dd + (size_t)i * dd_stride;
+    int i = blockIdx.x;
+    BoxJob job = single;
+    if (jobs) {
+        int j = 0;
+        while (j + 1 < n_jobs && jobs[j + 1].row_start <= i) ++j;
+        job = jobs[j];
+        i -= job.row_start;
+    }
+    const int64_t n_out = job.n_out;
+    const int32_t *__restrict__ row = job.dd + (size_t)i * job.dd_stride;
     const int outs = chunk - halo;
     const double d0 = (double)row[0];
 
@@ -209,7 +217,7 @@ __global__ __launch_bounds__(1024) void integrate_snr_kernel(const int32_t *__re
     for (int k = 0; k < NW; ++k) stat_init(st[k]);
 
     for (int64_t cs = 0; cs < n_out; cs += outs) {
-        load_prefix(row, cs, n_out, vec_ok != 0, Q, wave_tot);
+        load_prefix(row, cs, n_out, job.vec_ok != 0, Q, wave_tot);
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
             if (k < ws.n) {
@@ -223,8 +231,8 @@ __global__ __launch_bounds__(1024) void integrate_snr_kernel(const int32_t *__re
     if ((int)threadIdx.x < ws.n) {
         const int k = threadIdx.x;
         const int w = ws.w[k];
-        finish(scratch[k * 16], n_out - w + 1, d0 * w, snr + (size_t)k * n_dm + i,
-               peak ? peak + (size_t)k * n_dm + i : nullptr);
+        finish(scratch[k * 16], n_out - w + 1, d0 * w, job.snr + (size_t)k * job.n_dm + i,
+               job.peak ? job.peak + (size_t)k * job.n_dm + i : nullptr);
     }
 }
 
@@ -311,34 +319,58 @@ amber_status allow_lds(F fn, int64_t bytes, const char *what)
 
 }  // namespace
 
-amber_status launch_integrate_snr(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_dd, int n_dm,
-                                  int64_t dd_stride, int64_t n_out, const int32_t *widths, int n_widths,
-                                  float *d_snr, int32_t *d_peak, hipStream_t stream)
+BoxJob make_box_job(const int32_t *d_dd, int n_dm, int64_t dd_stride, int64_t n_out, float *d_snr, int32_t *d_peak)
+{
+    BoxJob j{};
+    j.dd = d_dd;
+    j.dd_stride = dd_stride;
+    j.n_out = n_out;
+    j.snr = d_snr;
+    j.peak = d_peak;
+    j.n_dm = n_dm;
+    j.vec_ok = (dd_stride % 4 == 0) && (((uintptr_t)d_dd & 15) == 0);
+    j.row_start = 0;
+    return j;
+}
+
+amber_status launch_integrate_snr_jobs(const BoxcarPlan &p, const amber_tiles &t, const BoxJob *single,
+                                       const BoxJob *d_jobs, int n_jobs, int64_t n_rows, const int32_t *widths,
+                                       int n_widths, hipStream_t stream)
 {
     amber_status s = check_chunk(p);
     if (s != AMBER_OK) return s;
+    if (n_rows > 0x7fffffff) return fail(AMBER_E_SHAPE, "too many rows (%lld)", (long long)n_rows);
     const WidthSet ws = make_widths(t, widths, n_widths);
     const int halo = halo_of(p);
-    const int vec_ok = (dd_stride % 4 == 0) && (((uintptr_t)d_dd & 15) == 0);
     // the stats scratch reuses the prefix buffer after the last chunk
     int64_t lds = p.lds_bytes;
     const int64_t need = (int64_t)AMBER_MAX_WIDTHS * 16 * sizeof(Stat);
     if (lds < need) lds = need;
+    const BoxJob one = single ? *single : BoxJob{};
+    const dim3 grid((unsigned)n_rows);
     if (n_widths <= 4) {
         if ((s = allow_lds(integrate_snr_kernel<4>, lds, "hipFuncSetAttribute(integrate_snr)")) != AMBER_OK) return s;
-        hipLaunchKernelGGL(integrate_snr_kernel<4>, dim3(n_dm), dim3(p.threads), (size_t)lds, stream, d_dd, n_dm,
-                           dd_stride, n_out, ws, p.chunk, halo, vec_ok, d_snr, d_peak);
+        hipLaunchKernelGGL(integrate_snr_kernel<4>, grid, dim3(p.threads), (size_t)lds, stream, one, d_jobs, n_jobs, ws,
+                           p.chunk, halo);
     } else if (n_widths <= 8) {
         if ((s = allow_lds(integrate_snr_kernel<8>, lds, "hipFuncSetAttribute(integrate_snr)")) != AMBER_OK) return s;
-        hipLaunchKernelGGL(integrate_snr_kernel<8>, dim3(n_dm), dim3(p.threads), (size_t)lds, stream, d_dd, n_dm,
-                           dd_stride, n_out, ws, p.chunk, halo, vec_ok, d_snr, d_peak);
+        hipLaunchKernelGGL(integrate_snr_kernel<8>, grid, dim3(p.threads), (size_t)lds, stream, one, d_jobs, n_jobs, ws,
+                           p.chunk, halo);
     } else {
         if ((s = allow_lds(integrate_snr_kernel<16>, lds, "hipFuncSetAttribute(integrate_snr)")) != AMBER_OK) return s;
-        hipLaunchKernelGGL(integrate_snr_kernel<16>, dim3(n_dm), dim3(p.threads), (size_t)lds, stream, d_dd, n_dm,
-                           dd_stride, n_out, ws, p.chunk, halo, vec_ok, d_snr, d_peak);
+        hipLaunchKernelGGL(integrate_snr_kernel<16>, grid, dim3(p.threads), (size_t)lds, stream, one, d_jobs, n_jobs,
+                           ws, p.chunk, halo);
     }
     AMBER_HIP(hipGetLastError(), "integrate_snr launch");
     return AMBER_OK;
+}
+
+amber_status launch_integrate_snr(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_dd, int n_dm,
+                                  int64_t dd_stride, int64_t n_out, const int32_t *widths, int n_widths,
+                                  float *d_snr, int32_t *d_peak, hipStream_t stream)
+{
+    const BoxJob j = make_box_job(d_dd, n_dm, dd_stride, n_out, d_snr, d_peak);
+    return launch_integrate_snr_jobs(p, t, &j, nullptr, 1, n_dm, widths, n_widths, stream);
 }
 
 amber_status launch_integrate(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_dd, int n_dm,

@@ -46,9 +46,8 @@ __host__ __device__ constexpr uint32_t widen_sel(int a)
 // Maps the round-robin dispatch of work-groups over the 8 XCDs onto tiles so
 // that the groups one XCD runs are consecutive DM blocks of the same time tile
 // and share their input windows in that XCD's L2.
-__device__ __forceinline__ void tile_of_block(int nx, int ny, int remap, int &tx, int &ty)
+__device__ __forceinline__ void tile_of_block(int id, int nx, int ny, int remap, int &tx, int &ty)
 {
-    const int id = blockIdx.x;
     if (remap) {
         const int nb = nx * ny;
         const int xcd = id & 7, local = id >> 3;
@@ -122,15 +121,26 @@ __device__ __forceinline__ void stage_store(lds_w4 *lds, int win2, int items_per
 }
 
 template <int M, int CU, int MAXI>
-__global__ __launch_bounds__(1024) void dedisperse_kernel(
-    const int32_t *__restrict__ delays, int n_dm, int n_chan,
-    const uint8_t *__restrict__ in, int64_t in_stride, int64_t in_bytes,
-    int32_t *__restrict__ dd, int64_t dd_stride, int64_t n_out,
-    int tpd, int dpb, int win, int omax, int tiles_t, int tiles_dm, int store_vec, int remap)
+__global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs,
+                                                          int n_jobs, int tpd, int dpb, int remap)
 {
     static_assert(CU <= 64, "one lane per channel of a group");
     extern __shared__ u32x4 lds_raw[];
     lds_w4 *lds = (lds_w4 *)lds_raw;
+
+    // One job (beam) per launch, or a table of jobs whose tiles are laid out
+    // back to back in the grid.
+    int block = blockIdx.x;
+    DedispJob job = single;
+    if (jobs) {
+        int j = 0;
+        while (j + 1 < n_jobs && jobs[j + 1].block_start <= block) ++j;
+        job = jobs[j];
+        block -= job.block_start;
+    }
+    const int32_t *__restrict__ delays = job.delays;
+    const int n_dm = job.n_dm, n_chan = job.n_chan, win = job.win, omax = job.omax;
+    const int64_t n_out = job.n_out, dd_stride = job.dd_stride;
 
     const int win2 = win >> 1;  // dwords per staged row copy
     const int tid = threadIdx.x;
@@ -141,16 +151,16 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(
     const int dm_local = uniform(wave / waves_per_dm);
     const int wave_t = uniform((wave - dm_local * waves_per_dm) * 128 * M);  // first sample of the wave
     int tx, ty;
-    tile_of_block(tiles_t, tiles_dm, remap, tx, ty);
+    tile_of_block(block, job.tiles_t, job.tiles_dm, remap, tx, ty);
     const int i0 = ty * dpb;
     const int i = i0 + dm_local;
     const bool active = i < n_dm;
     const int64_t t0 = (int64_t)tx * tpd * 2 * M;
 
     StageArgs sa;
-    sa.in = in;
-    sa.in_stride = in_stride;
-    sa.in_bytes = in_bytes;
+    sa.in = job.in;
+    sa.in_stride = job.in_stride;
+    sa.in_bytes = job.in_bytes;
     sa.dfirst = delays + (size_t)i0 * n_chan;
     sa.t0 = t0;
     sa.n_chan = n_chan;
@@ -217,7 +227,8 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(
     }
 
     if (!active) return;
-    int32_t *__restrict__ out = dd + (size_t)i * dd_stride;
+    const int store_vec = job.store_vec;
+    int32_t *__restrict__ out = job.dd + (size_t)i * dd_stride;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const int64_t t = t0 + wave_t + 128 * k + 2 * lane;
@@ -230,8 +241,7 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(
     }
 }
 
-using KernelFn = void (*)(const int32_t *, int, int, const uint8_t *, int64_t, int64_t, int32_t *, int64_t, int64_t,
-                          int, int, int, int, int, int, int, int);
+using KernelFn = void (*)(DedispJob, const DedispJob *, int, int, int, int);
 
 template <int M, int CU>
 KernelFn pick_items(int maxi)
@@ -278,28 +288,52 @@ int xcd_remap_setting()
 
 }  // namespace
 
+DedispJob make_dedisp_job(const DedispPlan &p, const int32_t *d_delays, int n_dm, int n_chan, const uint8_t *d_in,
+                          int64_t in_stride, int32_t *d_dd, int64_t dd_stride, int64_t n_out)
+{
+    DedispJob j{};
+    j.delays = d_delays;
+    j.in = d_in;
+    j.dd = d_dd;
+    j.in_stride = in_stride;
+    j.in_bytes = (int64_t)n_chan * in_stride;
+    j.dd_stride = dd_stride;
+    j.n_out = n_out;
+    j.n_dm = n_dm;
+    j.n_chan = n_chan;
+    j.win = p.win;
+    j.omax = p.omax;
+    j.tiles_t = (int)((n_out + p.tile_t - 1) / p.tile_t);
+    j.tiles_dm = (n_dm + p.dpb - 1) / p.dpb;
+    j.store_vec = (dd_stride % 2 == 0) && (((uintptr_t)d_dd & 7) == 0);
+    j.block_start = 0;
+    return j;
+}
+
+amber_status launch_dedisperse_jobs(const DedispPlan &p, const DedispJob *single, const DedispJob *d_jobs,
+                                    int n_jobs, int64_t n_blocks, int64_t lds_bytes, hipStream_t stream)
+{
+    KernelFn fn = pick(p.spt, p.cu, p.maxi);
+    if (!fn) return fail(AMBER_E_CONFIG, "no dedispersion kernel for spt=%d cu=%d maxi=%d", p.spt, p.cu, p.maxi);
+    if (lds_bytes > 64 * 1024)
+        AMBER_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes),
+                  "hipFuncSetAttribute(dedisperse)");
+    if (n_blocks > 0x7fffffff) return fail(AMBER_E_SHAPE, "grid of %lld work-groups is too large", (long long)n_blocks);
+    static const int remap = xcd_remap_setting();
+    hipLaunchKernelGGL(fn, dim3((unsigned)n_blocks), dim3(p.threads), (size_t)lds_bytes, stream,
+                       single ? *single : DedispJob{}, d_jobs, n_jobs, p.tpd, p.dpb, d_jobs ? 0 : remap);
+    AMBER_HIP(hipGetLastError(), "dedisperse launch");
+    return AMBER_OK;
+}
+
 amber_status launch_dedisperse(const DedispPlan &p, const int32_t *d_delays, int n_dm, int n_chan,
                                const uint8_t *d_in, int64_t in_stride, int64_t n_in, int32_t *d_dd,
                                int64_t dd_stride, int64_t n_out, hipStream_t stream)
 {
     (void)n_in;
-    KernelFn fn = pick(p.spt, p.cu, p.maxi);
-    if (!fn) return fail(AMBER_E_CONFIG, "no dedispersion kernel for spt=%d cu=%d", p.spt, p.cu);
-    if (p.lds_bytes > 64 * 1024)
-        AMBER_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_bytes),
-                  "hipFuncSetAttribute(dedisperse)");
-    const int64_t tiles_t = (n_out + p.tile_t - 1) / p.tile_t;
-    const int64_t tiles_dm = (n_dm + p.dpb - 1) / p.dpb;
-    if (tiles_t * tiles_dm > 0x7fffffff)
-        return fail(AMBER_E_SHAPE, "grid of %lld x %lld tiles is too large", (long long)tiles_t, (long long)tiles_dm);
-    const int store_vec = (dd_stride % 2 == 0) && (((uintptr_t)d_dd & 7) == 0);
-    static const int remap = xcd_remap_setting();
-    hipLaunchKernelGGL(fn, dim3((unsigned)(tiles_t * tiles_dm)), dim3(p.threads), (size_t)p.lds_bytes, stream,
-                       d_delays, n_dm, n_chan, d_in, in_stride, (int64_t)n_chan * in_stride, d_dd, dd_stride, n_out,
-                       p.tpd, p.dpb, p.win, p.omax, (int)tiles_t, (int)tiles_dm, store_vec, remap);
-    AMBER_HIP(hipGetLastError(), "dedisperse launch");
-    return AMBER_OK;
+    const DedispJob j = make_dedisp_job(p, d_delays, n_dm, n_chan, d_in, in_stride, d_dd, dd_stride, n_out);
+    return launch_dedisperse_jobs(p, &j, nullptr, 1, (int64_t)j.tiles_t * j.tiles_dm, p.lds_bytes, stream);
 }
 
 }  // namespace amber

@@ -54,6 +54,36 @@ amber_status plan_boxcar(const amber_tiles &t, const int32_t *widths, int32_t n_
 
 const amber_tiles &default_tiles();
 
+// One beam's dedispersion work: the arguments of a launch, or one entry of a
+// batched launch's job table (tiles of job j occupy work-groups
+// [block_start, block_start + tiles_t * tiles_dm)).
+struct DedispJob {
+    const int32_t *delays;
+    const uint8_t *in;
+    int32_t *dd;
+    int64_t in_stride, in_bytes, dd_stride, n_out;
+    int n_dm, n_chan, win, omax, tiles_t, tiles_dm, store_vec, block_start;
+};
+
+// One beam's boxcar / S/N work (rows of job j occupy work-groups
+// [row_start, row_start + n_dm)).
+struct BoxJob {
+    const int32_t *dd;
+    int64_t dd_stride, n_out;
+    float *snr;
+    int32_t *peak;
+    int n_dm, vec_ok, row_start;
+};
+
+DedispJob make_dedisp_job(const DedispPlan &p, const int32_t *d_delays, int n_dm, int n_chan, const uint8_t *d_in,
+                          int64_t in_stride, int32_t *d_dd, int64_t dd_stride, int64_t n_out);
+amber_status launch_dedisperse_jobs(const DedispPlan &p, const DedispJob *single, const DedispJob *d_jobs,
+                                    int n_jobs, int64_t n_blocks, int64_t lds_bytes, hipStream_t stream);
+BoxJob make_box_job(const int32_t *d_dd, int n_dm, int64_t dd_stride, int64_t n_out, float *d_snr, int32_t *d_peak);
+amber_status launch_integrate_snr_jobs(const BoxcarPlan &p, const amber_tiles &t, const BoxJob *single,
+                                       const BoxJob *d_jobs, int n_jobs, int64_t n_rows, const int32_t *widths,
+                                       int n_widths, hipStream_t stream);
+
 // Launchers (device translation units).
 amber_status launch_dedisperse(const DedispPlan &p, const int32_t *d_delays, int n_dm, int n_chan,
                                const uint8_t *d_in, int64_t in_stride, int64_t n_in, int32_t *d_dd,

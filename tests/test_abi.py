@@ -128,6 +128,11 @@ def test_gpu_test_tiles_are_valid():
         assert amber.auto_tiles(info).as_dict() == amber.default_tiles().as_dict()
         for kw in t.TILE_SWEEP:
             amber.validate_tiles(amber.make_tiles(**kw), info, len(wl.widths))
+    for k, wl in enumerate(t._small_batch_workloads()):
+        g = wl.geom
+        _, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+        amber.validate_tiles(amber.make_tiles(samples_per_thread=8 if k % 2 else 16, channel_unroll=16), info,
+                             len(wl.widths))
     for n_chan, n_dm, n_out, step, pad in t.ODD:
         freqs = t.odd_freqs(n_chan, n_dm)
         _, info = amber.delay_table(freqs, 81.92e-6, n_dm, 1.5, step)

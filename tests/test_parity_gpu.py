@@ -331,3 +331,63 @@ def test_tune_on_device_keeps_parity(amber, torch, small_case):
     assert np.array_equal(got.cpu().numpy(), dd)
     _, ref_s, ref_p = _oracle_box_snr(dd, wl.widths)
     _check_snr(s.cpu().numpy(), p.cpu().numpy(), ref_s, ref_p)
+
+
+# --- batched beams -------------------------------------------------------------------------
+
+def _small_batch_workloads():
+    """Uneven beams (channels, samples and DM trials differ) small enough for
+    the oracle: same recipe as the 40-beam workload at reduced sizes."""
+    out = []
+    for b, (n_chan, n_out, n_dm) in enumerate([(96, 1500, 40), (192, 2300, 24), (96, 1100, 40), (48, 3001, 17),
+                                                 (192, 777, 33), (384, 1800, 12)]):
+        out.append(workloads.Workload(
+            name="b%d" % b, geom=workloads.Geometry(n_chan=n_chan, n_dm=n_dm, dm_first=0.0, dm_step=2.0),
+            n_out=n_out, widths=(1, 2, 4, 8, 16),
+            pulses=(workloads.Pulse(dm_index=n_dm // 2, width=4, amp=50, t0=n_out // 2),), seed=900 + b))
+    return out
+
+
+def test_batched_beams_match_single_beams(amber, torch):
+    widths = (1, 2, 4, 8, 16)
+    beams, refs = [], []
+    for wl in _small_batch_workloads():
+        g = wl.geom
+        d, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+        do, mx = oracle.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+        x, n_in = workloads.make_input(wl, do, mx)
+        ref_dd = oracle.dedisperse(do, x, n_in, wl.n_out)
+        _, ref_s, ref_p = _oracle_box_snr(ref_dd, widths)
+        refs.append((ref_dd, ref_s, ref_p))
+        beams.append(dict(delays=torch.from_numpy(d).cuda(), info=info, x=torch.from_numpy(x).cuda(), n_in=n_in,
+                          dd=torch.full((g.n_dm, wl.n_out + 3), -1, dtype=torch.int32, device="cuda"),
+                          n_out=wl.n_out, snr=torch.zeros((len(widths), g.n_dm), dtype=torch.float32, device="cuda"),
+                          peak=torch.zeros((len(widths), g.n_dm), dtype=torch.int32, device="cuda")))
+    # two tile classes so the batch needs more than one launch per kernel
+    tiles = [amber.make_tiles(samples_per_thread=8 if k % 2 else 16, channel_unroll=16) for k in range(len(beams))]
+    say("batch of %d uneven beams, eager" % len(beams))
+    batch = amber.Batch(beams, widths, tiles=tiles)
+    assert batch.launches() == (2, 1)
+    batch.run()
+    torch.cuda.synchronize()
+    for b, (ref_dd, ref_s, ref_p) in zip(beams, refs):
+        assert np.array_equal(b["dd"][:, :b["n_out"]].cpu().numpy(), ref_dd)
+        _check_snr(b["snr"].cpu().numpy(), b["peak"].cpu().numpy(), ref_s, ref_p)
+    first = [(b["snr"].clone(), b["dd"][:, :b["n_out"]].clone()) for b in beams]
+    # graph replays: identical results every time, with eager work in between
+    stream = torch.cuda.Stream()
+    say("batch graph capture + 3 replays")
+    with torch.cuda.stream(stream):
+        batch.capture(stream)
+    for rep in range(3):
+        for b in beams:
+            b["snr"].zero_()
+            b["dd"].fill_(-5)
+        torch.cuda.synchronize()
+        batch.launch(stream)
+        stream.synchronize()
+        for b, (s0, d0) in zip(beams, first):
+            assert torch.equal(b["snr"], s0) and torch.equal(b["dd"][:, :b["n_out"]], d0), rep
+            assert torch.all(b["dd"][:, b["n_out"]:] == -5)   # columns past n_out untouched
+        _ = torch.ones(1000, device="cuda").sum()   # unrelated eager work between replays
+    batch.close()
