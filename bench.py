@@ -235,6 +235,108 @@ def batched_report(n_beams: int, steps: int, warmup: int):
                 "tune_per_class": tune_cost}}
 
 
+def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitters: int = 4):
+    """Streaming: Poisson arrivals of 0.5-s chunks from beams of 768 ch / 1024
+    DM trials and 1536 ch / 2048 DM trials, served with continuous batching
+    vs the same service restricted to one chunk at a time (plain per-chunk
+    launches: no fusion, no overlap).  Latency runs from a chunk's scheduled
+    arrival to its results being on the host."""
+    import threading
+    import numpy as np
+    import paper_1811_04165_amd as amber
+    import workloads
+    geoms = workloads.stream_geometries(n_beams)
+    L = workloads.STREAM_CHUNK
+    widths = (1, 2, 4, 8, 16, 32, 64)
+    # one seeded noise block per beam shape, 4 chunks long with one pulse per
+    # second; beam b reads its chunks from it at a rotated offset
+    n_blk, blocks = 4, {}
+    for g in geoms:
+        key = (g.n_chan, g.n_dm)
+        if key in blocks:
+            continue
+        d, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+        x = workloads.noise(g.n_chan, n_blk * L, n_blk * L, seed=5000 + len(blocks))
+        for s_ in range(2):
+            workloads.inject(x, d[g.n_dm // 2], t0=1000 + 2 * L * s_, width=8, amp=40)
+        blocks[key] = x
+        print("[bench] stream block %s built" % (key,), file=sys.stderr, flush=True)
+
+    def run(rate, duration, **cfg):
+        arrivals = workloads.poisson_arrivals(n_beams, rate / n_beams, duration, seed=5)
+        srv = amber.Server(**cfg)
+        for g in geoms:
+            srv.add_beam(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step, L, widths)
+        done, err = [], []
+
+        def collect(n):
+            try:
+                for _ in range(n):
+                    r = srv.wait(60.0)
+                    if r is None:
+                        raise RuntimeError("no chunk completed within 60 s")
+                    done.append(r)
+            except Exception as e:  # reported below
+                err.append(e)
+
+        lag = [0.0]
+        t0 = amber.server_clock() + 0.05
+
+        def submit(part):
+            for t, b, seq in part:
+                now = amber.server_clock() - t0
+                if t > now:
+                    time.sleep(t - now)
+                else:
+                    lag[0] = max(lag[0], now - t)
+                g = geoms[b]
+                off = ((seq + 3 * b) % n_blk) * L
+                srv.submit(b, blocks[(g.n_chan, g.n_dm)][:, off:off + L], tag=seq)
+
+        col = threading.Thread(target=collect, args=(len(arrivals),))
+        col.start()
+        subs = [threading.Thread(target=submit, args=([a for a in arrivals if a[1] % submitters == i],))
+                for i in range(submitters)]
+        for th in subs:
+            th.start()
+        for th in subs:
+            th.join()
+        col.join()
+        st = srv.stats()
+        srv.close()
+        if err:
+            raise err[0]
+        arr = {(b, seq): t for t, b, seq in arrivals}
+        meas = [r for r in done if arr[(r["beam"], r["seq"])] >= warmup_s]
+        lat = np.array([r["t_done"] - (t0 + arr[(r["beam"], r["seq"])]) for r in meas])
+        work = sum(geoms[r["beam"]].n_dm * r["n_out"] for r in meas)
+        first = t0 + min(arr[(r["beam"], r["seq"])] for r in meas)
+        last = max(r["t_done"] for r in meas)
+        bs = np.array([r["batch_size"] for r in meas])
+        return {"offered_chunks_per_s": rate, "chunks": len(meas), "value": work / (last - first),
+                "chunks_per_s": len(meas) / (last - first),
+                "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99)),
+                               "max": 1e3 * float(lat.max()), "mean": 1e3 * float(lat.mean())},
+                "batch_size": {"mean": float(bs.mean()), "max": int(bs.max())},
+                "launch_groups": st["batches"], "max_submit_lag_ms": 1e3 * lag[0],
+                "memory_peak_bytes": st["memory_peak"]}
+
+    out = {}
+    for rate in rates:
+        for name, cfg in (("served", dict(max_inflight=64, max_batch=16, n_streams=4)),
+                          ("one_at_a_time", dict(max_inflight=1, max_batch=1, n_streams=1))):
+            print("[bench] serve %s at %g chunks/s" % (name, rate), file=sys.stderr, flush=True)
+            # overload points run briefly: a backlog holds one pinned staging buffer per queued chunk
+            dur = seconds if rate == rates[0] else min(seconds, 3.0)
+            out.setdefault(str(rate), {})[name] = run(rate, warmup_s + dur, **cfg)
+    base = out[str(rates[0])]
+    return {"metric": "p99 chunk latency", "unit": "ms", "value": base["served"]["latency_ms"]["p99"],
+            "higher_is_better": False,
+            "serve": {"workload": "%d beams (768 ch / 1024 DM trials and 1536 ch / 2048 DM trials, alternating), "
+                                  "0.5-s chunks of %d samples, widths 1-64, Poisson arrivals" % (n_beams, L),
+                      "seconds": seconds, "warmup_s": warmup_s, "submit_threads": submitters, "by_rate": out}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,6 +352,12 @@ def main() -> int:
                     help="instead of the single-beam step: 40 uneven beams, per-beam launches vs one batch vs "
                          "the batch replayed as a HIP graph")
     ap.add_argument("--beams", type=int, default=40)
+    ap.add_argument("--serve", action="store_true",
+                    help="instead of the single-beam step: the streaming service under Poisson arrivals, "
+                         "continuous batching vs one chunk at a time")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-warmup", type=float, default=1.0)
+    ap.add_argument("--serve-rates", type=str, default="400,1600", help="offered chunks/s, comma separated")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run a plain device-to-device copy of this many bytes 5 times (for scaling "
                          "hardware byte counters read under a profiler)")
@@ -272,6 +380,10 @@ def main() -> int:
         return 0
     if args.batched:
         print(json.dumps(batched_report(args.beams, args.steps, args.warmup)))
+        return 0
+    if args.serve:
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        print(json.dumps(serve_report(args.beams, args.serve_seconds, args.serve_warmup, rates)))
         return 0
     wl = workloads.beam()
     g = wl.geom

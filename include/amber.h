@@ -43,7 +43,7 @@ typedef enum {
     AMBER_E_CONFIG = -3,  /* tile configuration outside the kernel's space */
     AMBER_E_DEVICE = -4,  /* HIP runtime or launch error */
     AMBER_E_NOMEM = -5,   /* device allocation failed */
-    AMBER_E_TIMEOUT = -6  /* a timed evaluation exceeded its limit */
+    AMBER_E_TIMEOUT = -6  /* a timed evaluation exceeded its limit, or a wait ended empty */
 } amber_status;
 
 #define AMBER_MAX_WIDTHS 16
@@ -318,6 +318,115 @@ amber_status amber_batch_launches(const amber_batch *batch, int32_t *n_dedispers
 
 /* Frees the batch's device job tables and graph.  NULL is a no-op. */
 amber_status amber_batch_destroy(amber_batch *batch);
+
+/* ---- streaming service: continuous batching of beam chunks ------------------ */
+
+/* Chunks of L samples of several beams arrive over time (the paper's data
+ * arrives in batches of fixed length, Table 2 BATCHES).  Each beam keeps the
+ * last max_delay input samples in HBM, so chunk k (k = 0, 1, ...) yields the
+ * dedispersed outputs for absolute times [max(0, kL - max_delay),
+ * (k+1)L - max_delay) and their S/N table, exactly what a single call on the
+ * concatenated input would give for those outputs (boxcars do not cross chunk
+ * edges; S/N statistics use only the chunk's outputs).  A scheduler thread
+ * admits each beam's next chunk when a slot and device memory are free, fuses
+ * the admitted chunks of different beams into shared launches, and runs
+ * batches on several streams so their work overlaps. */
+typedef struct amber_server amber_server;
+
+typedef struct {
+    int32_t max_inflight;   /* chunks on the device at once (1..4096); at most 32 launch groups run at once */
+    int32_t max_batch;      /* chunks fused into one launch group (1..1024) */
+    int32_t n_streams;      /* HIP streams launch groups are spread over (1..8), default priority */
+    int64_t memory_budget;  /* device bytes for in-flight chunks; 0 = 90 % of the free HBM at creation */
+} amber_server_config;
+
+typedef struct {
+    int32_t n_chan;
+    const double *freq_mhz;   /* [n_chan], copied */
+    double t_samp_s;
+    int32_t n_dm;
+    double dm_first, dm_step;
+    int64_t chunk;            /* samples per chunk L; widths <= L */
+    const amber_tiles *tiles; /* NULL = amber_auto_tiles */
+} amber_stream_beam;
+
+typedef struct {
+    int32_t beam;
+    int32_t n_widths, n_dm;   /* shape of the S/N table */
+    int64_t seq;              /* chunk index within the beam */
+    uint64_t tag;             /* caller's tag from amber_server_submit */
+    int64_t t_first;          /* absolute time of the chunk's first output */
+    int64_t n_out;            /* outputs of the chunk (0: still inside the first max_delay samples) */
+    int32_t has_snr;          /* 0 if n_out is shorter than the largest width */
+    int32_t batch_size;       /* chunks in the launch group it ran in */
+    double t_submit, t_start, t_done;  /* seconds on the library's steady clock */
+} amber_chunk_result;
+
+typedef struct {
+    int64_t submitted, completed, batches, queued, inflight;
+    int64_t memory_in_use, memory_peak, memory_budget;
+    int64_t admissions_deferred_for_memory;
+} amber_server_stats;
+
+/* Outputs of chunk `seq` of a beam with chunks of L samples and largest delay
+ * max_delay: absolute times [*t_first, *t_first + *n_out), where
+ * t_first = max(0, seq*L - max_delay) and the end is (seq+1)*L - max_delay
+ * (n_out = 0 while that end is not past t_first).  Host only. */
+amber_status amber_chunk_span(int64_t seq, int64_t L, int32_t max_delay, int64_t *t_first, int64_t *n_out);
+
+/* The admission rule the service applies, exported so that it can be checked
+ * and capacity planned without a device.  Pending chunks are taken in arrival
+ * order.  A chunk is passed over while its beam has a chunk on the device or
+ * an earlier chunk still waiting (one beam's chunks run one at a time, in
+ * order).  Admission stops at the first other chunk whose device bytes would
+ * take memory_in_use past config->memory_budget (so large chunks are not
+ * overtaken by small ones), once `inflight` plus the admitted
+ * reach config->max_inflight, or once config->max_batch were admitted.
+ * beam_busy[b] != 0 marks beams with a chunk on the device; memory_budget is
+ * taken as given (0 is a zero budget here).  Writes the indices of the
+ * admitted chunks, ascending, to `admitted` (room for n_pending), their count
+ * to *n_admitted, and to *blocked_at the index of the chunk that did not fit
+ * the budget, or -1.  Host only. */
+typedef struct {
+    int32_t beam;
+    int64_t bytes;
+} amber_pending_chunk;
+
+amber_status amber_server_admit(const amber_pending_chunk *pending, int32_t n_pending, const uint8_t *beam_busy,
+                                int32_t n_beams, int32_t inflight, int64_t memory_in_use,
+                                const amber_server_config *config, int32_t *admitted, int32_t *n_admitted,
+                                int32_t *blocked_at);
+
+amber_status amber_server_create(const amber_server_config *config, amber_server **server);
+
+/* Registers a beam (allocates its delay table and overlap buffers; refused
+ * with AMBER_E_NOMEM if they do not fit the free HBM). */
+amber_status amber_server_add_beam(amber_server *server, const amber_stream_beam *beam, const int32_t *widths,
+                                   int32_t n_widths, int32_t *beam_id);
+
+/* Queues the next chunk of a beam: host uint8 [n_chan][L] with row pitch
+ * `pitch` bytes, copied (into pinned staging) before the call returns.  The
+ * chunks of one beam are numbered in the order their submissions return, so
+ * one beam's chunks come from one thread at a time.  t_submit is taken on
+ * entry, so latency includes the staging copy. */
+amber_status amber_server_submit(amber_server *server, int32_t beam_id, const uint8_t *chunk, int64_t pitch,
+                                 uint64_t tag);
+
+/* Waits up to timeout_s for the oldest completed chunk; copies its S/N table
+ * (float [n_widths][n_dm]) and peaks (int32, peak index relative to t_first)
+ * into the caller's host buffers of `capacity` elements each (either may be
+ * NULL).  AMBER_E_TIMEOUT if nothing completed in time. */
+amber_status amber_server_wait(amber_server *server, double timeout_s, amber_chunk_result *result, float *snr,
+                               int32_t *peak_t, int64_t capacity);
+
+amber_status amber_server_get_stats(amber_server *server, amber_server_stats *stats);
+
+/* Seconds on the clock used for t_submit / t_start / t_done. */
+double amber_server_clock(void);
+
+/* Completes every submitted chunk (results not waited for are dropped), stops
+ * the scheduler and frees everything. */
+amber_status amber_server_destroy(amber_server *server);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,8 @@ Steps (see include/amber.h for the exact contracts):
     integrate      -> int32 [n_w, n_dm, n_out] sliding boxcars (valid prefix per width)
     snr            -> (float32 [n_w, n_dm], int32 [n_w, n_dm]) from boxcar series
     integrate_snr  -> the previous two fused
+    Batch          -> beams of uneven sizes in shared launches / one HIP graph
+    Server         -> streaming chunks with continuous batching
 """
 from __future__ import annotations
 
@@ -20,12 +22,14 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-from ._lib import (AMBER_MAX_WIDTHS, FITNESS_FN, Beam, SEARCH_KINDS, AmberError, DelayInfo, Geometry, Tiles, TuneParams,
-                   TuneResult, TuneSpace, check, load)
+from ._lib import (AMBER_E_TIMEOUT, AMBER_MAX_WIDTHS, FITNESS_FN, Beam, ChunkResult, PendingChunk, SEARCH_KINDS,
+                   AmberError, DelayInfo, Geometry, ServerConfig, ServerStats, StreamBeam, Tiles, TuneParams, TuneResult,
+                   TuneSpace, check, load)
 
 __all__ = ["AmberError", "DelayInfo", "Tiles", "TuneSpace", "TuneParams", "TuneResult", "default_space",
            "space_size", "tune_params", "search_tiles", "tune", "Batch", "default_tiles", "make_tiles", "delay_table", "dedisperse",
-           "integrate", "snr", "integrate_snr", "validate_tiles", "auto_tiles", "version", "Search"]
+           "integrate", "snr", "integrate_snr", "validate_tiles", "auto_tiles", "version", "Search", "Server",
+           "chunk_span", "admit", "server_config", "server_clock"]
 
 load()  # fail loudly at import if the native library is missing
 
@@ -322,6 +326,113 @@ class Batch:
         if getattr(self, "_h", None) is not None and self._h.value:
             check(load().amber_batch_destroy(self._h))
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def chunk_span(seq: int, chunk: int, max_delay: int):
+    """(t_first, n_out): the absolute output times chunk `seq` of a stream yields."""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    check(load().amber_chunk_span(int(seq), int(chunk), int(max_delay), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def server_config(max_inflight: int = 64, max_batch: int = 32, n_streams: int = 4, memory_budget: int = 0):
+    return ServerConfig(max_inflight=max_inflight, max_batch=max_batch, n_streams=n_streams,
+                        memory_budget=memory_budget)
+
+
+def admit(pending, beam_busy, inflight: int, memory_in_use: int, config: ServerConfig):
+    """The service's admission rule on host data: pending = [(beam, bytes)] in
+    arrival order, beam_busy = per-beam flags.  Returns (admitted indices,
+    index of the chunk that did not fit the memory budget or -1)."""
+    n = len(pending)
+    parr = (PendingChunk * max(n, 1))(*[PendingChunk(beam=int(b), bytes=int(x)) for b, x in pending])
+    busy = (ctypes.c_uint8 * max(len(beam_busy), 1))(*[1 if v else 0 for v in beam_busy])
+    out = (ctypes.c_int32 * max(n, 1))()
+    na, blocked = ctypes.c_int32(), ctypes.c_int32()
+    check(load().amber_server_admit(parr, n, busy, len(beam_busy), int(inflight), int(memory_in_use),
+                                    ctypes.byref(config), out, ctypes.byref(na), ctypes.byref(blocked)))
+    return [out[k] for k in range(na.value)], blocked.value
+
+
+def server_clock() -> float:
+    return load().amber_server_clock()
+
+
+class Server:
+    """Streaming service: beams registered with add_beam(), chunks (host
+    uint8 [n_chan, L] arrays) queued with submit(), results taken with wait().
+
+    The library's scheduler thread admits chunks as launch slots and device
+    memory free up, fuses the admitted chunks of different beams into shared
+    launches and spreads them over n_streams streams; every beam keeps its
+    last max_delay input samples on the device between chunks.
+    """
+
+    def __init__(self, max_inflight: int = 64, max_batch: int = 32, n_streams: int = 4, memory_budget: int = 0):
+        self.config = server_config(max_inflight, max_batch, n_streams, memory_budget)
+        h = ctypes.c_void_p()
+        check(load().amber_server_create(ctypes.byref(self.config), ctypes.byref(h)))
+        self._h = h
+        self._beams = []
+
+    def add_beam(self, freqs, t_samp_s: float, n_dm: int, dm_first: float, dm_step: float, chunk: int,
+                 widths: Sequence[int], tiles: Optional[Tiles] = None) -> int:
+        f = np.ascontiguousarray(freqs, dtype=np.float64)
+        w, wp = _widths_arr(widths)
+        b = StreamBeam(n_chan=len(f), freq_mhz=f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), t_samp_s=t_samp_s,
+                       n_dm=n_dm, dm_first=dm_first, dm_step=dm_step, chunk=int(chunk),
+                       tiles=ctypes.pointer(tiles) if tiles is not None else None)
+        bid = ctypes.c_int32()
+        check(load().amber_server_add_beam(self._h, ctypes.byref(b), wp, len(w), ctypes.byref(bid)))
+        self._beams.append((len(f), int(chunk), n_dm, len(w)))
+        return bid.value
+
+    def submit(self, beam: int, chunk: np.ndarray, tag: int = 0) -> None:
+        n_chan, L, _, _ = self._beams[beam]
+        if chunk.dtype != np.uint8 or chunk.ndim != 2 or chunk.shape[0] != n_chan or chunk.shape[1] < L \
+                or chunk.strides[1] != 1:
+            raise ValueError("chunk must be a uint8 [%d, >= %d] array with unit column stride" % (n_chan, L))
+        check(load().amber_server_submit(self._h, beam, chunk.ctypes.data, chunk.strides[0], int(tag)))
+
+    def wait(self, timeout: float = 10.0):
+        """The oldest completed chunk as a dict (result fields plus "snr" and
+        "peak" arrays of [n_widths, n_dm], None when has_snr is 0), or None if
+        nothing completed within `timeout` seconds."""
+        r = ChunkResult()
+        cap = max(nd * nw for _, _, nd, nw in self._beams) if self._beams else 0
+        snr = np.empty(max(cap, 1), np.float32)
+        peak = np.empty(max(cap, 1), np.int32)
+        st = load().amber_server_wait(self._h, float(timeout), ctypes.byref(r), snr.ctypes.data, peak.ctypes.data, cap)
+        if st == AMBER_E_TIMEOUT:
+            return None
+        check(st)
+        d = r.as_dict()
+        n = r.n_widths * r.n_dm
+        d["snr"] = snr[:n].reshape(r.n_widths, r.n_dm).copy() if r.has_snr else None
+        d["peak"] = peak[:n].reshape(r.n_widths, r.n_dm).copy() if r.has_snr else None
+        return d
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        check(load().amber_server_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            check(load().amber_server_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):
         try:

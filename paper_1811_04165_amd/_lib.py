@@ -45,6 +45,7 @@ class Tiles(ctypes.Structure):
 
 AMBER_MAX_GENES = 5 + AMBER_MAX_WIDTHS
 AMBER_MAX_GENE_VALUES = 8
+AMBER_E_TIMEOUT = -6
 SEARCH_KINDS = {"ga": 0, "exhaustive": 1, "random": 2, "per_kernel": 3}
 
 
@@ -89,6 +90,40 @@ class Beam(ctypes.Structure):
                 ("d_peak_t", ctypes.c_void_p)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("memory_budget", ctypes.c_int64)]
+
+
+class StreamBeam(ctypes.Structure):
+    _fields_ = [("n_chan", ctypes.c_int32), ("freq_mhz", c_f64p), ("t_samp_s", ctypes.c_double),
+                ("n_dm", ctypes.c_int32), ("dm_first", ctypes.c_double), ("dm_step", ctypes.c_double),
+                ("chunk", ctypes.c_int64), ("tiles", ctypes.POINTER(Tiles))]
+
+
+class ChunkResult(ctypes.Structure):
+    _fields_ = [("beam", ctypes.c_int32), ("n_widths", ctypes.c_int32), ("n_dm", ctypes.c_int32),
+                ("seq", ctypes.c_int64), ("tag", ctypes.c_uint64), ("t_first", ctypes.c_int64),
+                ("n_out", ctypes.c_int64), ("has_snr", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "batches", "queued", "inflight",
+                                               "memory_in_use", "memory_peak", "memory_budget",
+                                               "admissions_deferred_for_memory")]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class PendingChunk(ctypes.Structure):
+    _fields_ = [("beam", ctypes.c_int32), ("bytes", ctypes.c_int64)]
+
+
 FITNESS_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.POINTER(Tiles), ctypes.c_void_p, ctypes.POINTER(ctypes.c_double))
 
 # (name, restype, argtypes) of every exported symbol the header declares.
@@ -125,6 +160,21 @@ SIGNATURES = [
     ("amber_batch_launches", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32)]),
     ("amber_batch_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("amber_chunk_span", ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    ("amber_server_admit", ctypes.c_int, [ctypes.POINTER(PendingChunk), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_uint8), ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int64, ctypes.POINTER(ServerConfig), c_i32p, c_i32p, c_i32p]),
+    ("amber_server_create", ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]),
+    ("amber_server_add_beam", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(StreamBeam), c_i32p, ctypes.c_int32,
+                                             c_i32p]),
+    ("amber_server_submit", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_uint64]),
+    ("amber_server_wait", ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(ChunkResult),
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    ("amber_server_get_stats", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    ("amber_server_clock", ctypes.c_double, []),
+    ("amber_server_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("amber_tune", ctypes.c_int, [ctypes.POINTER(TuneSpace), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                   ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.POINTER(TuneParams), ctypes.POINTER(TuneResult), ctypes.c_char_p,

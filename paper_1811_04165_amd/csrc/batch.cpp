@@ -1,30 +1,11 @@
 // Batched beams: independent beams of uneven sizes planned into as few
 // launches as their tiles allow, replayable as one HIP graph.
-#include <algorithm>
-#include <map>
-#include <tuple>
 #include <vector>
 
 #include "internal.h"
 
 namespace amber {
 namespace {
-
-struct DGroup {
-    DedispPlan plan;
-    int64_t lds = 0;
-    int64_t n_blocks = 0;
-    std::vector<DedispJob> jobs;
-    DedispJob *d_jobs = nullptr;
-};
-
-struct BGroup {
-    BoxcarPlan plan;
-    amber_tiles tiles;
-    int64_t n_rows = 0;
-    std::vector<BoxJob> jobs;
-    BoxJob *d_jobs = nullptr;
-};
 
 amber_status check_beam(const amber_beam &b, int k, const int32_t *widths, int n_widths)
 {
@@ -47,9 +28,7 @@ amber_status check_beam(const amber_beam &b, int k, const int32_t *widths, int n
 }  // namespace amber
 
 struct amber_batch {
-    std::vector<amber::DGroup> dg;
-    std::vector<amber::BGroup> bg;
-    std::vector<int32_t> widths;
+    amber::LaunchSet set;
     void *d_mem = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -61,16 +40,7 @@ namespace {
 
 amber_status run_batch(amber_batch *b, hipStream_t stream)
 {
-    for (auto &g : b->dg) {
-        amber_status s = launch_dedisperse_jobs(g.plan, nullptr, g.d_jobs, (int)g.jobs.size(), g.n_blocks, g.lds, stream);
-        if (s != AMBER_OK) return s;
-    }
-    for (auto &g : b->bg) {
-        amber_status s = launch_integrate_snr_jobs(g.plan, g.tiles, nullptr, g.d_jobs, (int)g.jobs.size(), g.n_rows,
-                                                   b->widths.data(), (int)b->widths.size(), stream);
-        if (s != AMBER_OK) return s;
-    }
-    return AMBER_OK;
+    return b->set.launch(b->d_mem, stream);
 }
 
 void release(amber_batch *b)
@@ -99,10 +69,7 @@ amber_status amber_batch_create(const amber_beam *beams, int32_t n_beams, const 
         if (s != AMBER_OK) return s;
     }
     auto b = new amber_batch();
-    b->widths.assign(widths, widths + n_widths);
     // group beams by identical launch shapes
-    std::map<std::tuple<int, int, int, int, int>, size_t> dkey;
-    std::map<std::vector<int>, size_t> bkey;
     for (int k = 0; k < n_beams; ++k) {
         const amber_beam &bm = beams[k];
         amber_tiles t;
@@ -116,70 +83,23 @@ amber_status amber_batch_create(const amber_beam *beams, int32_t n_beams, const 
             delete b;
             return s;
         }
-        const auto dk = std::make_tuple(dp.tpd, dp.spt, dp.dpb, dp.cu, 0);
-        auto it = dkey.find(dk);
-        if (it == dkey.end()) {
-            it = dkey.emplace(dk, b->dg.size()).first;
-            b->dg.emplace_back();
-            b->dg.back().plan = dp;
-        }
-        DGroup &g = b->dg[it->second];
-        DedispJob j = make_dedisp_job(dp, bm.d_delays, bm.info.n_dm, bm.info.n_chan, bm.d_in, bm.in_stride, bm.d_dd,
-                                      bm.dd_stride, bm.n_out);
-        j.block_start = (int)g.n_blocks;
-        g.n_blocks += (int64_t)j.tiles_t * j.tiles_dm;
-        g.plan.maxi = std::max(g.plan.maxi, dp.maxi);  // the kernel stages up to maxi items per work-item
-        g.lds = std::max(g.lds, dp.lds_bytes);
-        g.jobs.push_back(j);
-
-        std::vector<int> bk = {t.snr_threads};
-        for (int w = 0; w < n_widths; ++w) bk.push_back(t.boxcar_step[w]);
-        auto bt = bkey.find(bk);
-        if (bt == bkey.end()) {
-            bt = bkey.emplace(bk, b->bg.size()).first;
-            b->bg.emplace_back();
-            b->bg.back().plan = bp;
-            b->bg.back().tiles = t;
-        }
-        BGroup &h = b->bg[bt->second];
-        BoxJob bj = make_box_job(bm.d_dd, bm.info.n_dm, bm.dd_stride, bm.n_out, bm.d_snr, bm.d_peak_t);
-        bj.row_start = (int)h.n_rows;
-        h.n_rows += bm.info.n_dm;
-        h.plan.maxw = std::max(h.plan.maxw, bp.maxw);
-        h.plan.lds_bytes = std::max(h.plan.lds_bytes, bp.lds_bytes);
-        h.jobs.push_back(bj);
+        b->set.add_dedisperse(dp, make_dedisp_job(dp, bm.d_delays, bm.info.n_dm, bm.info.n_chan, bm.d_in,
+                                                  bm.in_stride, bm.d_dd, bm.dd_stride, bm.n_out));
+        b->set.add_integrate_snr(bp, t, widths, n_widths,
+                                 make_box_job(bm.d_dd, bm.info.n_dm, bm.dd_stride, bm.n_out, bm.d_snr, bm.d_peak_t));
     }
-    for (auto &g : b->dg)
-        if (g.plan.maxi > 4 || (g.plan.spt >= 16 && g.plan.maxi > 3) || (g.plan.spt >= 32 && g.plan.maxi > 2)) {
-            delete b;
-            return fail(AMBER_E_CONFIG, "beams sharing tiles need more staging items than one kernel holds");
-        }
     // one device allocation for every job table
-    size_t bytes = 0;
-    for (auto &g : b->dg) bytes += g.jobs.size() * sizeof(DedispJob);
-    for (auto &g : b->bg) bytes += g.jobs.size() * sizeof(BoxJob);
+    const size_t bytes = b->set.table_bytes();
+    std::vector<char> host(bytes);
+    b->set.write_tables(host.data());
     if (hipMalloc(&b->d_mem, bytes) != hipSuccess) {
         delete b;
         return fail(AMBER_E_NOMEM, "cannot allocate %zu bytes of job tables", bytes);
     }
-    char *p = static_cast<char *>(b->d_mem);
-    for (auto &g : b->dg) {
-        g.d_jobs = reinterpret_cast<DedispJob *>(p);
-        if (hipMemcpy(p, g.jobs.data(), g.jobs.size() * sizeof(DedispJob), hipMemcpyHostToDevice) != hipSuccess) {
-            release(b);
-            delete b;
-            return fail(AMBER_E_DEVICE, "copying job tables failed");
-        }
-        p += g.jobs.size() * sizeof(DedispJob);
-    }
-    for (auto &g : b->bg) {
-        g.d_jobs = reinterpret_cast<BoxJob *>(p);
-        if (hipMemcpy(p, g.jobs.data(), g.jobs.size() * sizeof(BoxJob), hipMemcpyHostToDevice) != hipSuccess) {
-            release(b);
-            delete b;
-            return fail(AMBER_E_DEVICE, "copying job tables failed");
-        }
-        p += g.jobs.size() * sizeof(BoxJob);
+    if (hipMemcpy(b->d_mem, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        release(b);
+        delete b;
+        return fail(AMBER_E_DEVICE, "copying job tables failed");
     }
     *out = b;
     return AMBER_OK;
@@ -228,8 +148,8 @@ amber_status amber_batch_launches(const amber_batch *b, int32_t *n_dedisperse, i
 {
     clear_error();
     if (!b) return fail(AMBER_E_ARG, "batch is NULL");
-    if (n_dedisperse) *n_dedisperse = (int32_t)b->dg.size();
-    if (n_snr) *n_snr = (int32_t)b->bg.size();
+    if (n_dedisperse) *n_dedisperse = b->set.n_dedisperse();
+    if (n_snr) *n_snr = b->set.n_snr();
     return AMBER_OK;
 }
 

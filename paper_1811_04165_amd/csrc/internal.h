@@ -5,6 +5,7 @@
 
 #include <cstdarg>
 #include <cstdint>
+#include <vector>
 
 #include "amber.h"
 
@@ -83,6 +84,42 @@ BoxJob make_box_job(const int32_t *d_dd, int n_dm, int64_t dd_stride, int64_t n_
 amber_status launch_integrate_snr_jobs(const BoxcarPlan &p, const amber_tiles &t, const BoxJob *single,
                                        const BoxJob *d_jobs, int n_jobs, int64_t n_rows, const int32_t *widths,
                                        int n_widths, hipStream_t stream);
+
+// Jobs of several beams grouped into as few launches as their launch shapes
+// allow.  Dedispersion jobs with the same tile genes share a launch (the
+// group takes the largest LDS window and staging depth of its members; both
+// stay within the kernel's limits because members share samples_per_thread);
+// boxcar/S/N jobs share a launch when their S/N tiles and widths agree.  The
+// job tables of all groups are laid out in one buffer: write_tables() fills
+// its host image, launch() takes its device copy.
+class LaunchSet {
+public:
+    void add_dedisperse(const DedispPlan &p, DedispJob j);
+    void add_integrate_snr(const BoxcarPlan &p, const amber_tiles &t, const int32_t *widths, int n_widths, BoxJob j);
+    size_t table_bytes() const;
+    void write_tables(void *host) const;
+    amber_status launch(const void *d_tables, hipStream_t stream) const;
+    int n_dedisperse() const { return (int)d_.size(); }
+    int n_snr() const { return (int)b_.size(); }
+    bool empty() const { return d_.empty() && b_.empty(); }
+    void clear();
+
+private:
+    struct DGroup {
+        DedispPlan plan;
+        int64_t lds = 0, n_blocks = 0;
+        std::vector<DedispJob> jobs;
+    };
+    struct BGroup {
+        BoxcarPlan plan;
+        amber_tiles tiles;
+        std::vector<int32_t> widths;
+        int64_t n_rows = 0;
+        std::vector<BoxJob> jobs;
+    };
+    std::vector<DGroup> d_;
+    std::vector<BGroup> b_;
+};
 
 // Launchers (device translation units).
 amber_status launch_dedisperse(const DedispPlan &p, const int32_t *d_delays, int n_dm, int n_chan,

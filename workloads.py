@@ -166,3 +166,39 @@ def tiny(n_chan: int, n_dm: int, n_out: int, seed: int, max_delay: int = 16):
     stride = n_in + int(rng.integers(0, 5))
     x = rng.integers(0, 256, size=(n_chan, stride)).astype(np.uint8)
     return delays, x, n_in
+
+
+# --- streaming ---------------------------------------------------------------
+
+STREAM_CHUNK = 6104          # samples per chunk: 0.5 s at 81.92 us (whole samples)
+
+
+def stream_geometries(n_beams: int = 40) -> List[Geometry]:
+    """Beams of the streaming workload, alternating 768 channels / 1024 DM
+    trials and 1536 channels / 2048 DM trials, DM step 0.5 from 0 (so the
+    largest delays are about 5.8k and 11.6k samples)."""
+    out = []
+    for b in range(n_beams):
+        if b % 2 == 0:
+            out.append(Geometry(n_chan=768, n_dm=1024, dm_first=0.0, dm_step=0.5))
+        else:
+            out.append(Geometry(n_chan=1536, n_dm=2048, dm_first=0.0, dm_step=0.5))
+    return out
+
+
+def poisson_arrivals(n_beams: int, rate_per_beam: float, duration_s: float, seed: int = 5):
+    """Arrival times of chunks: each beam an independent Poisson process of
+    `rate_per_beam` chunks/s over [0, duration_s), its chunks in order.
+    Returns a list of (time_s, beam, seq) sorted by time."""
+    rng = np.random.default_rng(seed)
+    ev = []
+    for b in range(n_beams):
+        t, seq = 0.0, 0
+        while True:
+            t += float(rng.exponential(1.0 / rate_per_beam))
+            if t >= duration_s:
+                break
+            ev.append((t, b, seq))
+            seq += 1
+    ev.sort()
+    return ev
