@@ -27,9 +27,11 @@ if ROOT not in sys.path:
 
 # MI355X published / derived peaks
 HBM_PEAK_GBS = 8000.0
-# 256 CUs x 64 VALU lanes x 2.4 GHz = 39.3 T lane-ops/s; the dedispersion sums
-# live in 16-bit lanes, two per 32-bit VALU op -> 78.6 T sample-additions/s.
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 * 2 / 1e12
+# 32-bit VALU: 256 CUs x 128 lane-ops/clk x 2.4 GHz = 78.6 T lane-ops/s (the
+# published FP32 vector rate, 157.3 TFLOP/s, counts an FMA as two); the
+# dedispersion sums live in 16-bit halves, two per 32-bit add
+# -> 157.3 T sample-additions/s.
+ALU_PEAK_TOPS = 256 * 128 * 2.4e9 * 2 / 1e12
 
 METRIC = "DM-trial·samples/s per GPU + % HBM roofline; GA tune time; p99 chunk latency"
 UNIT = "DM-trial·samples/s"

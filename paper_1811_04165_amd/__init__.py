@@ -394,6 +394,8 @@ class Server:
         return bid.value
 
     def submit(self, beam: int, chunk: np.ndarray, tag: int = 0) -> None:
+        if not 0 <= beam < len(self._beams):  # the library rejects the id
+            check(load().amber_server_submit(self._h, int(beam), chunk.ctypes.data, chunk.strides[0], int(tag)))
         n_chan, L, _, _ = self._beams[beam]
         if chunk.dtype != np.uint8 or chunk.ndim != 2 or chunk.shape[0] != n_chan or chunk.shape[1] < L \
                 or chunk.strides[1] != 1:
