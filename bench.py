@@ -14,6 +14,7 @@ launches, and the CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -79,6 +80,7 @@ def time_configs(search, x, configs, reps: int):
     import torch
     import paper_1811_04165_amd as amber
     times = [[] for _ in configs]
+    gc.collect()
     for _ in range(reps):
         for k, t in enumerate(configs):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -195,6 +197,7 @@ def batched_report(n_beams: int, steps: int, warmup: int):
             for _ in range(warmup):
                 fn()
             s.synchronize()
+            gc.collect()
             a, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             t0 = time.perf_counter()
             a.record(s)
@@ -204,6 +207,8 @@ def batched_report(n_beams: int, steps: int, warmup: int):
             s.synchronize()
             wall = time.perf_counter() - t0
         return a.elapsed_time(b_) / 1e3 / steps, wall / steps
+
+    gc.disable()  # no collection pauses inside the timed loops
 
     print("[bench] timing", file=sys.stderr, flush=True)
     t_plain, w_plain = timed(per_beam)
@@ -220,6 +225,7 @@ def batched_report(n_beams: int, steps: int, warmup: int):
         sn = b["snr"].cpu().numpy()
         found += int(sn[list(widths).index(p.width), p.dm_index] > 8.0)
     samples = sum(b["info"].n_dm * b["n_out"] for b in beams)
+    gc.enable()
     n_launch = batch.launches()
     batch.close()
     return {"metric": "DM-trial·samples/s per GPU", "unit": UNIT, "value": samples / t_graph,
@@ -282,6 +288,7 @@ def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitter
                 err.append(e)
 
         lag = [0.0]
+        submit_s = []
         t0 = amber.server_clock() + 0.05
 
         def submit(part):
@@ -293,8 +300,12 @@ def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitter
                     lag[0] = max(lag[0], now - t)
                 g = geoms[b]
                 off = ((seq + 3 * b) % n_blk) * L
+                a = amber.server_clock()
                 srv.submit(b, blocks[(g.n_chan, g.n_dm)][:, off:off + L], tag=seq)
+                submit_s.append(amber.server_clock() - a)
 
+        gc.collect()
+        gc.disable()  # a collection would stall the submitting threads
         col = threading.Thread(target=collect, args=(len(arrivals),))
         col.start()
         subs = [threading.Thread(target=submit, args=([a for a in arrivals if a[1] % submitters == i],))
@@ -304,6 +315,7 @@ def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitter
         for th in subs:
             th.join()
         col.join()
+        gc.enable()
         st = srv.stats()
         srv.close()
         if err:
@@ -315,10 +327,17 @@ def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitter
         first = t0 + min(arr[(r["beam"], r["seq"])] for r in meas)
         last = max(r["t_done"] for r in meas)
         bs = np.array([r["batch_size"] for r in meas])
+        wait = np.array([r["t_start"] - r["t_submit"] for r in meas])
+        run = np.array([r["t_done"] - r["t_start"] for r in meas])
+
+        def pct(v):
+            return {"p50": 1e3 * float(np.percentile(v, 50)), "p99": 1e3 * float(np.percentile(v, 99))}
         return {"offered_chunks_per_s": rate, "chunks": len(meas), "value": work / (last - first),
                 "chunks_per_s": len(meas) / (last - first),
                 "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99)),
                                "max": 1e3 * float(lat.max()), "mean": 1e3 * float(lat.mean())},
+                "breakdown_ms": {"submit_call": pct(np.array(submit_s)), "queued": pct(wait),
+                                 "launch_to_done": pct(run)},
                 "batch_size": {"mean": float(bs.mean()), "max": int(bs.max())},
                 "launch_groups": st["batches"], "max_submit_lag_ms": 1e3 * lag[0],
                 "memory_peak_bytes": st["memory_peak"]}
@@ -405,7 +424,18 @@ def main() -> int:
     n_launch = args.steps
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(n_launch)]
+    # torch creates the HIP events on their first record: do that before the
+    # timed region so that event creation never stalls the launches
+    for a, b, c in ev:
+        a.record()
+        b.record()
+        c.record()
     print("[bench] timed %d steps" % args.steps, file=sys.stderr, flush=True)
+    # a garbage collection over torch's heap can stall the launching thread for
+    # tens of milliseconds while the GPU idles: none inside the timed region
+    gc.collect()
+    gc.disable()
+    host_t = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -415,8 +445,13 @@ def main() -> int:
         b.record()
         amber.integrate_snr(search.dd, search.n_out, search.widths, tiles, out=(search.snr, search.peak))
         c.record()
+        host_t.append(time.perf_counter())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gc.enable()
+    gaps = [1e3 * (t2 - t1) for t1, t2 in zip([t0] + host_t, host_t)]
+    print("[bench] host ms per launch pair: median %.3f max %.3f" % (statistics.median(gaps), max(gaps)),
+          file=sys.stderr, flush=True)
     k1_ms = [a.elapsed_time(b) for a, b, _ in ev]
     k23_ms = [b.elapsed_time(c) for _, b, c in ev]
 
@@ -449,7 +484,10 @@ def main() -> int:
                      "avg_launch_ms": k1_avg, "ops_per_launch": ops},
         "kernels": {
             "dedisperse_ms": k1_avg,
+            "dedisperse_median_ms": statistics.median(k1_ms),
             "integrate_snr_ms": k23_avg,
+            "integrate_snr_median_ms": statistics.median(k23_ms),
+            "integrate_snr_max_ms": max(k23_ms),
             "integrate_snr_hbm_frac": k23_bytes / (k23_avg / 1e3) / 1e9 / HBM_PEAK_GBS,
         },
         "hbm_frac_path": path_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS,

@@ -7,6 +7,10 @@
 // overlap by H >= max width samples so every output of a chunk finds its whole
 // window inside it; all widths are served from the same prefix array.
 //
+// The prefix array lives in LDS with one pad dword after every 64 (element i
+// at qix(i) = i + i / 64), so that lanes writing 16 consecutive elements each
+// and lanes reading at a stride of 1, 2, 4 or 8 elements hit distinct banks.
+//
 // S/N statistics per (width, row): the maximum with its first index, packed
 // as one int64 key (value << 32 | ~t) so that a plain max keeps the earliest
 // peak, and FP64 sums of (x - r) and (x - r)^2 about an integer reference r
@@ -19,6 +23,8 @@
 
 namespace amber {
 namespace {
+
+__device__ __forceinline__ int qix(int i) { return i + (i >> 6); }
 
 struct WidthSet {
     int32_t w[AMBER_MAX_WIDTHS];
@@ -108,7 +114,8 @@ __device__ __forceinline__ void block_reduce(Stat (&st)[NW], int n_w, Stat *scra
 }
 
 // Loads samples [cs, cs + chunk) of one row (zero past n_out) and writes the
-// exclusive prefix Q[0..chunk] to LDS.  16 contiguous samples per thread.
+// exclusive prefix Q[0..chunk] to LDS (padded layout).  16 contiguous samples
+// per thread.
 __device__ __forceinline__ void load_prefix(const int32_t *__restrict__ row, int64_t cs, int64_t n_out, bool vec_ok,
                                             uint32_t *Q, uint32_t *wave_tot)
 {
@@ -148,9 +155,8 @@ __device__ __forceinline__ void load_prefix(const int32_t *__restrict__ row, int
     }
     __syncthreads();
     const uint32_t excl = incl - v[15] + wave_tot[wave];
-    uint32_t *q = Q + tid * 16 + 1;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) q[e] = v[e] + excl;
+    for (int e = 0; e < 16; ++e) Q[qix(tid * 16 + 1 + e)] = v[e] + excl;
     if (tid == 0) Q[0] = 0u;
     __syncthreads();
 }
@@ -164,10 +170,11 @@ __device__ __forceinline__ void width_stats(const uint32_t *Q, int w, int outs, 
     for (int g = threadIdx.x; g * S < outs; g += blockDim.x) {
         const int u = g * S;
         uint32_t a[S], b[S];
+        const int pu = qix(u);  // u .. u + S - 1 share one 64-element block
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            a[s] = Q[u + s];
-            b[s] = Q[u + s + w];
+            a[s] = Q[pu + s];
+            b[s] = Q[qix(u + s + w)];
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -254,7 +261,7 @@ __global__ __launch_bounds__(1024) void integrate_kernel(const int32_t *__restri
         int32_t *__restrict__ out = box + ((size_t)k * n_dm + i) * box_stride;
         for (int u = threadIdx.x; u < outs; u += blockDim.x) {
             const int64_t t = cs + u;
-            if (t < n_valid) out[t] = (int32_t)(Q[u + w] - Q[u]);
+            if (t < n_valid) out[t] = (int32_t)(Q[qix(u + w)] - Q[qix(u)]);
         }
     }
 }
