@@ -399,8 +399,9 @@ amber_status amber_server_admit(const amber_pending_chunk *pending, int32_t n_pe
 
 amber_status amber_server_create(const amber_server_config *config, amber_server **server);
 
-/* Registers a beam (allocates its delay table and overlap buffers; refused
- * with AMBER_E_NOMEM if they do not fit the free HBM). */
+/* Registers a beam: allocates its delay table and overlap buffers (refused
+ * with AMBER_E_NOMEM if they do not fit the budget or the free HBM) and pinned
+ * host staging for 4 queued chunks (more is pinned on demand). */
 amber_status amber_server_add_beam(amber_server *server, const amber_stream_beam *beam, const int32_t *widths,
                                    int32_t n_widths, int32_t *beam_id);
 

@@ -134,6 +134,12 @@ amber_status launch_snr(const BoxcarPlan &p, const amber_tiles &t, const int32_t
                         int64_t box_stride, int64_t n_out, const int32_t *widths, int n_widths,
                         float *d_snr, int32_t *d_peak, hipStream_t stream);
 
+// Window of a streamed chunk: row c of d_cur = d_prev[c][L, L + D) followed
+// by d_stage[c][0, L) (rows of d_cur / d_prev are `stride` bytes apart, d_stage
+// is contiguous).
+amber_status launch_assemble(uint8_t *d_cur, const uint8_t *d_prev, const uint8_t *d_stage, int n_chan,
+                             int64_t stride, int64_t L, int64_t D, hipStream_t stream);
+
 amber_status launch_integrate_snr(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_dd, int n_dm,
                                   int64_t dd_stride, int64_t n_out, const int32_t *widths, int n_widths,
                                   float *d_snr, int32_t *d_peak, hipStream_t stream);

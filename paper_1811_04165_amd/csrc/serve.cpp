@@ -6,13 +6,13 @@
 // waits for a group to fill) and spreads the groups over several streams so
 // that one group's copies overlap another's kernels.
 //
-// Each beam keeps its last max_delay input samples in HBM.  Two input buffers
-// of max_delay + L columns are used alternately: chunk k lands in columns
-// [max_delay, max_delay + L) of buffer k % 2 and the tail of chunk k - 1 is
-// copied device-to-device from columns [L, L + max_delay) of the other buffer
-// into columns [0, max_delay), so column j holds absolute time
-// k*L - max_delay + j and a plain dedispersion of L outputs from column 0
-// covers the chunk.  The outputs of negative absolute time (the first
+// Each beam keeps its last max_delay input samples in HBM.  Two input windows
+// of max_delay + L columns are used alternately: chunk k is copied (one
+// contiguous host-to-device copy) into the device staging area of its block,
+// and one assembly pass writes window k % 2 as columns [L, L + max_delay) of
+// the other window followed by the staged chunk, so column j holds absolute
+// time k*L - max_delay + j and a plain dedispersion of L outputs from column
+// 0 covers the chunk.  The outputs of negative absolute time (the first
 // max_delay samples of the stream) are computed from zeros and dropped.
 #include <algorithm>
 #include <chrono>
@@ -37,6 +37,7 @@ constexpr int kMaxInflight = 4096;
 constexpr int kMaxBatch = 1024;
 constexpr int kMaxSlots = 32;       // launch groups on the device at once
 constexpr int kScanLimit = 4096;    // pending chunks looked at per admission
+constexpr int kStagingPerBeam = 4;  // pinned chunk buffers allocated with a beam
 
 double clock_s()
 {
@@ -136,6 +137,7 @@ struct SBeam {
     int64_t dd_stride = 0;        // int32 per dedispersed row of a chunk block
     int64_t res_off = 0;          // byte offset of the S/N table in a chunk block
     int64_t res_bytes = 0;        // S/N table + peak table
+    int64_t stage_off = 0;        // byte offset of the staged chunk in a chunk block
     int64_t block_bytes = 0;      // device bytes one chunk holds while it runs
     int64_t persistent_bytes = 0; // delay table + both input buffers
     int64_t submitted = 0;
@@ -155,7 +157,7 @@ struct Request {
 
 struct Active {
     Request rq;
-    void *block = nullptr;  // device: dd [n_dm][dd_stride], S/N [n_widths][n_dm], peak [n_widths][n_dm]
+    void *block = nullptr;  // device: dd [n_dm][dd_stride], S/N and peak [n_widths][n_dm], chunk [n_chan][L]
     void *h_res = nullptr;  // pinned copy of S/N and peak
     int64_t t_first = 0, n_out = 0;
     int has_snr = 0;
@@ -267,13 +269,12 @@ amber_status enqueue(amber_server *s, Flight &f, hipStream_t stream)
         SBeam &b = *a.rq.b;
         const int cur = (int)(a.rq.seq & 1);
         const int n_chan = b.info.n_chan;
-        AMBER_HIP(hipMemcpy2DAsync(b.d_in[cur] + b.D, (size_t)b.stride, a.rq.host, (size_t)b.L, (size_t)b.L,
-                                   (size_t)n_chan, hipMemcpyHostToDevice, stream),
-                  "chunk copy");
-        if (a.rq.seq > 0 && b.D > 0)
-            AMBER_HIP(hipMemcpy2DAsync(b.d_in[cur], (size_t)b.stride, b.d_in[cur ^ 1] + b.L, (size_t)b.stride,
-                                       (size_t)b.D, (size_t)n_chan, hipMemcpyDeviceToDevice, stream),
-                      "overlap copy");
+        uint8_t *stage = static_cast<uint8_t *>(a.block) + b.stage_off;
+        AMBER_HIP(hipMemcpyAsync(stage, a.rq.host, b.host_bytes(), hipMemcpyHostToDevice, stream), "chunk copy");
+        // window k % 2 = tail of the other window + this chunk (the other
+        // window is still all zeros for chunk 0)
+        amber_status as = launch_assemble(b.d_in[cur], b.d_in[cur ^ 1], stage, n_chan, b.stride, b.L, b.D, stream);
+        if (as != AMBER_OK) return as;
         if (!a.has_snr) continue;
         int32_t *dd = static_cast<int32_t *>(a.block);
         float *snr = reinterpret_cast<float *>(static_cast<char *>(a.block) + b.res_off);
@@ -585,7 +586,8 @@ amber_status amber_server_add_beam(amber_server *s, const amber_stream_beam *bm,
     b->dd_stride = round_up(b->L, 64);
     b->res_off = round_up((int64_t)b->info.n_dm * b->dd_stride * 4, 256);
     b->res_bytes = (int64_t)n_widths * b->info.n_dm * 8;
-    b->block_bytes = round_up(b->res_off + b->res_bytes, 256);
+    b->stage_off = round_up(b->res_off + b->res_bytes, 256);
+    b->block_bytes = round_up(b->stage_off + (int64_t)b->info.n_chan * b->L, 256);
     const int64_t table_bytes = round_up((int64_t)delays.size() * 4, 256);
     const int64_t in_bytes = (int64_t)b->info.n_chan * b->stride;
     b->persistent_bytes = table_bytes + 2 * in_bytes;
@@ -617,6 +619,13 @@ amber_status amber_server_add_beam(amber_server *s, const amber_stream_beam *bm,
                                         : hip_fail(e, "beam set-up");
     }
     s->st.memory_peak = std::max(s->st.memory_peak, s->st.memory_in_use);
+    // pinned staging for a few queued chunks of this beam, so that submissions
+    // do not pin memory while a backlog is short (the pool grows past this)
+    for (int k = 0; k < kStagingPerBeam; ++k) {
+        void *h = nullptr;
+        if (hipHostMalloc(&h, b->host_bytes(), hipHostMallocDefault) != hipSuccess) break;
+        s->pinned.put(h, b->host_bytes());
+    }
     *beam_id = (int32_t)s->beams.size();
     s->beams.push_back(std::move(b));
     return AMBER_OK;

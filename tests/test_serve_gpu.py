@@ -131,12 +131,15 @@ def test_memory_budget_admits_one_chunk_at_a_time(amber, streams):
     with amber.Server(max_inflight=16, max_batch=8, n_streams=2) as probe:
         _add_beams(amber, probe, streams)
         resident = probe.stats()["memory_in_use"]
-    # chunk blocks: int32 dd [n_dm][round64(L)] + S/N and peak tables, 256-byte aligned
+    # chunk blocks: int32 dd [n_dm][round64(L)], the S/N and peak tables and
+    # the staged chunk [n_chan][L], each part 256-byte aligned
+    def r256(n):
+        return (n + 255) // 256 * 256
     blocks = []
     for g, *_ in streams:
-        dd = g.n_dm * ((L + 63) // 64 * 64) * 4
-        dd = (dd + 255) // 256 * 256
-        blocks.append((dd + len(WIDTHS) * g.n_dm * 8 + 255) // 256 * 256)
+        res_off = r256(g.n_dm * ((L + 63) // 64 * 64) * 4)
+        stage_off = r256(res_off + len(WIDTHS) * g.n_dm * 8)
+        blocks.append(r256(stage_off + g.n_chan * L))
     budget = resident + max(blocks)
     with amber.Server(max_inflight=16, max_batch=8, n_streams=2, memory_budget=budget) as srv:
         _add_beams(amber, srv, streams)
