@@ -13,6 +13,7 @@ numpy in / numpy out functions:
 * ``dedisperse``   -- brute-force one-step dedispersion (Section 5 names the
   one-step scheme; Section 2 the dedispersion kernel).
 * ``boxcar``       -- sliding boxcar "smoothing" of each series (Section 2).
+* ``downsample``   -- decimating downsampling by a factor (Section 2, Table 2).
 * ``snr``          -- (max - mean) / population std per series (Section 2's
   S/N kernel; the paper prints no formula).
 * ``search``       -- the four steps in order, for every width.
@@ -60,8 +61,11 @@ def _load():
                                               ctypes.c_int64, ctypes.c_int64, i32p, ctypes.c_int]
             lib.oracle_boxcar.argtypes = [i32p, ctypes.c_int, ctypes.c_int64, ctypes.c_int, i64p,
                                           ctypes.c_int]
+            lib.oracle_downsample.argtypes = [i32p, ctypes.c_int, ctypes.c_int64, ctypes.c_int, i64p,
+                                              ctypes.c_int]
             lib.oracle_snr.argtypes = [i64p, ctypes.c_int, ctypes.c_int64, f64p, i32p, ctypes.c_int]
-            for f in (lib.oracle_delay_table, lib.oracle_dedisperse, lib.oracle_boxcar, lib.oracle_snr):
+            for f in (lib.oracle_delay_table, lib.oracle_dedisperse, lib.oracle_boxcar, lib.oracle_downsample,
+                      lib.oracle_snr):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -109,6 +113,18 @@ def boxcar(dd: np.ndarray, w: int, threads: int = 0) -> np.ndarray:
                                int(threads))
     if rc != 0:
         raise ValueError("oracle_boxcar: width outside [1, n_out]")
+    return out
+
+
+def downsample(dd: np.ndarray, f: int, threads: int = 0) -> np.ndarray:
+    """y[i][j] = sum_{k<f} dd[i][j*f + k] for j < n_out // f (int64): decimation by f."""
+    a = np.ascontiguousarray(dd, dtype=np.int32)
+    n_dm, n_out = a.shape
+    out = np.empty((n_dm, n_out // int(f) if f >= 1 else 0), dtype=np.int64)
+    rc = _load().oracle_downsample(_ptr(a, ctypes.c_int32), n_dm, n_out, int(f), _ptr(out, ctypes.c_int64),
+                                   int(threads))
+    if rc != 0:
+        raise ValueError("oracle_downsample: factor outside [1, n_out]")
     return out
 
 

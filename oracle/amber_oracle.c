@@ -147,6 +147,36 @@ int oracle_boxcar(const int32_t *dd, int n_dm, int64_t n_out, int w,
 }
 
 /*
+ * Decimating downsampling (the downsampling step of Section 2; Table 2 gives
+ * the factors and NRSAMPLES = SAMPLES / DOWNSAMPLING):
+ *
+ *     y[i][j] = sum_{k<f} dd[i][j*f + k]     for j < floor(n_out / f)
+ *
+ * rows of dd have stride n_out; rows of y have stride floor(n_out / f) and
+ * are int64.  Samples past the last whole bin are dropped.  Returns -1 unless
+ * 1 <= f <= n_out.
+ */
+int oracle_downsample(const int32_t *dd, int n_dm, int64_t n_out, int f,
+                      int64_t *y, int n_threads)
+{
+    if (n_dm <= 0 || f < 1 || f > n_out)
+        return -1;
+    int64_t nb = n_out / f;
+    int nt = oracle_threads(n_threads);
+    #pragma omp parallel for num_threads(nt) schedule(static)
+    for (int i = 0; i < n_dm; ++i) {
+        const int32_t *row = dd + (size_t)i * n_out;
+        for (int64_t j = 0; j < nb; ++j) {
+            int64_t s = 0;
+            for (int k = 0; k < f; ++k)
+                s += row[j * f + k];
+            y[(size_t)i * nb + j] = s;
+        }
+    }
+    return 0;
+}
+
+/*
  * Signal-to-noise of the peak of each series (the S/N step of Section 2):
  *
  *     mu    = (1/N) sum x[t]

@@ -194,6 +194,41 @@ def test_boxcar_identity_doubling_and_convolve():
         oracle.boxcar(dd, 301)
 
 
+def test_downsample_pins():
+    """Decimation by f (Table 2: NRSAMPLES = SAMPLES / DOWNSAMPLING) is the
+    sliding boxcar of width f read at t = j f; decimating by a then by b is
+    decimating by a b; whole bins conserve the sum; the remainder is dropped."""
+    rng = np.random.default_rng(22)
+    dd = rng.integers(0, 400000, size=(4, 1000)).astype(np.int32)
+    assert np.array_equal(oracle.downsample(dd, 1), dd.astype(np.int64))
+    for f in (2, 3, 7, 10, 64, 333, 1000):
+        y = oracle.downsample(dd, f)
+        nb = 1000 // f
+        assert y.shape == (4, nb)
+        assert np.array_equal(y, oracle.boxcar(dd, f)[:, ::f][:, :nb])
+        assert np.array_equal(y.sum(axis=1), dd[:, :nb * f].astype(np.int64).sum(axis=1))
+    for a, b in ((2, 5), (10, 3), (4, 4)):
+        inner = oracle.downsample(dd, a)
+        assert np.array_equal(oracle.downsample(inner.astype(np.int32), b), oracle.downsample(dd, a * b))
+    for bad in (0, 1001):
+        with pytest.raises(ValueError):
+            oracle.downsample(dd, bad)
+
+
+def test_downsample_snr_closed_form():
+    """A constant series with m equal spikes in separate bins: after
+    decimation by f the bins form a constant series with m raised bins, whose
+    S/N is sqrt((N - m) / m) for N bins (as for the sliding case)."""
+    n_out, f = 8000, 10
+    dd = np.full((1, n_out), 7, dtype=np.int32)
+    for t in (95, 4321):
+        dd[0, t] += 1000
+    s, p = oracle.snr(oracle.downsample(dd, f))
+    nb = n_out // f
+    assert s[0] == pytest.approx(np.sqrt((nb - 2) / 2), rel=1e-12)
+    assert p[0] == 9       # first raised bin: 95 // 10
+
+
 # --- S/N ----------------------------------------------------------------------------
 
 def test_snr_matches_numpy_routine():
