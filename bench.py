@@ -358,6 +358,55 @@ def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitter
                       "seconds": seconds, "warmup_s": warmup_s, "submit_threads": submitters, "by_rate": out}}
 
 
+def downsample_report(steps: int, warmup: int):
+    """Decimating downsampling + S/N (the paper's smoothing definition) on the
+    1536-channel beam: the ten series of the factor ladder in one fused launch,
+    beside the sliding boxcar widths on the same dedispersed data."""
+    import torch
+    import paper_1811_04165_amd as amber
+    import workloads
+    wl = workloads.beam()
+    g = wl.geom
+    search = amber.Search(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step, wl.n_out, wl.widths)
+    x_host, n_in = workloads.make_input(wl, search.delays_host, search.info.max_delay)
+    x = torch.from_numpy(x_host).cuda()
+    search.run(x)
+    factors = workloads.DOWNSAMPLING_FACTORS
+    s = torch.empty((len(factors), g.n_dm), dtype=torch.float32, device="cuda")
+    p = torch.empty((len(factors), g.n_dm), dtype=torch.int32, device="cuda")
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        b.record()
+        torch.cuda.synchronize()
+        gc.collect()
+        gc.disable()
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        gc.enable()
+        return a.elapsed_time(b) / 1e3 / steps
+
+    t_ds = timed(lambda: amber.downsample_snr(search.dd, wl.n_out, factors, out=(s, p)))
+    t_box = timed(lambda: amber.integrate_snr(search.dd, wl.n_out, wl.widths, out=(search.snr, search.peak)))
+    sn = s.cpu().numpy()
+    found = sum(1 for pu in wl.pulses if sn[:, pu.dm_index].max() > 8.0)
+    alg = 4 * g.n_dm * wl.n_out + 8 * len(factors) * g.n_dm
+    return {"metric": "downsample + S/N time", "unit": "s", "value": t_ds, "higher_is_better": False,
+            "downsample": {"workload": wl.name, "factors": list(factors), "steps": steps,
+                           "downsample_snr_ms": 1e3 * t_ds, "integrate_snr_ms": 1e3 * t_box,
+                           "widths": list(wl.widths),
+                           "roofline": {"bound": "hbm", "achieved": alg / t_ds / 1e9, "peak": HBM_PEAK_GBS,
+                                        "unit": "GB/s", "frac": alg / t_ds / 1e9 / HBM_PEAK_GBS,
+                                        "bytes_per_launch": alg},
+                           "pulses_with_snr_above_8": found}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,6 +428,9 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
     ap.add_argument("--serve-rates", type=str, default="400,1600", help="offered chunks/s, comma separated")
+    ap.add_argument("--downsample", action="store_true",
+                    help="instead of the single-beam step: decimating downsampling + S/N over the factor ladder "
+                         "on the dedispersed beam")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run a plain device-to-device copy of this many bytes 5 times (for scaling "
                          "hardware byte counters read under a profiler)")
@@ -401,6 +453,9 @@ def main() -> int:
         return 0
     if args.batched:
         print(json.dumps(batched_report(args.beams, args.steps, args.warmup)))
+        return 0
+    if args.downsample:
+        print(json.dumps(downsample_report(args.steps, args.warmup)))
         return 0
     if args.serve:
         rates = [float(r) for r in args.serve_rates.split(",") if r]

@@ -11,6 +11,8 @@
  *   amber_integrate     device: box_w[i][t] = sum_{k<w} dd[i][t+k]
  *   amber_snr           device: per (w, i) peak, first argmax, mean, std -> S/N
  *   amber_integrate_snr device: the previous two fused, box never stored
+ *   amber_downsample    device: decimating downsampling (sums of f samples)
+ *   amber_downsample_snr device: downsampling + S/N fused
  *   amber_tune          genetic-algorithm tile search (Section 3), fitness =
  *                       measured time of dedisperse + integrate + S/N
  *
@@ -188,6 +190,35 @@ amber_status amber_integrate_snr(const int32_t *d_dd, int32_t n_dm, int64_t dd_s
                                  const int32_t *widths, int32_t n_widths,
                                  float *d_snr, int32_t *d_peak_t,
                                  const amber_tiles *tiles, void *stream);
+
+/* ---- decimating downsampling (Section 2; Table 2 DOWNSAMPLING, NRSAMPLES) -- */
+
+/* The pipeline's downsampling step: for each factor f = factors[k],
+ *     y[k][i][j] = sum_{m<f} dd[i][j*f + m]      for j < n_out / f
+ * (integer division: samples past the last whole bin are dropped; Table 2
+ * gives NRSAMPLES = SAMPLES / DOWNSAMPLING and factors 10 ... 3200).  The same
+ * prefix-sum kernel as amber_integrate, read at multiples of f, exact in
+ * int32 while f * 255 * n_chan < 2^31.
+ * factors: host [n_factors], 1 <= f <= min(n_out, 4096), n_factors <= 16.
+ * d_y:     device int32 [n_factors][n_dm][y_stride], y_stride >= n_out / min f.
+ * tiles:   snr_threads and boxcar_step[k] (one per factor, as the paper has
+ *          one gene per downsampling factor) are used; NULL = defaults with
+ *          snr_threads raised until 16 * snr_threads >= 2 * round16(max f)
+ *          and boxcar_step 1 for every factor. */
+amber_status amber_downsample(const int32_t *d_dd, int32_t n_dm, int64_t dd_stride, int64_t n_out,
+                              const int32_t *factors, int32_t n_factors, int32_t *d_y, int64_t y_stride,
+                              const amber_tiles *tiles, void *stream);
+
+/* Downsampling followed by S/N (Section 2's S/N kernel on each downsampled
+ * series), fused: per (k, i) over the N = n_out / factors[k] values y_j,
+ *     snr[k][i] = (max y - mean) / std (population), or 0 when std == 0,
+ *     peak_t[k][i] = smallest j with y_j == max y   (in downsampled samples).
+ * Factor 1 is the S/N of the series itself.  FP64 moments as in amber_snr.
+ * d_snr: device float [n_factors][n_dm]; d_peak_t: int32 [n_factors][n_dm] or
+ * NULL.  Errors as amber_integrate_snr. */
+amber_status amber_downsample_snr(const int32_t *d_dd, int32_t n_dm, int64_t dd_stride, int64_t n_out,
+                                  const int32_t *factors, int32_t n_factors, float *d_snr, int32_t *d_peak_t,
+                                  const amber_tiles *tiles, void *stream);
 
 /* ---- tile search (Section 3: genetic algorithm; Section 2: brute force) ---- */
 

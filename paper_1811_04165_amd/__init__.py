@@ -12,6 +12,8 @@ Steps (see include/amber.h for the exact contracts):
     integrate      -> int32 [n_w, n_dm, n_out] sliding boxcars (valid prefix per width)
     snr            -> (float32 [n_w, n_dm], int32 [n_w, n_dm]) from boxcar series
     integrate_snr  -> the previous two fused
+    downsample     -> int32 [n_f, n_dm, n_out // f] decimated sums of f samples
+    downsample_snr -> S/N of each decimated series, fused
     Batch          -> beams of uneven sizes in shared launches / one HIP graph
     Server         -> streaming chunks with continuous batching
 """
@@ -28,7 +30,7 @@ from ._lib import (AMBER_E_TIMEOUT, AMBER_MAX_WIDTHS, FITNESS_FN, Beam, ChunkRes
 
 __all__ = ["AmberError", "DelayInfo", "Tiles", "TuneSpace", "TuneParams", "TuneResult", "default_space",
            "space_size", "tune_params", "search_tiles", "tune", "Batch", "default_tiles", "make_tiles", "delay_table", "dedisperse",
-           "integrate", "snr", "integrate_snr", "validate_tiles", "auto_tiles", "version", "Search", "Server",
+           "integrate", "snr", "integrate_snr", "downsample", "downsample_snr", "validate_tiles", "auto_tiles", "version", "Search", "Server",
            "chunk_span", "admit", "server_config", "server_clock"]
 
 load()  # fail loudly at import if the native library is missing
@@ -180,6 +182,35 @@ def integrate_snr(dd, n_out: int, widths: Sequence[int], tiles: Optional[Tiles] 
         s, p = out
     check(load().amber_integrate_snr(dd.data_ptr(), n_dm, dd.stride(0), int(n_out), wp, len(w), s.data_ptr(),
                                      p.data_ptr(), _tiles_ref(tiles), _stream_handle(stream)))
+    return s, p
+
+
+def downsample(dd, n_out: int, factors: Sequence[int], tiles: Optional[Tiles] = None, out=None, stream=None):
+    """Decimation: int32 [n_f, n_dm, max_j] with row k valid up to n_out // factors[k]."""
+    torch = _torch()
+    _check_dev(dd, torch.int32, "dd", 2)
+    f, fp = _widths_arr(factors)
+    n_dm = dd.shape[0]
+    if out is None:
+        out = torch.empty((len(f), n_dm, int(n_out) // int(f.min())), dtype=torch.int32, device=dd.device)
+    check(load().amber_downsample(dd.data_ptr(), n_dm, dd.stride(0), int(n_out), fp, len(f), out.data_ptr(),
+                                  out.stride(1), _tiles_ref(tiles), _stream_handle(stream)))
+    return out
+
+
+def downsample_snr(dd, n_out: int, factors: Sequence[int], tiles: Optional[Tiles] = None, stream=None, out=None):
+    """Decimation + S/N fused.  Returns (snr float32, peak int32), [n_f, n_dm] each; peaks in decimated samples."""
+    torch = _torch()
+    _check_dev(dd, torch.int32, "dd", 2)
+    f, fp = _widths_arr(factors)
+    n_dm = dd.shape[0]
+    if out is None:
+        s = torch.empty((len(f), n_dm), dtype=torch.float32, device=dd.device)
+        p = torch.empty((len(f), n_dm), dtype=torch.int32, device=dd.device)
+    else:
+        s, p = out
+    check(load().amber_downsample_snr(dd.data_ptr(), n_dm, dd.stride(0), int(n_out), fp, len(f), s.data_ptr(),
+                                      p.data_ptr(), _tiles_ref(tiles), _stream_handle(stream)))
     return s, p
 
 

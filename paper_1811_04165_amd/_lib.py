@@ -146,6 +146,12 @@ SIGNATURES = [
     ("amber_integrate_snr", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                            c_i32p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.POINTER(Tiles), ctypes.c_void_p]),
+    ("amber_downsample", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                        c_i32p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.POINTER(Tiles), ctypes.c_void_p]),
+    ("amber_downsample_snr", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                            c_i32p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(Tiles), ctypes.c_void_p]),
     ("amber_default_space", ctypes.c_int, [ctypes.POINTER(DelayInfo), c_i32p, ctypes.c_int32, ctypes.c_int64,
                                            ctypes.POINTER(TuneSpace)]),
     ("amber_space_size", ctypes.c_int, [ctypes.POINTER(TuneSpace), ctypes.POINTER(ctypes.c_int64)]),

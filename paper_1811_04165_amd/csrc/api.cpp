@@ -121,16 +121,16 @@ amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info,
 }
 
 amber_status plan_boxcar(const amber_tiles &t, const int32_t *widths, int32_t n_widths, int64_t n_out,
-                         BoxcarPlan *out)
+                         BoxcarPlan *out, int max_width)
 {
     BoxcarPlan p{};
     if (!widths || n_widths < 1 || n_widths > AMBER_MAX_WIDTHS)
         return fail(AMBER_E_ARG, "n_widths=%d must be in [1, %d]", n_widths, AMBER_MAX_WIDTHS);
     int maxw = 0;
     for (int k = 0; k < n_widths; ++k) {
-        if (widths[k] < 1 || widths[k] > 1024 || widths[k] > n_out)
-            return fail(AMBER_E_ARG, "widths[%d]=%d must be in [1, min(n_out=%lld, 1024)]", k, widths[k],
-                        (long long)n_out);
+        if (widths[k] < 1 || widths[k] > max_width || widths[k] > n_out)
+            return fail(AMBER_E_ARG, "widths[%d]=%d must be in [1, min(n_out=%lld, %d)]", k, widths[k],
+                        (long long)n_out, max_width);
         if (widths[k] > maxw) maxw = widths[k];
         int s = t.boxcar_step[k];
         if (s != 1 && s != 2 && s != 4 && s != 8)
@@ -155,6 +155,35 @@ amber_status plan_boxcar(const amber_tiles &t, const int32_t *widths, int32_t n_
 }  // namespace amber
 
 using namespace amber;
+
+namespace {
+
+constexpr int kMaxFactor = 4096;  // largest decimation factor (the paper's largest is 3200)
+
+// The caller's tiles, or the defaults with snr_threads raised until a chunk
+// (16 samples per work-item) holds twice the largest factor and one decimated
+// bin per work-item and step (measured fastest on the 1536-channel beam: the
+// decimated series are short, so larger steps leave work-items idle).
+amber_status downsample_tiles(const amber_tiles *tiles, const int32_t *factors, int32_t n_factors, int64_t n_out,
+                              amber_tiles *out)
+{
+    (void)n_out;
+    if (!factors || n_factors < 1 || n_factors > AMBER_MAX_WIDTHS)
+        return fail(AMBER_E_ARG, "n_factors=%d must be in [1, %d]", n_factors, AMBER_MAX_WIDTHS);
+    if (tiles) {
+        *out = *tiles;
+        return AMBER_OK;
+    }
+    *out = default_tiles();
+    int maxf = 1;
+    for (int k = 0; k < n_factors; ++k) maxf = factors[k] > maxf ? factors[k] : maxf;
+    const int64_t halo = (maxf + 15) / 16 * 16;
+    while ((int64_t)out->snr_threads * 16 < 2 * halo && out->snr_threads < kMaxThreads) out->snr_threads *= 2;
+    for (int k = 0; k < AMBER_MAX_WIDTHS; ++k) out->boxcar_step[k] = 1;
+    return AMBER_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -316,6 +345,41 @@ amber_status amber_integrate_snr(const int32_t *d_dd, int32_t n_dm, int64_t dd_s
     if ((s = plan_boxcar(t, widths, n_widths, n_out, &plan)) != AMBER_OK) return s;
     return launch_integrate_snr(plan, t, d_dd, n_dm, dd_stride, n_out, widths, n_widths, d_snr, d_peak_t,
                                 (hipStream_t)stream);
+}
+
+amber_status amber_downsample(const int32_t *d_dd, int32_t n_dm, int64_t dd_stride, int64_t n_out,
+                              const int32_t *factors, int32_t n_factors, int32_t *d_y, int64_t y_stride,
+                              const amber_tiles *tiles, void *stream)
+{
+    clear_error();
+    amber_status s = check_rows(d_dd, n_dm, dd_stride, n_out, "d_dd");
+    if (s != AMBER_OK) return s;
+    amber_tiles t;
+    if ((s = downsample_tiles(tiles, factors, n_factors, n_out, &t)) != AMBER_OK) return s;
+    for (int k = 0; k < n_factors; ++k)
+        if (y_stride < n_out / factors[k])
+            return fail(AMBER_E_SHAPE, "y_stride=%lld < n_out / factors[%d]", (long long)y_stride, k);
+    if (!d_y || ((uintptr_t)d_y & 3) != 0) return fail(AMBER_E_ARG, "d_y is NULL or misaligned");
+    BoxcarPlan plan;
+    if ((s = plan_boxcar(t, factors, n_factors, n_out, &plan, kMaxFactor)) != AMBER_OK) return s;
+    return launch_integrate(plan, t, d_dd, n_dm, dd_stride, n_out, factors, n_factors, d_y, y_stride,
+                            (hipStream_t)stream, 1);
+}
+
+amber_status amber_downsample_snr(const int32_t *d_dd, int32_t n_dm, int64_t dd_stride, int64_t n_out,
+                                  const int32_t *factors, int32_t n_factors, float *d_snr, int32_t *d_peak,
+                                  const amber_tiles *tiles, void *stream)
+{
+    clear_error();
+    amber_status s = check_rows(d_dd, n_dm, dd_stride, n_out, "d_dd");
+    if (s != AMBER_OK) return s;
+    if (!d_snr) return fail(AMBER_E_ARG, "d_snr is NULL");
+    amber_tiles t;
+    if ((s = downsample_tiles(tiles, factors, n_factors, n_out, &t)) != AMBER_OK) return s;
+    BoxcarPlan plan;
+    if ((s = plan_boxcar(t, factors, n_factors, n_out, &plan, kMaxFactor)) != AMBER_OK) return s;
+    return launch_integrate_snr(plan, t, d_dd, n_dm, dd_stride, n_out, factors, n_factors, d_snr, d_peak,
+                                (hipStream_t)stream, 1);
 }
 
 }  // extern "C"

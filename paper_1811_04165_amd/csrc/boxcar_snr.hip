@@ -26,10 +26,14 @@ namespace {
 
 __device__ __forceinline__ int qix(int i) { return i + (i >> 6); }
 
+// Widths of the sliding boxcars, or (dec != 0) decimation factors: then entry
+// k is the series of sums of w[k] consecutive samples starting at multiples
+// of w[k], i.e. the width-w[k] boxcar read at t = j w[k], j < n_out / w[k].
 struct WidthSet {
     int32_t w[AMBER_MAX_WIDTHS];
     int32_t step[AMBER_MAX_WIDTHS];
     int32_t n;
+    int32_t dec;
 };
 
 struct Stat {
@@ -184,6 +188,38 @@ __device__ __forceinline__ void width_stats(const uint32_t *Q, int w, int outs, 
     }
 }
 
+// Accumulates the decimated series of factor f over the bins j whose first
+// sample j f lies in [cs, cs + outs), j < n_bins, S bins per thread per step.
+template <int S>
+__device__ __forceinline__ void dec_stats(const uint32_t *Q, int f, int outs, int64_t cs, int64_t n_bins, double r,
+                                          Stat &st)
+{
+    const int64_t j_lo = (cs + f - 1) / f;
+    int64_t j_end = (cs + outs + f - 1) / f;
+    j_end = j_end < n_bins ? j_end : n_bins;
+    for (int64_t jj = (int64_t)threadIdx.x * S; j_lo + jj < j_end; jj += (int64_t)blockDim.x * S) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int64_t j = j_lo + jj + s;
+            if (j < j_end) {
+                const int u = (int)(j * f - cs);
+                stat_add(st, (int32_t)(Q[qix(u + f)] - Q[qix(u)]), j, r);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void dec_stats_any(int step, const uint32_t *Q, int f, int outs, int64_t cs,
+                                              int64_t n_bins, double r, Stat &st)
+{
+    switch (step) {
+    case 1: dec_stats<1>(Q, f, outs, cs, n_bins, r, st); break;
+    case 2: dec_stats<2>(Q, f, outs, cs, n_bins, r, st); break;
+    case 4: dec_stats<4>(Q, f, outs, cs, n_bins, r, st); break;
+    default: dec_stats<8>(Q, f, outs, cs, n_bins, r, st); break;
+    }
+}
+
 __device__ __forceinline__ void width_stats_any(int step, const uint32_t *Q, int w, int outs, int64_t cs,
                                                 int64_t n_valid, double r, Stat &st)
 {
@@ -229,7 +265,10 @@ __global__ __launch_bounds__(1024) void integrate_snr_kernel(BoxJob single, cons
         for (int k = 0; k < NW; ++k) {
             if (k < ws.n) {
                 const int w = ws.w[k];
-                width_stats_any(ws.step[k], Q, w, outs, cs, n_out - w + 1, d0 * w, st[k]);
+                if (ws.dec)
+                    dec_stats_any(ws.step[k], Q, w, outs, cs, n_out / w, d0 * w, st[k]);
+                else
+                    width_stats_any(ws.step[k], Q, w, outs, cs, n_out - w + 1, d0 * w, st[k]);
             }
         }
         __syncthreads();
@@ -238,7 +277,7 @@ __global__ __launch_bounds__(1024) void integrate_snr_kernel(BoxJob single, cons
     if ((int)threadIdx.x < ws.n) {
         const int k = threadIdx.x;
         const int w = ws.w[k];
-        finish(scratch[k * 16], n_out - w + 1, d0 * w, job.snr + (size_t)k * job.n_dm + i,
+        finish(scratch[k * 16], ws.dec ? n_out / w : n_out - w + 1, d0 * w, job.snr + (size_t)k * job.n_dm + i,
                job.peak ? job.peak + (size_t)k * job.n_dm + i : nullptr);
     }
 }
@@ -257,11 +296,22 @@ __global__ __launch_bounds__(1024) void integrate_kernel(const int32_t *__restri
     load_prefix(dd + (size_t)i * dd_stride, cs, n_out, vec_ok != 0, Q, wave_tot);
     for (int k = 0; k < ws.n; ++k) {
         const int w = ws.w[k];
-        const int64_t n_valid = n_out - w + 1;
         int32_t *__restrict__ out = box + ((size_t)k * n_dm + i) * box_stride;
-        for (int u = threadIdx.x; u < outs; u += blockDim.x) {
-            const int64_t t = cs + u;
-            if (t < n_valid) out[t] = (int32_t)(Q[qix(u + w)] - Q[qix(u)]);
+        if (ws.dec) {
+            // bins j whose first sample j w lies in this chunk's outputs
+            const int64_t j_lo = (cs + w - 1) / w, n_bins = n_out / w;
+            int64_t j_end = (cs + outs + w - 1) / w;
+            j_end = j_end < n_bins ? j_end : n_bins;
+            for (int64_t j = j_lo + threadIdx.x; j < j_end; j += blockDim.x) {
+                const int u = (int)(j * w - cs);
+                out[j] = (int32_t)(Q[qix(u + w)] - Q[qix(u)]);
+            }
+        } else {
+            const int64_t n_valid = n_out - w + 1;
+            for (int u = threadIdx.x; u < outs; u += blockDim.x) {
+                const int64_t t = cs + u;
+                if (t < n_valid) out[t] = (int32_t)(Q[qix(u + w)] - Q[qix(u)]);
+            }
         }
     }
 }
@@ -294,9 +344,10 @@ __global__ __launch_bounds__(1024) void snr_kernel(const int32_t *__restrict__ b
         finish(scratch[0], n, r, snr + (size_t)k * n_dm + i, peak ? peak + (size_t)k * n_dm + i : nullptr);
 }
 
-WidthSet make_widths(const amber_tiles &t, const int32_t *widths, int n)
+WidthSet make_widths(const amber_tiles &t, const int32_t *widths, int n, int decimate)
 {
     WidthSet ws{};
+    ws.dec = decimate ? 1 : 0;
     for (int k = 0; k < n; ++k) {
         ws.w[k] = widths[k];
         ws.step[k] = t.boxcar_step[k];
@@ -342,12 +393,12 @@ BoxJob make_box_job(const int32_t *d_dd, int n_dm, int64_t dd_stride, int64_t n_
 
 amber_status launch_integrate_snr_jobs(const BoxcarPlan &p, const amber_tiles &t, const BoxJob *single,
                                        const BoxJob *d_jobs, int n_jobs, int64_t n_rows, const int32_t *widths,
-                                       int n_widths, hipStream_t stream)
+                                       int n_widths, hipStream_t stream, int decimate)
 {
     amber_status s = check_chunk(p);
     if (s != AMBER_OK) return s;
     if (n_rows > 0x7fffffff) return fail(AMBER_E_SHAPE, "too many rows (%lld)", (long long)n_rows);
-    const WidthSet ws = make_widths(t, widths, n_widths);
+    const WidthSet ws = make_widths(t, widths, n_widths, decimate);
     const int halo = halo_of(p);
     // the stats scratch reuses the prefix buffer after the last chunk
     int64_t lds = p.lds_bytes;
@@ -374,19 +425,19 @@ amber_status launch_integrate_snr_jobs(const BoxcarPlan &p, const amber_tiles &t
 
 amber_status launch_integrate_snr(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_dd, int n_dm,
                                   int64_t dd_stride, int64_t n_out, const int32_t *widths, int n_widths,
-                                  float *d_snr, int32_t *d_peak, hipStream_t stream)
+                                  float *d_snr, int32_t *d_peak, hipStream_t stream, int decimate)
 {
     const BoxJob j = make_box_job(d_dd, n_dm, dd_stride, n_out, d_snr, d_peak);
-    return launch_integrate_snr_jobs(p, t, &j, nullptr, 1, n_dm, widths, n_widths, stream);
+    return launch_integrate_snr_jobs(p, t, &j, nullptr, 1, n_dm, widths, n_widths, stream, decimate);
 }
 
 amber_status launch_integrate(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_dd, int n_dm,
                               int64_t dd_stride, int64_t n_out, const int32_t *widths, int n_widths, int32_t *d_box,
-                              int64_t box_stride, hipStream_t stream)
+                              int64_t box_stride, hipStream_t stream, int decimate)
 {
     amber_status s = check_chunk(p);
     if (s != AMBER_OK) return s;
-    const WidthSet ws = make_widths(t, widths, n_widths);
+    const WidthSet ws = make_widths(t, widths, n_widths, decimate);
     const int halo = halo_of(p);
     const int outs = p.chunk - halo;
     const int64_t n_chunks = (n_out + outs - 1) / outs;
@@ -402,7 +453,7 @@ amber_status launch_snr(const BoxcarPlan &p, const amber_tiles &t, const int32_t
                         int64_t n_out, const int32_t *widths, int n_widths, float *d_snr, int32_t *d_peak,
                         hipStream_t stream)
 {
-    const WidthSet ws = make_widths(t, widths, n_widths);
+    const WidthSet ws = make_widths(t, widths, n_widths, 0);
     // the per-row kernel uses the first width's step as its items per thread
     const int step = t.boxcar_step[0];
     dim3 grid(n_dm, n_widths);

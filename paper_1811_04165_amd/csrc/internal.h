@@ -50,8 +50,9 @@ struct BoxcarPlan {
     int64_t lds_bytes;
 };
 
+// max_width: 1024 for sliding widths, 4096 for decimation factors
 amber_status plan_boxcar(const amber_tiles &t, const int32_t *widths, int32_t n_widths, int64_t n_out,
-                         BoxcarPlan *out);
+                         BoxcarPlan *out, int max_width = 1024);
 
 const amber_tiles &default_tiles();
 
@@ -81,9 +82,10 @@ DedispJob make_dedisp_job(const DedispPlan &p, const int32_t *d_delays, int n_dm
 amber_status launch_dedisperse_jobs(const DedispPlan &p, const DedispJob *single, const DedispJob *d_jobs,
                                     int n_jobs, int64_t n_blocks, int64_t lds_bytes, hipStream_t stream);
 BoxJob make_box_job(const int32_t *d_dd, int n_dm, int64_t dd_stride, int64_t n_out, float *d_snr, int32_t *d_peak);
+// decimate != 0: the widths are decimation factors (see amber_downsample_snr)
 amber_status launch_integrate_snr_jobs(const BoxcarPlan &p, const amber_tiles &t, const BoxJob *single,
                                        const BoxJob *d_jobs, int n_jobs, int64_t n_rows, const int32_t *widths,
-                                       int n_widths, hipStream_t stream);
+                                       int n_widths, hipStream_t stream, int decimate = 0);
 
 // Jobs of several beams grouped into as few launches as their launch shapes
 // allow.  Dedispersion jobs with the same tile genes share a launch (the
@@ -128,7 +130,7 @@ amber_status launch_dedisperse(const DedispPlan &p, const int32_t *d_delays, int
 
 amber_status launch_integrate(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_dd, int n_dm,
                               int64_t dd_stride, int64_t n_out, const int32_t *widths, int n_widths,
-                              int32_t *d_box, int64_t box_stride, hipStream_t stream);
+                              int32_t *d_box, int64_t box_stride, hipStream_t stream, int decimate = 0);
 
 amber_status launch_snr(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_box, int n_dm,
                         int64_t box_stride, int64_t n_out, const int32_t *widths, int n_widths,
@@ -142,6 +144,6 @@ amber_status launch_assemble(uint8_t *d_cur, const uint8_t *d_prev, const uint8_
 
 amber_status launch_integrate_snr(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_dd, int n_dm,
                                   int64_t dd_stride, int64_t n_out, const int32_t *widths, int n_widths,
-                                  float *d_snr, int32_t *d_peak, hipStream_t stream);
+                                  float *d_snr, int32_t *d_peak, hipStream_t stream, int decimate = 0);
 
 }  // namespace amber

@@ -114,6 +114,18 @@ def test_device_calls_validate_before_launch():
     assert lib.amber_last_error() != b""
     rc = lib.amber_default_tiles(None)
     assert rc == -1
+    # downsampling: factor beyond n_out, factor beyond 4096, no factors, output rows too short
+    f = (ctypes.c_int32 * 2)(10, 200)
+    rc = lib.amber_downsample_snr(fake, 4, 100, 100, f, 2, fake, fake, None, None)
+    assert rc == -1 and b"widths" in lib.amber_last_error()
+    big = (ctypes.c_int32 * 1)(5000)
+    rc = lib.amber_downsample_snr(fake, 4, 10000, 10000, big, 1, fake, fake, None, None)
+    assert rc == -1 and b"4096" in lib.amber_last_error()
+    rc = lib.amber_downsample_snr(fake, 4, 100, 100, f, 0, fake, fake, None, None)
+    assert rc == -1
+    f10 = (ctypes.c_int32 * 1)(10)
+    rc = lib.amber_downsample(fake, 4, 100, 100, f10, 1, fake, 9, None, None)
+    assert rc == -2 and b"y_stride" in lib.amber_last_error()
 
 
 def test_gpu_test_tiles_are_valid():

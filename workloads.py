@@ -202,3 +202,10 @@ def poisson_arrivals(n_beams: int, rate_per_beam: float, duration_s: float, seed
             seq += 1
     ev.sort()
     return ev
+
+
+# --- downsampling --------------------------------------------------------------
+
+# Nine decimation factors spanning Table 2's 10 ... 3200 (doubling from 10, then
+# the largest), plus factor 1: the S/N of the series itself.
+DOWNSAMPLING_FACTORS = (1, 10, 20, 40, 80, 160, 320, 640, 1280, 3200)
