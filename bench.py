@@ -358,6 +358,155 @@ def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitter
                       "seconds": seconds, "warmup_s": warmup_s, "submit_threads": submitters, "by_rate": out}}
 
 
+def ga_study_report(seeds: int):
+    """The paper's GA studies (Figs 3-5, App. A) on MI355X, replayed against a
+    measured fitness table of the 256-channel / 128-DM workload.
+
+    Each kernel's GPU time is measured for every value of its own genes
+    (median of 7 runs); the two kernels run back to back, so a
+    configuration's fitness is the sum.  The library's search engine then
+    runs on the host against that table: every search gets the evaluation
+    budget of the per-kernel brute force (the paper's T_run = T_BF), and the
+    same seeds for every setting."""
+    import itertools
+    import os
+    import tempfile
+    import numpy as np
+    import torch
+    import paper_1811_04165_amd as amber
+    import workloads
+    wl = workloads.small()
+    g = wl.geom
+    search = amber.Search(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step, wl.n_out, wl.widths)
+    x_host, n_in = workloads.make_input(wl, search.delays_host, search.info.max_delay)
+    x = torch.from_numpy(x_host).cuda()
+    sp = amber.default_space(search.info, wl.widths, wl.n_out)
+    sp.set_gene_values(4, [256])
+    nw = len(wl.widths)
+    gv = [sp.gene_values(i) for i in range(sp.n_genes)]
+
+    def med_time(fn, reps=7):
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b) / 1e3)
+        return statistics.median(ts)
+
+    print("[bench] measuring the fitness table", file=sys.stderr, flush=True)
+    gc.collect()
+    t_dd = {}
+    for tpd, spt, dpb, cu in itertools.product(*gv[:4]):
+        t = amber.make_tiles(threads_per_dm=tpd, samples_per_thread=spt, dms_per_block=dpb, channel_unroll=cu,
+                             snr_threads=256)
+        try:
+            amber.validate_tiles(t, search.info, nw)
+        except amber.AmberError:
+            continue
+        amber.dedisperse(search.delays, search.info, x, n_in, wl.n_out, t, out=search.dd)
+        t_dd[(tpd, spt, dpb, cu)] = med_time(
+            lambda: amber.dedisperse(search.delays, search.info, x, n_in, wl.n_out, t, out=search.dd))
+    t_box = {}
+    for steps in itertools.product(*gv[5:]):
+        t = amber.make_tiles(snr_threads=256, boxcar_step=list(steps))
+        amber.integrate_snr(search.dd, wl.n_out, wl.widths, t, out=(search.snr, search.peak))
+        t_box[steps] = med_time(
+            lambda: amber.integrate_snr(search.dd, wl.n_out, wl.widths, t, out=(search.snr, search.peak)))
+
+    return ga_study_replay(sp, wl, t_dd, t_box, seeds)
+
+
+def ga_study_replay(sp, wl, t_dd, t_box, seeds: int):
+    """The searches of the GA study against a fitness table (host only)."""
+    import json
+    import os
+    import tempfile
+    import numpy as np
+    import paper_1811_04165_amd as amber
+    nw = len(wl.widths)
+
+    def fitness_of(t):
+        return t_dd[(t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll)] + \
+            t_box[tuple(t.boxcar_step[k] for k in range(nw))]
+
+    opt = min(t_dd.values()) + min(t_box.values())
+
+    def run(kind, log=None, **kw):
+        hist = []
+
+        def fit(t):
+            v = fitness_of(t)
+            hist.append((v, (t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll) +
+                         tuple(t.boxcar_step[k] for k in range(nw))))
+            return v
+        r = amber.search_tiles(sp, amber.tune_params(kind, **kw), fit, log_path=log)
+        return r, hist
+
+    bf, _ = run("per_kernel")
+    t_bf, budget = bf.best_time_s, bf.n_evals
+    checkpoints = [c for c in (50, 100, 200, 400, 800) if c < budget] + [budget]
+    genes = ["threads_per_dm", "samples_per_thread", "dms_per_block", "channel_unroll"] + \
+        ["boxcar_step_w%d" % w for w in wl.widths]
+    base = dict(pop=20, p_cross=0.8, p_mut=0.1, crossover=0)
+    settings = [("base (N_pop 20, p_cross 0.8, p_mut 0.1, uniform)", "ga", {})]
+    settings += [("p_mut %g" % v, "ga", {"p_mut": v}) for v in (0.01, 0.3, 1.0)]
+    settings += [("p_cross %g" % v, "ga", {"p_cross": v}) for v in (0.2, 0.5, 1.0)]
+    settings += [("N_pop %d" % v, "ga", {"pop": v}) for v in (30, 50)]
+    settings += [("one-point crossover", "ga", {"crossover": 1}), ("random search", "random", {})]
+    out = {"workload": wl.name, "space_size": amber.space_size(sp), "table": {
+        "dedisperse_configs": len(t_dd), "boxcar_configs": len(t_box), "optimum_s": opt,
+        "dedisperse_best_s": min(t_dd.values()), "boxcar_best_s": min(t_box.values())},
+        "brute_force_per_kernel": {"best_s": t_bf, "evals": budget, "over_optimum": t_bf / opt},
+        "budget_evals": budget, "seeds": seeds, "settings": []}
+    tmp = tempfile.mkdtemp()
+    for name, kind, kw in settings:
+        print("[bench] study: %s" % name, file=sys.stderr, flush=True)
+        p = dict(base)
+        p.update(kw)
+        finals, curves, cvs, best_genes, evals = [], [], [], [], []
+        for seed in range(1, seeds + 1):
+            if kind == "ga":
+                log = os.path.join(tmp, "ga.jsonl")
+                if os.path.exists(log):
+                    os.remove(log)
+                gens = max(1, budget // p["pop"] - 1)
+                r, hist = run("ga", log=log, seed=seed, generations=gens, **p)
+                lines = [json.loads(l) for l in open(log)]
+                end = np.array(lines[-1]["final_population"], dtype=np.float64)
+            else:
+                r, hist = run("random", seed=1000 + seed, max_evals=budget)
+                top = sorted({c: v for v, c in hist}.items(), key=lambda kv: kv[1])[:p["pop"]]
+                end = np.array([c for c, _ in top], dtype=np.float64)
+            vals = [v for v, _ in hist]
+            run_best = np.minimum.accumulate(vals)
+            curves.append([float(run_best[min(c, len(run_best)) - 1]) / t_bf for c in checkpoints])
+            finals.append(r.best_time_s)
+            evals.append(r.n_evals)
+            cvs.append(end.std(axis=0) / end.mean(axis=0))
+            b = r.best
+            best_genes.append([b.threads_per_dm, b.samples_per_thread, b.dms_per_block, b.channel_unroll] +
+                              [b.boxcar_step[k] for k in range(nw)])
+        f = np.array(finals)
+        cv = np.mean(cvs, axis=0)
+        hist_genes = {gname: dict(zip(*[list(map(int, a)) for a in np.unique(np.array(best_genes)[:, k],
+                                                                              return_counts=True)]))
+                      for k, gname in enumerate(genes)}
+        out["settings"].append({
+            "name": name, "kind": kind, "params": p, "evals_median": float(np.median(evals)),
+            "best_over_bf": {"median": float(np.median(f / t_bf)), "p10": float(np.percentile(f / t_bf, 10)),
+                             "p90": float(np.percentile(f / t_bf, 90))},
+            "best_over_optimum_median": float(np.median(f / opt)),
+            "runs_within_5pct_of_optimum": int(np.sum(f <= 1.05 * opt)),
+            "curve_best_over_bf_median": dict(zip(map(str, checkpoints), np.median(curves, axis=0).tolist())),
+            "cv_end_population": dict(zip(genes, cv.tolist())),
+            "best_over_bf_all": (f / t_bf).tolist(), "best_gene_histograms": hist_genes})
+    return {"metric": "GA studies", "unit": "ratio", "value": out["settings"][0]["best_over_bf"]["median"],
+            "higher_is_better": False, "ga_study": out}
+
+
 def downsample_report(steps: int, warmup: int):
     """Decimating downsampling + S/N (the paper's smoothing definition) on the
     1536-channel beam: the ten series of the factor ladder in one fused launch,
@@ -418,6 +567,10 @@ def main() -> int:
                     help="instead of the throughput step: compare the GA tile search with exhaustive, random and "
                          "per-kernel brute-force search on the 256-channel workload")
     ap.add_argument("--tune-seeds", type=int, default=10)
+    ap.add_argument("--ga-study", action="store_true",
+                    help="instead of the throughput step: the paper's GA studies (mutation and crossover rates, "
+                         "population size, crossover type, random search) replayed on a measured fitness table")
+    ap.add_argument("--study-seeds", type=int, default=35)
     ap.add_argument("--batched", action="store_true",
                     help="instead of the single-beam step: 40 uneven beams, per-beam launches vs one batch vs "
                          "the batch replayed as a HIP graph")
@@ -453,6 +606,9 @@ def main() -> int:
         return 0
     if args.batched:
         print(json.dumps(batched_report(args.beams, args.steps, args.warmup)))
+        return 0
+    if args.ga_study:
+        print(json.dumps(ga_study_report(args.study_seeds)))
         return 0
     if args.downsample:
         print(json.dumps(downsample_report(args.steps, args.warmup)))

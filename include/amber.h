@@ -287,7 +287,9 @@ amber_status amber_space_size(const amber_tune_space *space, int64_t *count);
 
 /* Runs the search of p->search over `space` with a caller-supplied fitness
  * (host only; no GPU needed).  log_jsonl_path, if not NULL, receives one JSON
- * line per GA generation (or per 1000 evaluations for the other searches). */
+ * line per GA generation (or per 1000 evaluations for the other searches);
+ * after its last generation the GA adds one line {"final_population": gene
+ * values per individual, "fitness": per individual (-1 for failures)}. */
 amber_status amber_search_tiles(const amber_tune_space *space, const amber_tune_params *p, amber_fitness_fn fn,
                                 void *user, amber_tune_result *result, const char *log_jsonl_path);
 

@@ -168,6 +168,31 @@ private:
         fflush(log_);
     }
 
+    // One line with the final population: gene values (in the space's gene
+    // order) and fitness of every individual.
+    void log_population(const std::vector<Genome> &pop, const std::vector<double> &fit)
+    {
+        if (!log_) return;
+        std::string out = "{\"final_population\":[";
+        for (size_t i = 0; i < pop.size(); ++i) {
+            out += i ? ",[" : "[";
+            for (int k = 0; k < n_genes(); ++k) {
+                if (k) out += ",";
+                out += std::to_string(sp_.values[k][pop[i][k]]);
+            }
+            out += "]";
+        }
+        out += "],\"fitness\":[";
+        for (size_t i = 0; i < fit.size(); ++i) {
+            char b[40];
+            snprintf(b, sizeof b, "%s%.9g", i ? "," : "", std::isfinite(fit[i]) ? fit[i] : -1.0);
+            out += b;
+        }
+        out += "]}\n";
+        fputs(out.c_str(), log_);
+        fflush(log_);
+    }
+
     bool random_genome(Genome &g)
     {
         g.assign(n_genes(), 0);
@@ -301,6 +326,7 @@ private:
             fit.swap(next_fit);
             log_line(gen);
         }
+        log_population(pop, fit);
         return AMBER_OK;
     }
 

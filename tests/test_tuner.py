@@ -120,7 +120,16 @@ def test_ga_valid_offspring_deterministic_and_converging(amber, tmp_path):
                                                      channel_unroll=16, snr_threads=256,
                                                      boxcar_step=[4, 2])) * 3.0
     lines = [json.loads(l) for l in log.read_text().splitlines()]
+    final = lines.pop()
     assert [l["generation"] for l in lines] == list(range(41))
+    # the final population: 32 valid individuals, the best of them the search's best
+    assert len(final["final_population"]) == len(final["fitness"]) == 32
+    for genes, f in zip(final["final_population"], final["fitness"]):
+        t = amber.make_tiles(threads_per_dm=genes[0], samples_per_thread=genes[1], dms_per_block=genes[2],
+                             channel_unroll=genes[3], snr_threads=genes[4], boxcar_step=genes[5:])
+        amber.validate_tiles(t, sp.info, len(widths))
+        assert f == pytest.approx(smooth(t), rel=1e-6)
+    assert min(final["fitness"]) == pytest.approx(r1.best_time_s, rel=1e-6)
     bests = [l["best_time_s"] for l in lines]
     assert all(b2 <= b1 for b1, b2 in zip(bests, bests[1:]))
     # one-point crossover also runs and stays valid
