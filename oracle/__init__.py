@@ -12,6 +12,7 @@ numpy in / numpy out functions:
   dedispersion as shift-and-sum of channels; textbook cold-plasma delay).
 * ``dedisperse``   -- brute-force one-step dedispersion (Section 5 names the
   one-step scheme; Section 2 the dedispersion kernel).
+* ``dedisperse_masked`` -- the same with zapped (RFI) channels excluded.
 * ``boxcar``       -- sliding boxcar "smoothing" of each series (Section 2).
 * ``downsample``   -- decimating downsampling by a factor (Section 2, Table 2).
 * ``snr``          -- (max - mean) / population std per series (Section 2's
@@ -59,12 +60,15 @@ def _load():
                                                ctypes.c_double, ctypes.c_double, i32p, i32p]
             lib.oracle_dedisperse.argtypes = [i32p, ctypes.c_int, ctypes.c_int, u8p, ctypes.c_int64,
                                               ctypes.c_int64, ctypes.c_int64, i32p, ctypes.c_int]
+            lib.oracle_dedisperse_masked.argtypes = [i32p, ctypes.c_int, ctypes.c_int, u8p, ctypes.c_int64,
+                                                     ctypes.c_int64, ctypes.c_int64, u8p, i32p, ctypes.c_int]
             lib.oracle_boxcar.argtypes = [i32p, ctypes.c_int, ctypes.c_int64, ctypes.c_int, i64p,
                                           ctypes.c_int]
             lib.oracle_downsample.argtypes = [i32p, ctypes.c_int, ctypes.c_int64, ctypes.c_int, i64p,
                                               ctypes.c_int]
             lib.oracle_snr.argtypes = [i64p, ctypes.c_int, ctypes.c_int64, f64p, i32p, ctypes.c_int]
-            for f in (lib.oracle_delay_table, lib.oracle_dedisperse, lib.oracle_boxcar, lib.oracle_downsample,
+            for f in (lib.oracle_delay_table, lib.oracle_dedisperse, lib.oracle_dedisperse_masked, lib.oracle_boxcar,
+                      lib.oracle_downsample,
                       lib.oracle_snr):
                 f.restype = ctypes.c_int
             _lib = lib
@@ -101,6 +105,23 @@ def dedisperse(delays: np.ndarray, x: np.ndarray, n_in: int, n_out: int, threads
                                    int(threads))
     if rc != 0:
         raise ValueError("oracle_dedisperse: a delay reads outside [0, n_in)")
+    return out
+
+
+def dedisperse_masked(delays: np.ndarray, x: np.ndarray, n_in: int, n_out: int, keep, threads: int = 0) -> np.ndarray:
+    """dd[i][t] = sum over channels with keep[c] != 0 of x[c][t + delays[i][c]] (zapped channels excluded)."""
+    d = np.ascontiguousarray(delays, dtype=np.int32)
+    xa = np.ascontiguousarray(x, dtype=np.uint8)
+    k = np.ascontiguousarray(keep, dtype=np.uint8)
+    n_dm, n_chan = d.shape
+    if xa.shape[0] != n_chan or k.shape != (n_chan,):
+        raise ValueError("channel count of x, delays and keep differ")
+    out = np.empty((n_dm, n_out), dtype=np.int32)
+    rc = _load().oracle_dedisperse_masked(_ptr(d, ctypes.c_int32), n_dm, n_chan, _ptr(xa, ctypes.c_uint8),
+                                          xa.shape[1], int(n_in), int(n_out), _ptr(k, ctypes.c_uint8),
+                                          _ptr(out, ctypes.c_int32), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_dedisperse_masked: a delay reads outside [0, n_in)")
     return out
 
 

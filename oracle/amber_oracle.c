@@ -118,6 +118,40 @@ int oracle_dedisperse(const int32_t *delays, int n_dm, int n_chan,
 }
 
 /*
+ * Dedispersion with zapped channels (channels excluded because of radio
+ * frequency interference; the paper's pipeline reads them from an input
+ * file, Section 2 footnote):
+ *
+ *     dd[i][t] = sum over c with keep[c] != 0 of in[c][t + delay[i][c]]
+ *
+ * Same arguments and checks as oracle_dedisperse, plus keep[n_chan].
+ */
+int oracle_dedisperse_masked(const int32_t *delays, int n_dm, int n_chan,
+                             const uint8_t *in, int64_t stride, int64_t n_in,
+                             int64_t n_out, const uint8_t *keep, int32_t *dd,
+                             int n_threads)
+{
+    if (n_dm <= 0 || n_chan <= 0 || n_out < 0 || n_in < 0 || stride < n_in || !keep)
+        return -1;
+    for (size_t k = 0; k < (size_t)n_dm * n_chan; ++k)
+        if (delays[k] < 0 || n_out + delays[k] > n_in)
+            return -1;
+    int nt = oracle_threads(n_threads);
+    #pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
+    for (int i = 0; i < n_dm; ++i) {
+        const int32_t *drow = delays + (size_t)i * n_chan;
+        for (int64_t t = 0; t < n_out; ++t) {
+            int32_t sum = 0;
+            for (int c = 0; c < n_chan; ++c)
+                if (keep[c])
+                    sum += in[(size_t)c * stride + (size_t)(t + drow[c])];
+            dd[(size_t)i * n_out + t] = sum;
+        }
+    }
+    return 0;
+}
+
+/*
  * Sliding boxcar integration of one dedispersed series ("smoothing" of the
  * dedispersed time series, Section 2), for a single width w:
  *

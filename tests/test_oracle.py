@@ -177,6 +177,29 @@ def test_dedisperse_rejects_out_of_range():
 
 # --- boxcar -----------------------------------------------------------------------
 
+def test_dedisperse_masked_pins():
+    """Zapping channels: an all-kept mask is plain dedispersion; a mask and its
+    complement partition the sum; a zapped row's data never matter; zapping
+    everything gives zeros; a single kept channel is its shifted row."""
+    delays, x, n_in = workloads.tiny(n_chan=19, n_dm=6, n_out=150, seed=31, max_delay=40)
+    rng = np.random.default_rng(32)
+    full = oracle.dedisperse(delays, x, n_in, 150)
+    assert np.array_equal(oracle.dedisperse_masked(delays, x, n_in, 150, np.ones(19, np.uint8)), full)
+    keep = (rng.random(19) < 0.7).astype(np.uint8)
+    a = oracle.dedisperse_masked(delays, x, n_in, 150, keep)
+    b = oracle.dedisperse_masked(delays, x, n_in, 150, 1 - keep)
+    assert np.array_equal(a + b, full)
+    x2 = x.copy()
+    x2[keep == 0] = rng.integers(0, 256, size=x2[keep == 0].shape, dtype=np.uint8)
+    assert np.array_equal(oracle.dedisperse_masked(delays, x2, n_in, 150, keep), a)
+    assert not np.any(oracle.dedisperse_masked(delays, x, n_in, 150, np.zeros(19, np.uint8)))
+    one = np.zeros(19, np.uint8)
+    one[5] = 1
+    got = oracle.dedisperse_masked(delays, x, n_in, 150, one)
+    for i in range(6):
+        assert np.array_equal(got[i], x[5, delays[i, 5]:delays[i, 5] + 150].astype(np.int32))
+
+
 def test_boxcar_identity_doubling_and_convolve():
     rng = np.random.default_rng(21)
     dd = rng.integers(0, 400000, size=(5, 300)).astype(np.int32)
