@@ -507,6 +507,51 @@ def ga_study_replay(sp, wl, t_dd, t_box, seeds: int):
             "higher_is_better": False, "ga_study": out}
 
 
+def rfi_report(steps: int, warmup: int):
+    """Dedispersion with zapped channels on the 1536-channel beam (a 150-channel
+    band and 40 scattered channels zapped) beside plain dedispersion."""
+    import numpy as np
+    import torch
+    import paper_1811_04165_amd as amber
+    import workloads
+    wl = workloads.beam()
+    g = wl.geom
+    search = amber.Search(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step, wl.n_out, wl.widths)
+    x_host, n_in = workloads.make_input(wl, search.delays_host, search.info.max_delay)
+    x = torch.from_numpy(x_host).cuda()
+    keep = np.ones(g.n_chan, np.uint8)
+    keep[700:850] = 0
+    keep[np.random.default_rng(42).choice(g.n_chan, 40, replace=False)] = 0
+    keep_dev = torch.from_numpy(keep).cuda()
+    tiles = amber.default_tiles()
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        b.record()
+        torch.cuda.synchronize()
+        gc.collect()
+        gc.disable()
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        gc.enable()
+        return a.elapsed_time(b) / 1e3 / steps
+
+    t_plain = timed(lambda: amber.dedisperse(search.delays, search.info, x, n_in, wl.n_out, tiles, out=search.dd))
+    t_mask = timed(lambda: amber.dedisperse(search.delays, search.info, x, n_in, wl.n_out, tiles, out=search.dd,
+                                            keep=keep_dev))
+    adds = float(int(keep.sum())) * g.n_dm * wl.n_out
+    return {"metric": "masked dedispersion time", "unit": "s", "value": t_mask, "higher_is_better": False,
+            "rfi": {"workload": wl.name, "zapped_channels": int((keep == 0).sum()), "steps": steps,
+                    "dedisperse_ms": 1e3 * t_plain, "dedisperse_masked_ms": 1e3 * t_mask,
+                    "kept_adds_per_s": adds / t_mask}}
+
+
 def downsample_report(steps: int, warmup: int):
     """Decimating downsampling + S/N (the paper's smoothing definition) on the
     1536-channel beam: the ten series of the factor ladder in one fused launch,
@@ -581,6 +626,8 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
     ap.add_argument("--serve-rates", type=str, default="400,1600", help="offered chunks/s, comma separated")
+    ap.add_argument("--rfi", action="store_true",
+                    help="instead of the single-beam step: dedispersion with zapped channels beside plain")
     ap.add_argument("--downsample", action="store_true",
                     help="instead of the single-beam step: decimating downsampling + S/N over the factor ladder "
                          "on the dedispersed beam")
@@ -609,6 +656,9 @@ def main() -> int:
         return 0
     if args.ga_study:
         print(json.dumps(ga_study_report(args.study_seeds)))
+        return 0
+    if args.rfi:
+        print(json.dumps(rfi_report(args.steps, args.warmup)))
         return 0
     if args.downsample:
         print(json.dumps(downsample_report(args.steps, args.warmup)))

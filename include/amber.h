@@ -154,6 +154,18 @@ amber_status amber_dedisperse(const int32_t *d_delays, const amber_delay_info *i
                               int32_t *d_dd, int64_t dd_stride, int64_t n_out,
                               const amber_tiles *tiles, void *stream);
 
+/* amber_dedisperse with zapped channels (channels flagged because of radio
+ * frequency interference, which the paper's pipeline reads from an input
+ * file; Section 2 footnote):
+ *     dd[i][t] = sum over c with keep[c] != 0 of in[c][t + delay[i][c]]
+ * d_keep: device uint8 [n_chan], caller-owned; 0 = zapped.  A zapped row is
+ * never read.  Other arguments and errors as amber_dedisperse (AMBER_E_ARG if
+ * d_keep is NULL). */
+amber_status amber_dedisperse_masked(const int32_t *d_delays, const amber_delay_info *info,
+                                     const uint8_t *d_in, int64_t in_stride, int64_t n_in,
+                                     int32_t *d_dd, int64_t dd_stride, int64_t n_out,
+                                     const uint8_t *d_keep, const amber_tiles *tiles, void *stream);
+
 /* Sliding boxcar integration ("smoothing" of each dedispersed series):
  *     box[k][i][t] = sum over j < widths[k] of dd[i][t + j],
  *     t < n_out - widths[k] + 1

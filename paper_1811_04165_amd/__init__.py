@@ -113,8 +113,9 @@ def _tiles_ref(tiles: Optional[Tiles]):
 
 
 def dedisperse(delays, info: DelayInfo, x, n_in: int, n_out: int, tiles: Optional[Tiles] = None, out=None,
-               stream=None):
-    """delays: int32 CUDA [n_dm, n_chan]; x: uint8 CUDA [n_chan, stride].  Returns int32 [n_dm, n_out]."""
+               stream=None, keep=None):
+    """delays: int32 CUDA [n_dm, n_chan]; x: uint8 CUDA [n_chan, stride].  Returns int32 [n_dm, n_out].
+    keep: optional uint8 CUDA [n_chan], 0 = zapped channel (excluded from the sums)."""
     torch = _torch()
     _check_dev(delays, torch.int32, "delays", 2)
     _check_dev(x, torch.uint8, "x", 2)
@@ -127,6 +128,14 @@ def dedisperse(delays, info: DelayInfo, x, n_in: int, n_out: int, tiles: Optiona
     _check_dev(out, torch.int32, "out", 2)
     if out.shape[0] != info.n_dm or out.shape[1] < n_out:
         raise ValueError("out must be [n_dm, >= n_out]")
+    if keep is not None:
+        _check_dev(keep, torch.uint8, "keep", 1)
+        if keep.shape[0] != info.n_chan or not keep.is_contiguous():
+            raise ValueError("keep must be a contiguous uint8 [n_chan] tensor")
+        check(load().amber_dedisperse_masked(delays.data_ptr(), ctypes.byref(info), x.data_ptr(), x.stride(0),
+                                             int(n_in), out.data_ptr(), out.stride(0), int(n_out), keep.data_ptr(),
+                                             _tiles_ref(tiles), _stream_handle(stream)))
+        return out
     check(load().amber_dedisperse(delays.data_ptr(), ctypes.byref(info), x.data_ptr(), x.stride(0), int(n_in),
                                   out.data_ptr(), out.stride(0), int(n_out), _tiles_ref(tiles),
                                   _stream_handle(stream)))

@@ -137,6 +137,10 @@ SIGNATURES = [
     ("amber_dedisperse", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(DelayInfo), ctypes.c_void_p,
                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.POINTER(Tiles), ctypes.c_void_p]),
+    ("amber_dedisperse_masked", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(DelayInfo), ctypes.c_void_p,
+                                               ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                               ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(Tiles),
+                                               ctypes.c_void_p]),
     ("amber_integrate", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                        c_i32p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                        ctypes.POINTER(Tiles), ctypes.c_void_p]),

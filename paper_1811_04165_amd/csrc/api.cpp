@@ -263,11 +263,12 @@ amber_status amber_delay_table(const amber_geometry *g, int32_t *delays, amber_d
     return AMBER_OK;
 }
 
-amber_status amber_dedisperse(const int32_t *d_delays, const amber_delay_info *info, const uint8_t *d_in,
-                              int64_t in_stride, int64_t n_in, int32_t *d_dd, int64_t dd_stride, int64_t n_out,
-                              const amber_tiles *tiles, void *stream)
+namespace {
+
+amber_status dedisperse_common(const int32_t *d_delays, const amber_delay_info *info, const uint8_t *d_in,
+                               int64_t in_stride, int64_t n_in, int32_t *d_dd, int64_t dd_stride, int64_t n_out,
+                               const uint8_t *d_keep, const amber_tiles *tiles, void *stream)
 {
-    clear_error();
     if (!d_delays || !info || !d_in || !d_dd) return fail(AMBER_E_ARG, "NULL pointer argument");
     if (info->n_dm < 1 || info->n_chan < 1) return fail(AMBER_E_ARG, "info has n_dm=%d n_chan=%d", info->n_dm, info->n_chan);
     if (n_out < 0 || n_in < 0) return fail(AMBER_E_ARG, "n_out and n_in must be >= 0");
@@ -290,7 +291,26 @@ amber_status amber_dedisperse(const int32_t *d_delays, const amber_delay_info *i
     if (s != AMBER_OK) return s;
     if (n_out == 0) return AMBER_OK;
     return launch_dedisperse(plan, d_delays, info->n_dm, info->n_chan, d_in, in_stride, n_in, d_dd, dd_stride, n_out,
-                             (hipStream_t)stream);
+                             (hipStream_t)stream, d_keep);
+}
+
+}  // namespace
+
+amber_status amber_dedisperse(const int32_t *d_delays, const amber_delay_info *info, const uint8_t *d_in,
+                              int64_t in_stride, int64_t n_in, int32_t *d_dd, int64_t dd_stride, int64_t n_out,
+                              const amber_tiles *tiles, void *stream)
+{
+    clear_error();
+    return dedisperse_common(d_delays, info, d_in, in_stride, n_in, d_dd, dd_stride, n_out, nullptr, tiles, stream);
+}
+
+amber_status amber_dedisperse_masked(const int32_t *d_delays, const amber_delay_info *info, const uint8_t *d_in,
+                                     int64_t in_stride, int64_t n_in, int32_t *d_dd, int64_t dd_stride,
+                                     int64_t n_out, const uint8_t *d_keep, const amber_tiles *tiles, void *stream)
+{
+    clear_error();
+    if (!d_keep) return fail(AMBER_E_ARG, "d_keep is NULL");
+    return dedisperse_common(d_delays, info, d_in, in_stride, n_in, d_dd, dd_stride, n_out, d_keep, tiles, stream);
 }
 
 static amber_status check_rows(const void *p, int32_t n_dm, int64_t stride, int64_t n_out, const char *name)

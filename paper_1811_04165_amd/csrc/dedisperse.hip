@@ -63,6 +63,7 @@ __device__ __forceinline__ void tile_of_block(int id, int nx, int ny, int remap,
 
 struct StageArgs {
     const uint8_t *in;
+    const uint8_t *keep;
     int64_t in_stride, in_bytes;
     const int32_t *dfirst;
     int64_t t0;
@@ -72,6 +73,7 @@ struct StageArgs {
 // Loads the 20 input bytes (16 samples + 4 of lookahead) of staging item q of
 // the channel group starting at c0.  Dwords outside the buffer read as zero:
 // they lie past the last row's samples, so no output < n_out depends on them.
+// A zapped channel's items are zero, so it adds nothing to any sum.
 __device__ __forceinline__ void stage_load(const StageArgs &a, int c0, int q, uint32_t (&w)[5])
 {
 #pragma unroll
@@ -81,6 +83,7 @@ __device__ __forceinline__ void stage_load(const StageArgs &a, int c0, int q, ui
     const int it = q - j * a.items_per_row;
     const int c = c0 + j;
     if (c >= a.n_chan) return;
+    if (a.keep && a.keep[c] == 0) return;
     const int64_t g0 = (a.t0 + a.dfirst[c]) & ~(int64_t)3;
     const int64_t off = (int64_t)c * a.in_stride + g0 + 16 * (int64_t)it;
     if (off >= 0 && off + 20 <= a.in_bytes) {
@@ -159,6 +162,7 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
 
     StageArgs sa;
     sa.in = job.in;
+    sa.keep = job.keep;
     sa.in_stride = job.in_stride;
     sa.in_bytes = job.in_bytes;
     sa.dfirst = delays + (size_t)i0 * n_chan;
@@ -329,10 +333,11 @@ amber_status launch_dedisperse_jobs(const DedispPlan &p, const DedispJob *single
 
 amber_status launch_dedisperse(const DedispPlan &p, const int32_t *d_delays, int n_dm, int n_chan,
                                const uint8_t *d_in, int64_t in_stride, int64_t n_in, int32_t *d_dd,
-                               int64_t dd_stride, int64_t n_out, hipStream_t stream)
+                               int64_t dd_stride, int64_t n_out, hipStream_t stream, const uint8_t *d_keep)
 {
     (void)n_in;
-    const DedispJob j = make_dedisp_job(p, d_delays, n_dm, n_chan, d_in, in_stride, d_dd, dd_stride, n_out);
+    DedispJob j = make_dedisp_job(p, d_delays, n_dm, n_chan, d_in, in_stride, d_dd, dd_stride, n_out);
+    j.keep = d_keep;
     return launch_dedisperse_jobs(p, &j, nullptr, 1, (int64_t)j.tiles_t * j.tiles_dm, p.lds_bytes, stream);
 }
 

@@ -65,6 +65,7 @@ struct DedispJob {
     int32_t *dd;
     int64_t in_stride, in_bytes, dd_stride, n_out;
     int n_dm, n_chan, win, omax, tiles_t, tiles_dm, store_vec, block_start;
+    const uint8_t *keep;  // per-channel keep flags (0 = zapped), or NULL: every channel
 };
 
 // One beam's boxcar / S/N work (rows of job j occupy work-groups
@@ -126,7 +127,7 @@ private:
 // Launchers (device translation units).
 amber_status launch_dedisperse(const DedispPlan &p, const int32_t *d_delays, int n_dm, int n_chan,
                                const uint8_t *d_in, int64_t in_stride, int64_t n_in, int32_t *d_dd,
-                               int64_t dd_stride, int64_t n_out, hipStream_t stream);
+                               int64_t dd_stride, int64_t n_out, hipStream_t stream, const uint8_t *d_keep = nullptr);
 
 amber_status launch_integrate(const BoxcarPlan &p, const amber_tiles &t, const int32_t *d_dd, int n_dm,
                               int64_t dd_stride, int64_t n_out, const int32_t *widths, int n_widths,

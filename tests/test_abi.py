@@ -104,6 +104,11 @@ def test_device_calls_validate_before_launch():
     # NULL input
     rc = lib.amber_dedisperse(fake, ctypes.byref(info), None, 128, 120, fake, 100, 100, None, None)
     assert rc == -1
+    # masked: NULL keep flags, and the plain checks still apply
+    rc = lib.amber_dedisperse_masked(fake, ctypes.byref(info), fake, 128, 120, fake, 100, 100, None, None, None)
+    assert rc == -1 and b"d_keep" in lib.amber_last_error()
+    rc = lib.amber_dedisperse_masked(fake, ctypes.byref(info), fake, 128, 100, fake, 100, 95, fake, None, None)
+    assert rc == -2
     w = (ctypes.c_int32 * 2)(1, 200)
     rc = lib.amber_integrate_snr(fake, 4, 100, 100, w, 2, fake, fake, None, None)
     assert rc == -1 and b"widths" in lib.amber_last_error()
