@@ -13,6 +13,8 @@ numpy in / numpy out functions:
 * ``dedisperse``   -- brute-force one-step dedispersion (Section 5 names the
   one-step scheme; Section 2 the dedispersion kernel).
 * ``dedisperse_masked`` -- the same with zapped (RFI) channels excluded.
+* ``subband_delays``, ``subband_dedisperse`` -- the two-step subband scheme
+  (Section 2 footnote, Table 2).
 * ``boxcar``       -- sliding boxcar "smoothing" of each series (Section 2).
 * ``downsample``   -- decimating downsampling by a factor (Section 2, Table 2).
 * ``snr``          -- (max - mean) / population std per series (Section 2's
@@ -62,12 +64,19 @@ def _load():
                                               ctypes.c_int64, ctypes.c_int64, i32p, ctypes.c_int]
             lib.oracle_dedisperse_masked.argtypes = [i32p, ctypes.c_int, ctypes.c_int, u8p, ctypes.c_int64,
                                                      ctypes.c_int64, ctypes.c_int64, u8p, i32p, ctypes.c_int]
+            lib.oracle_subband_delays.argtypes = [ctypes.c_int, f64p, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                                  ctypes.c_double, i32p, i32p, i32p, i32p]
+            lib.oracle_subband_dedisperse.argtypes = [i32p, i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                      ctypes.c_int, u8p, ctypes.c_int64, ctypes.c_int64,
+                                                      ctypes.c_int64, i32p, ctypes.c_int]
             lib.oracle_boxcar.argtypes = [i32p, ctypes.c_int, ctypes.c_int64, ctypes.c_int, i64p,
                                           ctypes.c_int]
             lib.oracle_downsample.argtypes = [i32p, ctypes.c_int, ctypes.c_int64, ctypes.c_int, i64p,
                                               ctypes.c_int]
             lib.oracle_snr.argtypes = [i64p, ctypes.c_int, ctypes.c_int64, f64p, i32p, ctypes.c_int]
-            for f in (lib.oracle_delay_table, lib.oracle_dedisperse, lib.oracle_dedisperse_masked, lib.oracle_boxcar,
+            for f in (lib.oracle_delay_table, lib.oracle_dedisperse, lib.oracle_dedisperse_masked,
+                      lib.oracle_subband_delays, lib.oracle_subband_dedisperse, lib.oracle_boxcar,
                       lib.oracle_downsample,
                       lib.oracle_snr):
                 f.restype = ctypes.c_int
@@ -122,6 +131,45 @@ def dedisperse_masked(delays: np.ndarray, x: np.ndarray, n_in: int, n_out: int, 
                                           _ptr(out, ctypes.c_int32), int(threads))
     if rc != 0:
         raise ValueError("oracle_dedisperse_masked: a delay reads outside [0, n_in)")
+    return out
+
+
+def subband_delays(freq_mhz, t_samp_s: float, n_sub: int, n_coarse: int, coarse_first: float, coarse_step: float,
+                   n_fine: int, fine_first: float, fine_step: float):
+    """Two-step subband delay tables: (delay1 int32 [n_sub, n_coarse, n_chan / n_sub] (within each subband,
+    at the coarse DM), delay2 int32 [n_coarse, n_fine, n_sub] (subband references at the trial DM), max1, max2)."""
+    f = np.ascontiguousarray(freq_mhz, dtype=np.float64)
+    n_chan = f.shape[0]
+    if n_sub < 1 or n_chan % n_sub:
+        raise ValueError("n_sub must divide n_chan")
+    d1 = np.empty((n_sub, n_coarse, n_chan // n_sub), dtype=np.int32)
+    d2 = np.empty((n_coarse, n_fine, n_sub), dtype=np.int32)
+    m1, m2 = ctypes.c_int32(), ctypes.c_int32()
+    rc = _load().oracle_subband_delays(n_chan, _ptr(f, ctypes.c_double), float(t_samp_s), int(n_sub), int(n_coarse),
+                                       float(coarse_first), float(coarse_step), int(n_fine), float(fine_first),
+                                       float(fine_step), _ptr(d1, ctypes.c_int32), _ptr(d2, ctypes.c_int32),
+                                       ctypes.byref(m1), ctypes.byref(m2))
+    if rc != 0:
+        raise ValueError("oracle_subband_delays: bad arguments")
+    return d1, d2, m1.value, m2.value
+
+
+def subband_dedisperse(delay1: np.ndarray, delay2: np.ndarray, x: np.ndarray, n_in: int, n_out: int,
+                       threads: int = 0) -> np.ndarray:
+    """dd[j n_fine + k][t] = sum over subbands s and their channels c of x[c][t + delay2[j,k,s] + delay1[s,j,c']]."""
+    d1 = np.ascontiguousarray(delay1, dtype=np.int32)
+    d2 = np.ascontiguousarray(delay2, dtype=np.int32)
+    xa = np.ascontiguousarray(x, dtype=np.uint8)
+    n_sub, n_coarse, m = d1.shape
+    n_fine = d2.shape[1]
+    if d2.shape != (n_coarse, n_fine, n_sub) or xa.shape[0] != n_sub * m:
+        raise ValueError("inconsistent subband tables and input")
+    out = np.empty((n_coarse * n_fine, n_out), dtype=np.int32)
+    rc = _load().oracle_subband_dedisperse(_ptr(d1, ctypes.c_int32), _ptr(d2, ctypes.c_int32), n_sub * m, n_sub,
+                                           n_coarse, n_fine, _ptr(xa, ctypes.c_uint8), xa.shape[1], int(n_in),
+                                           int(n_out), _ptr(out, ctypes.c_int32), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_subband_dedisperse: a delay reads outside [0, n_in)")
     return out
 
 

@@ -152,6 +152,112 @@ int oracle_dedisperse_masked(const int32_t *delays, int n_dm, int n_chan,
 }
 
 /*
+ * Two-step subband dedispersion (the pipeline's dedispersion, Section 2 and
+ * its footnote; Table 2 SUBBANDS, SUBBANDING_DMS / _DM_FIRST / _DM_STEP and
+ * DMS / DM_FIRST / DM_STEP).  Subband s holds channels s*m .. s*m + m - 1
+ * (m = n_chan / n_sub); its reference frequency f_ref(s) is the largest
+ * frequency among them, f_top the largest of all.
+ *
+ *   coarse DM_j  = cdm_first + j * cdm_step,            j < n_coarse
+ *   trial DM_jk  = DM_j + fdm_first + k * fdm_step,      k < n_fine
+ *   delay1[s][j][c'] = round(K DM_j  (1/f_c^2      - 1/f_ref(s)^2) / t_samp),  c = s m + c'
+ *   delay2[j][k][s]  = round(K DM_jk (1/f_ref(s)^2 - 1/f_top^2)    / t_samp)
+ *
+ * max1 / max2 receive the largest entries.
+ */
+int oracle_subband_delays(int n_chan, const double *freq, double t_samp_s, int n_sub, int n_coarse,
+                          double cdm_first, double cdm_step, int n_fine, double fdm_first, double fdm_step,
+                          int32_t *delay1, int32_t *delay2, int32_t *max1, int32_t *max2)
+{
+    if (n_chan <= 0 || n_sub <= 0 || n_chan % n_sub != 0 || n_coarse <= 0 || n_fine <= 0 ||
+        !(t_samp_s > 0.0) || !freq || !delay1 || !delay2)
+        return -1;
+    const int m = n_chan / n_sub;
+    double f_top = freq[0];
+    for (int c = 0; c < n_chan; ++c) {
+        if (!(freq[c] > 0.0))
+            return -1;
+        if (freq[c] > f_top)
+            f_top = freq[c];
+    }
+    int32_t m1 = INT32_MIN, m2 = INT32_MIN;
+    for (int s = 0; s < n_sub; ++s) {
+        double f_ref = freq[s * m];
+        for (int c = s * m; c < (s + 1) * m; ++c)
+            if (freq[c] > f_ref)
+                f_ref = freq[c];
+        for (int j = 0; j < n_coarse; ++j) {
+            double dm = cdm_first + (double)j * cdm_step;
+            for (int cl = 0; cl < m; ++cl) {
+                double f = freq[s * m + cl];
+                double x = ((ORACLE_KDM * dm) * (1.0 / (f * f) - 1.0 / (f_ref * f_ref))) / t_samp_s;
+                int32_t d = (int32_t)llround(x);
+                delay1[((size_t)s * n_coarse + j) * m + cl] = d;
+                if (d > m1)
+                    m1 = d;
+            }
+            for (int k = 0; k < n_fine; ++k) {
+                double dmk = dm + fdm_first + (double)k * fdm_step;
+                double x = ((ORACLE_KDM * dmk) * (1.0 / (f_ref * f_ref) - 1.0 / (f_top * f_top))) / t_samp_s;
+                int32_t d = (int32_t)llround(x);
+                delay2[((size_t)j * n_fine + k) * n_sub + s] = d;
+                if (d > m2)
+                    m2 = d;
+            }
+        }
+    }
+    if (max1)
+        *max1 = m1;
+    if (max2)
+        *max2 = m2;
+    return 0;
+}
+
+/*
+ * The two steps composed, evaluated directly (no intermediate subband sums):
+ *
+ *   dd[j n_fine + k][t] = sum over s, c in s of in[c][t + delay2[j][k][s] + delay1[s][j][c']]
+ *
+ * for t < n_out; every index must stay inside [0, n_in).
+ */
+int oracle_subband_dedisperse(const int32_t *delay1, const int32_t *delay2, int n_chan, int n_sub,
+                              int n_coarse, int n_fine, const uint8_t *in, int64_t stride, int64_t n_in,
+                              int64_t n_out, int32_t *dd, int n_threads)
+{
+    if (n_chan <= 0 || n_sub <= 0 || n_chan % n_sub != 0 || n_coarse <= 0 || n_fine <= 0 || n_out < 0 ||
+        stride < n_in)
+        return -1;
+    const int m = n_chan / n_sub;
+    for (int j = 0; j < n_coarse; ++j)
+        for (int k = 0; k < n_fine; ++k)
+            for (int s = 0; s < n_sub; ++s)
+                for (int cl = 0; cl < m; ++cl) {
+                    int64_t d = (int64_t)delay2[((size_t)j * n_fine + k) * n_sub + s] +
+                                delay1[((size_t)s * n_coarse + j) * m + cl];
+                    if (d < 0 || n_out + d > n_in)
+                        return -1;
+                }
+    int nt = oracle_threads(n_threads);
+    #pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
+    for (int jk = 0; jk < n_coarse * n_fine; ++jk) {
+        const int j = jk / n_fine, k = jk % n_fine;
+        for (int64_t t = 0; t < n_out; ++t) {
+            int32_t sum = 0;
+            for (int s = 0; s < n_sub; ++s) {
+                const int64_t d2 = delay2[((size_t)j * n_fine + k) * n_sub + s];
+                for (int cl = 0; cl < m; ++cl) {
+                    const int c = s * m + cl;
+                    const int64_t d1 = delay1[((size_t)s * n_coarse + j) * m + cl];
+                    sum += in[(size_t)c * stride + (size_t)(t + d2 + d1)];
+                }
+            }
+            dd[(size_t)jk * n_out + t] = sum;
+        }
+    }
+    return 0;
+}
+
+/*
  * Sliding boxcar integration of one dedispersed series ("smoothing" of the
  * dedispersed time series, Section 2), for a single width w:
  *

@@ -200,6 +200,74 @@ def test_dedisperse_masked_pins():
         assert np.array_equal(got[i], x[5, delays[i, 5]:delays[i, 5] + 150].astype(np.int32))
 
 
+def _subband_case(n_chan, n_sub, n_coarse, cstep, n_fine, fstep, n_out, seed):
+    g = workloads.Geometry(n_chan=n_chan, n_dm=1, dm_first=0.0, dm_step=1.0)
+    d1, d2, m1, m2 = oracle.subband_delays(g.freqs(), g.t_samp_s, n_sub, n_coarse, 0.0, cstep, n_fine, 0.0, fstep)
+    n_in = n_out + m1 + m2
+    x = np.random.default_rng(seed).integers(0, 256, size=(n_chan, n_in + 3)).astype(np.uint8)
+    return g, d1, d2, m1, m2, x, n_in
+
+
+def test_subband_reduces_to_brute_force():
+    """One channel per subband: the subband shift is the full shift at the
+    trial DM, so the scheme is brute force on the fine grid.  One subband:
+    the reference is the top channel, so every fine trial equals brute force
+    at its coarse DM."""
+    n_out = 300
+    g, d1, d2, m1, m2, x, n_in = _subband_case(24, 24, 3, 6.0, 4, 1.5, n_out, 51)
+    assert not d1.any()
+    bf, mx = oracle.delay_table(g.freqs(), g.t_samp_s, 12, 0.0, 1.5)
+    assert np.array_equal(d2.reshape(12, 24), bf)
+    assert np.array_equal(oracle.subband_dedisperse(d1, d2, x, n_in, n_out), oracle.dedisperse(bf, x, n_in, n_out))
+    g, d1, d2, m1, m2, x, n_in = _subband_case(24, 1, 3, 6.0, 4, 1.5, n_out, 52)
+    assert not d2.any()
+    coarse, _ = oracle.delay_table(g.freqs(), g.t_samp_s, 3, 0.0, 6.0)
+    assert np.array_equal(d1[0], coarse)
+    got = oracle.subband_dedisperse(d1, d2, x, n_in, n_out).reshape(3, 4, n_out)
+    ref = oracle.dedisperse(coarse, x, n_in, n_out)
+    for k in range(4):
+        assert np.array_equal(got[:, k], ref)
+
+
+def test_subband_delay_error_bound_and_impulse():
+    """The composed shift differs from the exact one only by the intra-subband
+    residual K (DM_jk - DM_j) (1/f_c^2 - 1/f_ref^2) / t_samp plus rounding;
+    DM 0 is the channel sum; an impulse lands where the composed shifts say."""
+    n_chan, n_sub, n_coarse, cstep, n_fine, fstep = 64, 8, 5, 8.0, 8, 1.0
+    g = workloads.Geometry(n_chan=n_chan, n_dm=1, dm_first=0.0, dm_step=1.0)
+    f = g.freqs()
+    d1, d2, m1, m2 = oracle.subband_delays(f, g.t_samp_s, n_sub, n_coarse, 0.0, cstep, n_fine, 0.0, fstep)
+    K = 4.148808e3
+    m = n_chan // n_sub
+    for j in range(n_coarse):
+        for k in range(n_fine):
+            dm, dmk = j * cstep, j * cstep + k * fstep
+            for c in range(n_chan):
+                s, cl = divmod(c, m)
+                fref = f[s * m:(s + 1) * m].max()
+                exact = K * dmk * (1 / f[c] ** 2 - 1 / f.max() ** 2) / g.t_samp_s
+                resid = K * (dmk - dm) * (1 / f[c] ** 2 - 1 / fref ** 2) / g.t_samp_s
+                assert abs(d1[s, j, cl] + d2[j, k, s] - exact) <= resid + 1.0 + 1e-9
+    n_out = 200
+    n_in = n_out + m1 + m2
+    x = np.random.default_rng(53).integers(0, 256, size=(n_chan, n_in)).astype(np.uint8)
+    dd = oracle.subband_dedisperse(d1, d2, x, n_in, n_out)
+    assert np.array_equal(dd[0], x[:, :n_out].astype(np.int64).sum(axis=0))
+    imp = np.zeros((n_chan, n_in), np.uint8)
+    imp[17, 150] = 1
+    dd = oracle.subband_dedisperse(d1, d2, imp, n_in, n_out).reshape(n_coarse, n_fine, n_out)
+    s, cl = divmod(17, m)
+    for j in range(n_coarse):
+        for k in range(n_fine):
+            t = 150 - d2[j, k, s] - d1[s, j, cl]
+            want = np.zeros(n_out, np.int32)
+            if 0 <= t < n_out:
+                want[t] = 1
+            assert np.array_equal(dd[j, k], want)
+    with pytest.raises(ValueError):
+        oracle.subband_delays(f, g.t_samp_s, 7, 2, 0.0, 1.0, 2, 0.0, 0.5)     # 7 does not divide 64
+
+
 def test_boxcar_identity_doubling_and_convolve():
     rng = np.random.default_rng(21)
     dd = rng.integers(0, 400000, size=(5, 300)).astype(np.int32)
