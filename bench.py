@@ -601,6 +601,120 @@ def downsample_report(steps: int, warmup: int):
                            "pulses_with_snr_above_8": found}}
 
 
+SUBBAND_GRIDS = {
+    # the 1536-channel beam's own 2048 trials (0..1023.5 step 0.5) from 32 subbands
+    "beam-grid": (32, 128, 0.0, 8.0, 16, 0.0, 0.5),
+    # Table 2's subbanding grid: 2048 coarse DMs step 2.4, 24 fine DMs step 0.1
+    "table2-grid": (32, 2048, 0.0, 2.4, 24, 0.0, 0.1),
+}
+
+
+def subband_report(steps: int, warmup: int, grid_names, bf_steps: int = 3):
+    """Two-step subband dedispersion on the 1536-channel, 12208-sample beam,
+    beside brute-force dedispersion of the same trials: time, throughput, and
+    the S/N of injected pulses under both (the scheme's approximation loss)."""
+    import numpy as np
+    import torch
+    import paper_1811_04165_amd as amber
+    import workloads
+    wl = workloads.beam()
+    g = wl.geom
+    f = g.freqs()
+    n_out = wl.n_out
+
+    def timed(fn, n, w):
+        for _ in range(w):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        b.record()
+        torch.cuda.synchronize()
+        gc.collect()
+        gc.disable()
+        a.record()
+        for _ in range(n):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        gc.enable()
+        return a.elapsed_time(b) / 1e3 / n
+
+    out = {}
+    for name in grid_names:
+        grid = SUBBAND_GRIDS[name]
+        n_sub, nc, cf, cs, nf, ff, fs = grid
+        d1, d2, info = amber.subband_delay_tables(f, g.t_samp_s, *grid)
+        n_dm = nc * nf
+        # brute force over the same trial DMs (both grids are dyadic-free but
+        # DM_jk = (cf + j cs + ff) + k fs is what both tables use)
+        dms = np.array([(cf + j * cs + ff) + k * fs for j in range(nc) for k in range(nf)])
+        bd = np.empty((n_dm, g.n_chan), np.int32)
+        bmax = 0
+        for i0 in range(0, n_dm, 4096):  # one-row tables keep each trial's DM exactly as above
+            for i in range(i0, min(n_dm, i0 + 4096)):
+                row, info_i = amber.delay_table(f, g.t_samp_s, 1, float(dms[i]), 0.0)
+                bd[i] = row[0]
+                bmax = max(bmax, info_i.max_delay)
+        steps_bf = np.diff(bd, axis=0).max() if n_dm > 1 else 0
+        binfo = amber.DelayInfo(n_dm=n_dm, n_chan=g.n_chan, max_delay=int(bmax), max_step=int(steps_bf))
+        n_in = n_out + max(info.max_delay, bmax)
+        rng = np.random.default_rng([11, nc])
+        pulses = []
+        x = workloads.noise(g.n_chan, n_in, workloads.padded_stride(n_in), seed=12)
+        for k in range(5):
+            i = int(rng.integers(0, n_dm))
+            w = int(rng.choice([1, 2, 4, 8, 16, 32]))
+            t0 = 1024 + 2048 * k
+            workloads.inject(x, bd[i], t0=t0, width=w, amp=40)
+            pulses.append((i, w, t0))
+        xd = torch.from_numpy(x).cuda()
+        d1d, d2d = torch.from_numpy(d1).cuda(), torch.from_numpy(d2).cuda()
+        n1 = n_out + info.max_delay2
+        work = torch.empty((n_sub * nc, (n1 + 63) // 64 * 64), dtype=torch.uint16, device="cuda")
+        dd_sb = torch.empty((n_dm, n_out), dtype=torch.int32, device="cuda")
+        print("[bench] subband %s: %d trials, n_in %d" % (name, n_dm, n_in), file=sys.stderr, flush=True)
+        t_sb = timed(lambda: amber.subband_dedisperse(d1d, d2d, info, xd, n_in, n_out, out=dd_sb, work=work),
+                     steps, warmup)
+        widths = wl.widths
+        snr_sb = torch.empty((len(widths), n_dm), dtype=torch.float32, device="cuda")
+        pk = torch.empty((len(widths), n_dm), dtype=torch.int32, device="cuda")
+        t_snr = timed(lambda: amber.integrate_snr(dd_sb, n_out, widths, out=(snr_sb, pk)), steps, warmup)
+        s_sb = snr_sb.cpu().numpy()
+        del work
+        # brute force on the same trials, same input, same output buffer shape
+        bdd = torch.from_numpy(bd).cuda()
+        dd_bf = torch.empty((n_dm, n_out), dtype=torch.int32, device="cuda")
+        print("[bench] brute force %s" % name, file=sys.stderr, flush=True)
+        t_bf = timed(lambda: amber.dedisperse(bdd, binfo, xd, n_in, n_out, out=dd_bf), bf_steps, 1)
+        amber.integrate_snr(dd_bf, n_out, widths, out=(snr_sb, pk))
+        s_bf = snr_sb.cpu().numpy()
+        del bdd, dd_bf, dd_sb
+        torch.cuda.empty_cache()
+        loss = []
+        for i, w, t0 in pulses:
+            wi = list(widths).index(w)
+            lo, hi = max(0, i - 2), min(n_dm, i + 3)
+            a, b = float(s_sb[wi, lo:hi].max()), float(s_bf[wi, lo:hi].max())
+            loss.append({"trial": i, "dm": float(dms[i]), "width": w, "snr_subband": a, "snr_brute_force": b,
+                         "ratio": a / b})
+        adds1 = float(nc) * g.n_chan * n1
+        adds2 = float(nc) * nf * n_sub * n_out
+        out[name] = {
+            "grid": {"subbands": n_sub, "coarse": [nc, cf, cs], "fine": [nf, ff, fs]}, "n_dm": n_dm,
+            "n_in": n_in, "info": {k: getattr(info, k) for k, _ in info._fields_},
+            "subband_dedisperse_ms": 1e3 * t_sb, "brute_force_dedisperse_ms": 1e3 * t_bf,
+            "speedup_vs_brute_force": t_bf / t_sb, "integrate_snr_ms": 1e3 * t_snr,
+            "dm_trial_samples_per_s": n_dm * n_out / t_sb,
+            "path_dm_trial_samples_per_s": n_dm * n_out / (t_sb + t_snr),
+            "sample_adds": {"step1": adds1, "step2": adds2, "brute_force": float(n_dm) * g.n_chan * n_out},
+            "alu_frac_both_steps": (adds1 + adds2) / t_sb / 1e12 / ALU_PEAK_TOPS,
+            "snr_loss": loss,
+        }
+    first = out[grid_names[0]]
+    return {"metric": "subband dedispersion throughput", "unit": UNIT, "value": first["dm_trial_samples_per_s"],
+            "higher_is_better": True, "workload": wl.name, "steps": steps, "subband": out}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -628,6 +742,9 @@ def main() -> int:
     ap.add_argument("--serve-rates", type=str, default="400,1600", help="offered chunks/s, comma separated")
     ap.add_argument("--rfi", action="store_true",
                     help="instead of the single-beam step: dedispersion with zapped channels beside plain")
+    ap.add_argument("--subband", type=str, default="", metavar="GRIDS",
+                    help="two-step subband dedispersion vs brute force on the beam, for the comma-separated "
+                         "grids beam-grid, table2-grid")
     ap.add_argument("--downsample", action="store_true",
                     help="instead of the single-beam step: decimating downsampling + S/N over the factor ladder "
                          "on the dedispersed beam")
@@ -662,6 +779,9 @@ def main() -> int:
         return 0
     if args.downsample:
         print(json.dumps(downsample_report(args.steps, args.warmup)))
+        return 0
+    if args.subband:
+        print(json.dumps(subband_report(args.steps, args.warmup, [n for n in args.subband.split(",") if n])))
         return 0
     if args.serve:
         rates = [float(r) for r in args.serve_rates.split(",") if r]

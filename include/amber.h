@@ -166,6 +166,87 @@ amber_status amber_dedisperse_masked(const int32_t *d_delays, const amber_delay_
                                      int32_t *d_dd, int64_t dd_stride, int64_t n_out,
                                      const uint8_t *d_keep, const amber_tiles *tiles, void *stream);
 
+/* Two-step subband dedispersion (Section 2 footnote; Table 2's subbanding
+ * parameters: subbands, subbanding DMs and DMs per subbanding DM, each with
+ * first and step).
+ *
+ * The channels are split into n_subbands consecutive groups of
+ * m = n_chan / n_subbands channels.  Step one dedisperses every subband at the
+ * coarse DMs DM_j = coarse_first + j * coarse_step, relative to the
+ * subband's highest frequency f_ref(s); step two shifts and sums the subbands
+ * for the fine DMs DM_jk = DM_j + fine_first + k * fine_step, relative to
+ * f_top.  Trial j * n_fine + k is
+ *     dd[j n_fine + k][t] = sum over s, c' < m of in[s m + c'][t + D2 + D1]
+ *     D1 = round(4.148808e3 * DM_j  * (f_c^-2      - f_ref(s)^-2) / t_samp)
+ *     D2 = round(4.148808e3 * DM_jk * (f_ref(s)^-2 - f_top^-2)    / t_samp)
+ * (rounding half away from zero, FP64, DM_jk evaluated as
+ * (DM_j + fine_first) + k * fine_step).  It approximates brute-force
+ * dedispersion at DM_jk: inside a subband the channels are aligned for DM_j. */
+typedef struct {
+    int32_t n_chan;
+    const double *freq_mhz;   /* [n_chan] channel frequencies, > 0; subband s is
+                                 channels [s m, (s + 1) m) in this order */
+    double t_samp_s;          /* sampling time, seconds, > 0 */
+    int32_t n_subbands;       /* divides n_chan; n_chan / n_subbands <= 257 */
+    int32_t n_coarse;         /* subbanding (coarse) DM trials, >= 1 */
+    double coarse_first;      /* >= 0 */
+    double coarse_step;       /* >= 0 */
+    int32_t n_fine;           /* DM trials per coarse DM, >= 1 */
+    double fine_first;        /* coarse_first + fine_first >= 0 */
+    double fine_step;         /* >= 0 */
+} amber_subband_geometry;
+
+/* Summary of the two subband tables (amber_subband_delay_tables). */
+typedef struct {
+    int32_t n_chan, n_subbands, n_coarse, n_fine;
+    int32_t max_delay1;  /* largest delay1 entry */
+    int32_t max_step1;   /* largest delay1[s][j+1][c'] - delay1[s][j][c'] */
+    int32_t max_delay2;  /* largest delay2 entry */
+    int32_t max_step2;   /* largest delay2[j][k+1][s] - delay2[j][k][s] */
+    int32_t max_delay;   /* max_delay1 + max_delay2: the input samples needed
+                            beyond n_out */
+} amber_subband_info;
+
+/* The subband scheme's delays as the device path uses them (host, FP64).
+ * Each coarse DM's smallest step-two shift of subband s, B[j][s] = D2 at
+ * k = 0, is moved into step one, so that step one computes only the samples
+ * step two reads:
+ *     delay1[s][j][c'] = D1(s, j, c') + B[j][s]     int32 [n_subbands][n_coarse][m]
+ *     delay2[j][k][s]  = D2(j, k, s)  - B[j][s]     int32 [n_coarse][n_fine][n_subbands]
+ * Sums delay1 + delay2 are the scheme's composed delays exactly.  All entries
+ * are >= 0 and never decrease along j (delay1) or k (delay2).
+ * delay1, delay2: caller-owned host buffers, fully overwritten.
+ * info: filled (may be NULL).
+ * Errors: AMBER_E_ARG for NULL pointers, sizes < 1, n_subbands not dividing
+ * n_chan, more than 257 channels per subband (step-one sums are stored in 16
+ * bits), frequencies <= 0, t_samp <= 0, negative DMs or steps, delays beyond
+ * int32. */
+amber_status amber_subband_delay_tables(const amber_subband_geometry *g, int32_t *delay1, int32_t *delay2,
+                                        amber_subband_info *info);
+
+/* Two-step subband dedispersion on the device (formula above).
+ * d_delay1, d_delay2: device copies of amber_subband_delay_tables' tables.
+ * d_in:   device uint8 [n_chan][in_stride] as amber_dedisperse;
+ *         n_in >= n_out + info->max_delay.
+ * d_work: device uint16 [n_subbands][n_coarse][work_stride], caller-owned
+ *         scratch; receives step one's sums: row (s, j) holds
+ *         sum over c' of in[s m + c'][t + delay1[s][j][c']] for
+ *         t < n_out + info->max_delay2 (later columns are not written).
+ *         work_stride >= n_out + max_delay2, even; d_work 4-byte aligned.
+ * d_dd:   device int32 [n_coarse * n_fine][dd_stride], dd_stride >= n_out.
+ * d_keep: device uint8 [n_chan] keep flags as amber_dedisperse_masked, or
+ *         NULL for every channel.
+ * tiles1: step one's tiles (dedispersion genes), tiles2: step two's (its
+ *         kernels take samples_per_thread 8 or 16 and channel_unroll >= 4);
+ *         NULL picks a valid default for each.
+ * Asynchronous on `stream` (two launches).  Errors: AMBER_E_ARG, AMBER_E_SHAPE
+ * (strides, lengths, alignment), AMBER_E_CONFIG (tiles), AMBER_E_DEVICE. */
+amber_status amber_subband_dedisperse(const int32_t *d_delay1, const int32_t *d_delay2,
+                                      const amber_subband_info *info, const uint8_t *d_in, int64_t in_stride,
+                                      int64_t n_in, uint16_t *d_work, int64_t work_stride, int32_t *d_dd,
+                                      int64_t dd_stride, int64_t n_out, const uint8_t *d_keep,
+                                      const amber_tiles *tiles1, const amber_tiles *tiles2, void *stream);
+
 /* Sliding boxcar integration ("smoothing" of each dedispersed series):
  *     box[k][i][t] = sum over j < widths[k] of dd[i][t + j],
  *     t < n_out - widths[k] + 1

@@ -25,13 +25,14 @@ from typing import Optional, Sequence
 import numpy as np
 
 from ._lib import (AMBER_E_TIMEOUT, AMBER_MAX_WIDTHS, FITNESS_FN, Beam, ChunkResult, PendingChunk, SEARCH_KINDS,
-                   AmberError, DelayInfo, Geometry, ServerConfig, ServerStats, StreamBeam, Tiles, TuneParams, TuneResult,
-                   TuneSpace, check, load)
+                   AmberError, DelayInfo, Geometry, ServerConfig, ServerStats, StreamBeam, SubbandGeometry, SubbandInfo,
+                   Tiles, TuneParams, TuneResult, TuneSpace, check, load)
 
 __all__ = ["AmberError", "DelayInfo", "Tiles", "TuneSpace", "TuneParams", "TuneResult", "default_space",
            "space_size", "tune_params", "search_tiles", "tune", "Batch", "default_tiles", "make_tiles", "delay_table", "dedisperse",
            "integrate", "snr", "integrate_snr", "downsample", "downsample_snr", "validate_tiles", "auto_tiles", "version", "Search", "Server",
-           "chunk_span", "admit", "server_config", "server_clock"]
+           "chunk_span", "admit", "server_config", "server_clock", "SubbandInfo", "subband_delay_tables",
+           "subband_dedisperse"]
 
 load()  # fail loudly at import if the native library is missing
 
@@ -139,6 +140,69 @@ def dedisperse(delays, info: DelayInfo, x, n_in: int, n_out: int, tiles: Optiona
     check(load().amber_dedisperse(delays.data_ptr(), ctypes.byref(info), x.data_ptr(), x.stride(0), int(n_in),
                                   out.data_ptr(), out.stride(0), int(n_out), _tiles_ref(tiles),
                                   _stream_handle(stream)))
+    return out
+
+
+def subband_delay_tables(freq_mhz, t_samp_s: float, n_subbands: int, n_coarse: int, coarse_first: float,
+                         coarse_step: float, n_fine: int, fine_first: float, fine_step: float):
+    """FP64 host tables of the two-step subband scheme, with each coarse DM's k = 0 step-two shift
+    moved into step one.  Returns (delay1 int32 [n_sub, n_coarse, m], delay2 int32 [n_coarse, n_fine, n_sub],
+    SubbandInfo)."""
+    f = np.ascontiguousarray(freq_mhz, dtype=np.float64)
+    g = SubbandGeometry(n_chan=f.size, freq_mhz=f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        t_samp_s=float(t_samp_s), n_subbands=int(n_subbands), n_coarse=int(n_coarse),
+                        coarse_first=float(coarse_first), coarse_step=float(coarse_step), n_fine=int(n_fine),
+                        fine_first=float(fine_first), fine_step=float(fine_step))
+    m = f.size // max(int(n_subbands), 1)
+    d1 = np.empty((max(int(n_subbands), 0), max(int(n_coarse), 0), m), dtype=np.int32)
+    d2 = np.empty((max(int(n_coarse), 0), max(int(n_fine), 0), max(int(n_subbands), 0)), dtype=np.int32)
+    info = SubbandInfo()
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    check(load().amber_subband_delay_tables(ctypes.byref(g), d1.ctypes.data_as(i32), d2.ctypes.data_as(i32),
+                                            ctypes.byref(info)))
+    return d1, d2, info
+
+
+def subband_dedisperse(delay1, delay2, info: SubbandInfo, x, n_in: int, n_out: int, tiles1: Optional[Tiles] = None,
+                       tiles2: Optional[Tiles] = None, out=None, work=None, keep=None, stream=None):
+    """Two-step subband dedispersion.  delay1/delay2: int32 CUDA tables from subband_delay_tables; x: uint8 CUDA
+    [n_chan, stride].  work: optional uint16 CUDA [n_sub * n_coarse, >= n_out + max_delay2] (even row stride) for
+    step one's sums.  Returns int32 [n_coarse * n_fine, n_out] (trial j * n_fine + k)."""
+    torch = _torch()
+    _check_dev(delay1, torch.int32, "delay1", 3)
+    _check_dev(delay2, torch.int32, "delay2", 3)
+    _check_dev(x, torch.uint8, "x", 2)
+    n_sub, nc, nf = info.n_subbands, info.n_coarse, info.n_fine
+    if n_sub < 1 or info.n_chan % n_sub:
+        raise ValueError("info has an invalid subband count")
+    m = info.n_chan // n_sub
+    if not delay1.is_contiguous() or tuple(delay1.shape) != (n_sub, nc, m):
+        raise ValueError("delay1 must be contiguous [n_sub, n_coarse, n_chan / n_sub]")
+    if not delay2.is_contiguous() or tuple(delay2.shape) != (nc, nf, n_sub):
+        raise ValueError("delay2 must be contiguous [n_coarse, n_fine, n_sub]")
+    if x.shape[0] != info.n_chan or x.shape[1] < n_in:
+        raise ValueError("x must be [n_chan, >= n_in]")
+    n1 = int(n_out) + info.max_delay2
+    if work is None:
+        work = torch.empty((n_sub * nc, (n1 + 63) // 64 * 64), dtype=torch.uint16, device=x.device)
+    _check_dev(work, torch.uint16, "work", 2)
+    if work.shape[0] != n_sub * nc or work.shape[1] < n1 or work.stride(0) % 2:
+        raise ValueError("work must be uint16 [n_sub * n_coarse, >= n_out + max_delay2] with an even row stride")
+    if out is None:
+        out = torch.empty((nc * nf, n_out), dtype=torch.int32, device=x.device)
+    _check_dev(out, torch.int32, "out", 2)
+    if out.shape[0] != nc * nf or out.shape[1] < n_out:
+        raise ValueError("out must be [n_coarse * n_fine, >= n_out]")
+    kp = None
+    if keep is not None:
+        _check_dev(keep, torch.uint8, "keep", 1)
+        if keep.shape[0] != info.n_chan or not keep.is_contiguous():
+            raise ValueError("keep must be a contiguous uint8 [n_chan] tensor")
+        kp = keep.data_ptr()
+    check(load().amber_subband_dedisperse(delay1.data_ptr(), delay2.data_ptr(), ctypes.byref(info), x.data_ptr(),
+                                          x.stride(0), int(n_in), work.data_ptr(), work.stride(0), out.data_ptr(),
+                                          out.stride(0), int(n_out), kp, _tiles_ref(tiles1), _tiles_ref(tiles2),
+                                          _stream_handle(stream)))
     return out
 
 

@@ -27,6 +27,21 @@ class DelayInfo(ctypes.Structure):
             self.n_dm, self.n_chan, self.max_delay, self.max_step)
 
 
+class SubbandGeometry(ctypes.Structure):
+    _fields_ = [("n_chan", ctypes.c_int32), ("freq_mhz", c_f64p), ("t_samp_s", ctypes.c_double),
+                ("n_subbands", ctypes.c_int32), ("n_coarse", ctypes.c_int32), ("coarse_first", ctypes.c_double),
+                ("coarse_step", ctypes.c_double), ("n_fine", ctypes.c_int32), ("fine_first", ctypes.c_double),
+                ("fine_step", ctypes.c_double)]
+
+
+class SubbandInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("n_chan", "n_subbands", "n_coarse", "n_fine", "max_delay1",
+                                              "max_step1", "max_delay2", "max_step2", "max_delay")]
+
+    def __repr__(self):
+        return "SubbandInfo(%s)" % ", ".join("%s=%d" % (n, getattr(self, n)) for n, _ in self._fields_)
+
+
 class Tiles(ctypes.Structure):
     _fields_ = [("threads_per_dm", ctypes.c_int32), ("samples_per_thread", ctypes.c_int32),
                 ("dms_per_block", ctypes.c_int32), ("channel_unroll", ctypes.c_int32),
@@ -141,6 +156,13 @@ SIGNATURES = [
                                                ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                                ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(Tiles),
                                                ctypes.c_void_p]),
+    ("amber_subband_delay_tables", ctypes.c_int, [ctypes.POINTER(SubbandGeometry), c_i32p, c_i32p,
+                                                  ctypes.POINTER(SubbandInfo)]),
+    ("amber_subband_dedisperse", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(SubbandInfo),
+                                                ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                                ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                                ctypes.c_void_p, ctypes.POINTER(Tiles), ctypes.POINTER(Tiles),
+                                                ctypes.c_void_p]),
     ("amber_integrate", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                        c_i32p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                        ctypes.POINTER(Tiles), ctypes.c_void_p]),

@@ -12,9 +12,6 @@ namespace amber {
 namespace {
 thread_local std::string g_error;
 
-// Cold-plasma dispersion constant, s MHz^2 / (pc cm^-3).
-constexpr double kDispersion = 4.148808e3;
-
 amber_tiles make_default_tiles()
 {
     amber_tiles t{};
@@ -57,24 +54,32 @@ const amber_tiles &default_tiles()
 // The default configuration, shrunk (channel_unroll first, then
 // dms_per_block, then the time tile) until its dedispersion tile is valid for
 // this delay table.
-amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out)
+amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out, int in_u16, const amber_tiles *start)
 {
-    amber_tiles t = default_tiles();
+    const amber_tiles &first = start ? *start : default_tiles();
+    amber_tiles t = first;
+    // the kernels for uint16 input take channel_unroll >= 4 and 8 or 16
+    // samples per work-item
+    const int min_cu = in_u16 ? 4 : 1, min_spt = in_u16 ? 8 : 4;
     DedispPlan p;
     for (;;) {
-        if (plan_dedisperse(t, info, &p) == AMBER_OK) {
+        if (plan_dedisperse(t, info, &p, in_u16) == AMBER_OK) {
             clear_error();
             *out = t;
             return AMBER_OK;
         }
-        if (t.channel_unroll > 1) t.channel_unroll /= 2;
-        else if (t.dms_per_block > 1) { t.dms_per_block /= 2; t.channel_unroll = default_tiles().channel_unroll; }
-        else if (t.samples_per_thread > 4) { t.samples_per_thread /= 2; t.channel_unroll = default_tiles().channel_unroll; }
-        else return fail(AMBER_E_CONFIG, "no dedispersion tile fits this delay table (max_step=%d)", info.max_step);
+        if (t.channel_unroll > min_cu) t.channel_unroll /= 2;
+        else if (t.dms_per_block > 1) { t.dms_per_block /= 2; t.channel_unroll = first.channel_unroll; }
+        else if (t.samples_per_thread > min_spt) {
+            t.samples_per_thread /= 2;
+            t.channel_unroll = first.channel_unroll;
+        } else {
+            return fail(AMBER_E_CONFIG, "no dedispersion tile fits this delay table (max_step=%d)", info.max_step);
+        }
     }
 }
 
-amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info, DedispPlan *out)
+amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info, DedispPlan *out, int in_u16)
 {
     DedispPlan p{};
     p.tpd = t.threads_per_dm;
@@ -92,11 +97,16 @@ amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info,
         return fail(AMBER_E_CONFIG, "channel_unroll=%d must be a power of two <= 32", p.cu);
     if (info.max_step < 0 || info.max_delay < 0)
         return fail(AMBER_E_ARG, "delay info has negative max_step or max_delay");
+    if (in_u16 && ((p.spt != 8 && p.spt != 16) || p.cu < 4))
+        return fail(AMBER_E_CONFIG, "16-bit input takes samples_per_thread 8 or 16 and channel_unroll >= 4 "
+                    "(got %d, %d)", p.spt, p.cu);
+    p.in_u16 = in_u16 ? 1 : 0;
     p.threads = p.tpd * p.dpb;
     p.tile_t = p.tpd * p.spt;
     // Offsets a DM of the tile reads at, relative to the first DM's window
-    // start (which is rounded down to 4 samples): [0, omax].
-    const int64_t omax = (int64_t)(p.dpb - 1) * info.max_step + 3;
+    // start (which is rounded down to a dword: 4 uint8 or 2 uint16 samples):
+    // [0, omax].
+    const int64_t omax = (int64_t)(p.dpb - 1) * info.max_step + (in_u16 ? 1 : 3);
     if (omax > (int64_t)1 << 24)
         return fail(AMBER_E_CONFIG, "delay steps too large for one tile (max_step=%d)", info.max_step);
     // a DM reads dwords up to (o >> 1) + tile_t / 2 - 1 of a copy; the copy
@@ -109,7 +119,8 @@ amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info,
                     "channel_unroll, dms_per_block or the time tile", (long long)lds, (long long)kMaxLdsBytes);
     const int64_t items = p.cu * (win / 16);
     p.maxi = (int)((items + p.threads - 1) / p.threads);
-    const int maxi_cap = p.spt >= 32 ? 2 : (p.spt >= 16 ? 3 : 4);  // prefetch registers beside the accumulators
+    // prefetch registers beside the accumulators
+    const int maxi_cap = in_u16 ? 2 : (p.spt >= 32 ? 2 : (p.spt >= 16 ? 3 : 4));
     if (p.maxi > maxi_cap)
         return fail(AMBER_E_CONFIG, "staging needs %d items per work-item (max %d): reduce channel_unroll or "
                     "enlarge the work-group", p.maxi, maxi_cap);

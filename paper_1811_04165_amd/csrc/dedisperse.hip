@@ -23,6 +23,13 @@
 // each channel for the wave's DM is computed once per group by lane j for
 // channel j and broadcast with readlane, so the per-channel cost is one
 // readlane, one address add, the reads and the adds.
+//
+// Subband dedispersion runs on the same kernel.  Step one is a grouped job:
+// every subband is an independent problem over its own channels, and its sums
+// are stored as uint16.  Step two treats the subbands as channels and the
+// fine DMs of one coarse DM as the DM trials, again one group per coarse DM;
+// its uint16 input is staged as is (no widening) and its packed 16-bit sums
+// are widened every `flush_every` subbands, before they can overflow.
 #include "internal.h"
 
 #include <cstdlib>
@@ -70,41 +77,50 @@ struct StageArgs {
     int n_chan, items_per_row, n_items;
 };
 
-// Loads the 20 input bytes (16 samples + 4 of lookahead) of staging item q of
-// the channel group starting at c0.  Dwords outside the buffer read as zero:
-// they lie past the last row's samples, so no output < n_out depends on them.
-// A zapped channel's items are zero, so it adds nothing to any sum.
-__device__ __forceinline__ void stage_load(const StageArgs &a, int c0, int q, uint32_t (&w)[5])
+// Dwords one staging item loads: 16 samples and one dword of lookahead.
+template <bool U16>
+struct Item {
+    static constexpr int dwords = U16 ? 9 : 5;
+};
+
+// Loads staging item q (16 samples + lookahead) of the channel group starting
+// at c0.  Dwords outside the buffer read as zero: they lie past the last
+// row's samples, so no output < n_out depends on them.  A zapped channel's
+// items are zero, so it adds nothing to any sum.
+template <bool U16>
+__device__ __forceinline__ void stage_load(const StageArgs &a, int c0, int q, uint32_t (&w)[Item<U16>::dwords])
 {
+    constexpr int NW = Item<U16>::dwords;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) w[k] = 0u;
+    for (int k = 0; k < NW; ++k) w[k] = 0u;
     if (q >= a.n_items) return;
     const int j = q / a.items_per_row;
     const int it = q - j * a.items_per_row;
     const int c = c0 + j;
     if (c >= a.n_chan) return;
     if (a.keep && a.keep[c] == 0) return;
-    const int64_t g0 = (a.t0 + a.dfirst[c]) & ~(int64_t)3;
-    const int64_t off = (int64_t)c * a.in_stride + g0 + 16 * (int64_t)it;
-    if (off >= 0 && off + 20 <= a.in_bytes) {
+    // first sample of the window, rounded down to a dword boundary
+    const int64_t g0 = (a.t0 + a.dfirst[c]) & (U16 ? ~(int64_t)1 : ~(int64_t)3);
+    const int64_t off = (int64_t)c * a.in_stride + (U16 ? 2 : 1) * (g0 + 16 * (int64_t)it);
+    if (off >= 0 && off + 4 * NW <= a.in_bytes) {
         const uint32_t *p = reinterpret_cast<const uint32_t *>(a.in + off);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) w[k] = p[k];
+        for (int k = 0; k < NW; ++k) w[k] = p[k];
     } else {
         const uint32_t *src = reinterpret_cast<const uint32_t *>(a.in);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < NW; ++k) {
             const int64_t o = off + 4 * k;
             w[k] = (o >= 0 && o + 4 <= a.in_bytes) ? src[o >> 2] : 0u;
         }
     }
 }
 
-// Writes staging item q (16 samples) widened to 16 bits into the two copies:
+// Writes staging item q (16 samples) as 16-bit values into the two copies:
 // copy s, dword m of the item holds samples 2m + s and 2m + s + 1.
-template <int CU>
+template <int CU, bool U16>
 __device__ __forceinline__ void stage_store(lds_w4 *lds, int win2, int items_per_row, int n_items, int q,
-                                            const uint32_t (&w)[5])
+                                            const uint32_t (&w)[Item<U16>::dwords])
 {
     if (q >= n_items) return;
     const int j = q / items_per_row;
@@ -114,8 +130,12 @@ __device__ __forceinline__ void stage_store(lds_w4 *lds, int win2, int items_per
         uint32_t d[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            const int p = 2 * m + s;  // first byte of the pair within the 20 bytes
-            d[m] = __builtin_amdgcn_perm(w[(p >> 2) + 1], w[p >> 2], widen_sel(p & 3));
+            if (U16) {  // samples 2m + s, 2m + s + 1 of the item's dwords
+                d[m] = s == 0 ? w[m] : __builtin_amdgcn_alignbyte(w[m + 1], w[m], 2);
+            } else {
+                const int p = 2 * m + s;  // first byte of the pair within the 20 bytes
+                d[m] = __builtin_amdgcn_perm(w[(p >> 2) + 1], w[p >> 2], widen_sel(p & 3));
+            }
         }
         lds_w4 *dst = lds + (((s * CU + j) * win2) >> 2) + 2 * it;
         dst[0] = u32x4{d[0], d[1], d[2], d[3]};
@@ -123,7 +143,7 @@ __device__ __forceinline__ void stage_store(lds_w4 *lds, int win2, int items_per
     }
 }
 
-template <int M, int CU, int MAXI>
+template <int M, int CU, int MAXI, bool U16>
 __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs,
                                                           int n_jobs, int tpd, int dpb, int remap)
 {
@@ -140,6 +160,15 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
         while (j + 1 < n_jobs && jobs[j + 1].block_start <= block) ++j;
         job = jobs[j];
         block -= job.block_start;
+    }
+    if (job.groups > 1) {  // independent problems of one shape, back to back in the grid
+        const int gi = block / job.group_blocks;
+        block -= gi * job.group_blocks;
+        job.delays += gi * job.group_delays;
+        job.in += gi * job.group_in;
+        job.in_bytes -= gi * job.group_in;
+        job.dd = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(job.dd) + gi * job.group_out);
+        if (job.keep) job.keep += gi * job.group_keep;
     }
     const int32_t *__restrict__ delays = job.delays;
     const int n_dm = job.n_dm, n_chan = job.n_chan, win = job.win, omax = job.omax;
@@ -178,9 +207,9 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
 
     // Prefetch of the first channel group: input items, and on lane j < CU the
     // delays of channel j for this wave's DM and for the group's first DM.
-    uint32_t pre[MAXI][5];
+    uint32_t pre[MAXI][Item<U16>::dwords];
 #pragma unroll
-    for (int m = 0; m < MAXI; ++m) stage_load(sa, 0, tid + m * nthreads, pre[m]);
+    for (int m = 0; m < MAXI; ++m) stage_load<U16>(sa, 0, tid + m * nthreads, pre[m]);
     const int cl = lane < CU ? lane : CU - 1;
     int d_next = 0, f_next = 0;
     {
@@ -191,17 +220,20 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
 
     const uint32_t lane_off = 4u * (uint32_t)lane;
     int since_flush = 0;
+    const int flush_every = U16 ? uniform(job.flush_every) : 256;
+    int left = flush_every;  // channels the packed sums may still take (uint16 input)
     for (int c0 = 0; c0 < n_chan; c0 += CU) {
 #pragma unroll
-        for (int m = 0; m < MAXI; ++m) stage_store<CU>(lds, win2, sa.items_per_row, sa.n_items, tid + m * nthreads, pre[m]);
+        for (int m = 0; m < MAXI; ++m)
+            stage_store<CU, U16>(lds, win2, sa.items_per_row, sa.n_items, tid + m * nthreads, pre[m]);
         // LDS byte offset of channel `cl` for this wave's DM
-        int o = d_next - f_next + (f_next & 3);
+        int o = d_next - f_next + (f_next & (U16 ? 1 : 3));
         o = o < 0 ? 0 : (o > omax ? omax : o);
         const uint32_t chan_off = 4u * (uint32_t)(((o & 1) * CU + cl) * win2 + (o >> 1) + (wave_t >> 1));
         __syncthreads();
         if (c0 + CU < n_chan) {
 #pragma unroll
-            for (int m = 0; m < MAXI; ++m) stage_load(sa, c0 + CU, tid + m * nthreads, pre[m]);
+            for (int m = 0; m < MAXI; ++m) stage_load<U16>(sa, c0 + CU, tid + m * nthreads, pre[m]);
             const int c = c0 + CU + cl < n_chan ? c0 + CU + cl : n_chan - 1;
             d_next = dmine[c];
             f_next = sa.dfirst[c];
@@ -215,9 +247,18 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
                 lds_u1 *src = (lds_u1 *)((__attribute__((address_space(3))) const char *)lds + (base + lane_off));
 #pragma unroll
                 for (int k = 0; k < M; ++k) acc[k] += src[64 * k];
+                if (U16 && --left == 0) {
+#pragma unroll
+                    for (int k = 0; k < M; ++k) {
+                        lo[k] += acc[k] & 0xffffu;
+                        hi[k] += acc[k] >> 16;
+                        acc[k] = 0u;
+                    }
+                    left = flush_every;
+                }
             }
             since_flush += CU;
-            if (since_flush >= 256 || c0 + CU >= n_chan) {
+            if ((!U16 && since_flush >= 256) || c0 + CU >= n_chan) {
 #pragma unroll
                 for (int k = 0; k < M; ++k) {
                     lo[k] += acc[k] & 0xffffu;
@@ -232,6 +273,21 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
 
     if (!active) return;
     const int store_vec = job.store_vec;
+    if (job.out_u16) {  // sums known to fit 16 bits: one dword per sample pair
+        uint16_t *__restrict__ out =
+            reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(job.dd) + (size_t)i * dd_stride * 2);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int64_t t = t0 + wave_t + 128 * k + 2 * lane;
+            if (store_vec && t + 2 <= n_out) {
+                *reinterpret_cast<uint32_t *>(out + t) = lo[k] | (hi[k] << 16);
+            } else {
+                if (t < n_out) out[t] = (uint16_t)lo[k];
+                if (t + 1 < n_out) out[t + 1] = (uint16_t)hi[k];
+            }
+        }
+        return;
+    }
     int32_t *__restrict__ out = job.dd + (size_t)i * dd_stride;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -247,39 +303,60 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
 
 using KernelFn = void (*)(DedispJob, const DedispJob *, int, int, int, int);
 
-template <int M, int CU>
+// uint8 input: every (samples_per_thread, channel_unroll) with the staging
+// depths the planner allows (4 below 16 samples per work-item, 3 at 16, 2 at
+// 32).  uint16 input (subband step two, at most a few dozen subbands): 8 or
+// 16 samples per work-item, channel_unroll 4..32, staging depth 1..2.  Deeper
+// staging would not fit the 128 registers of a 1024-item work-group.
+template <int M, int CU, bool U16>
 KernelFn pick_items(int maxi)
 {
+    constexpr int cap = U16 ? 2 : (M >= 16 ? 2 : (M >= 8 ? 3 : 4));
     switch (maxi) {
-    case 1: return dedisperse_kernel<M, CU, 1>;
-    case 2: return dedisperse_kernel<M, CU, 2>;
-    case 3: return dedisperse_kernel<M, CU, 3>;
-    case 4: return M < 8 ? dedisperse_kernel<M, CU, (M < 8 ? 4 : 3)> : nullptr;
+    case 1: return dedisperse_kernel<M, CU, 1, U16>;
+    case 2: return dedisperse_kernel<M, CU, 2, U16>;
+    case 3:
+        if constexpr (cap >= 3) return dedisperse_kernel<M, CU, 3, U16>;
+        return nullptr;
+    case 4:
+        if constexpr (cap >= 4) return dedisperse_kernel<M, CU, 4, U16>;
+        return nullptr;
     }
     return nullptr;
 }
 
 template <int M>
-KernelFn pick_cu(int cu, int maxi)
+KernelFn pick_cu(int cu, int maxi, int u16)
 {
+    if (u16) {
+        if constexpr (M == 4 || M == 8) {
+            switch (cu) {
+            case 4: return pick_items<M, 4, true>(maxi);
+            case 8: return pick_items<M, 8, true>(maxi);
+            case 16: return pick_items<M, 16, true>(maxi);
+            case 32: return pick_items<M, 32, true>(maxi);
+            }
+        }
+        return nullptr;
+    }
     switch (cu) {
-    case 1: return pick_items<M, 1>(maxi);
-    case 2: return pick_items<M, 2>(maxi);
-    case 4: return pick_items<M, 4>(maxi);
-    case 8: return pick_items<M, 8>(maxi);
-    case 16: return pick_items<M, 16>(maxi);
-    case 32: return pick_items<M, 32>(maxi);
+    case 1: return pick_items<M, 1, false>(maxi);
+    case 2: return pick_items<M, 2, false>(maxi);
+    case 4: return pick_items<M, 4, false>(maxi);
+    case 8: return pick_items<M, 8, false>(maxi);
+    case 16: return pick_items<M, 16, false>(maxi);
+    case 32: return pick_items<M, 32, false>(maxi);
     }
     return nullptr;
 }
 
-KernelFn pick(int spt, int cu, int maxi)
+KernelFn pick(int spt, int cu, int maxi, int u16)
 {
     switch (spt) {
-    case 4: return pick_cu<2>(cu, maxi);
-    case 8: return pick_cu<4>(cu, maxi);
-    case 16: return pick_cu<8>(cu, maxi);
-    case 32: return pick_cu<16>(cu, maxi);
+    case 4: return pick_cu<2>(cu, maxi, u16);
+    case 8: return pick_cu<4>(cu, maxi, u16);
+    case 16: return pick_cu<8>(cu, maxi, u16);
+    case 32: return pick_cu<16>(cu, maxi, u16);
     }
     return nullptr;
 }
@@ -311,14 +388,18 @@ DedispJob make_dedisp_job(const DedispPlan &p, const int32_t *d_delays, int n_dm
     j.tiles_dm = (n_dm + p.dpb - 1) / p.dpb;
     j.store_vec = (dd_stride % 2 == 0) && (((uintptr_t)d_dd & 7) == 0);
     j.block_start = 0;
+    j.flush_every = 256;
+    j.groups = 1;
     return j;
 }
 
 amber_status launch_dedisperse_jobs(const DedispPlan &p, const DedispJob *single, const DedispJob *d_jobs,
                                     int n_jobs, int64_t n_blocks, int64_t lds_bytes, hipStream_t stream)
 {
-    KernelFn fn = pick(p.spt, p.cu, p.maxi);
-    if (!fn) return fail(AMBER_E_CONFIG, "no dedispersion kernel for spt=%d cu=%d maxi=%d", p.spt, p.cu, p.maxi);
+    KernelFn fn = pick(p.spt, p.cu, p.maxi, p.in_u16);
+    if (!fn)
+        return fail(AMBER_E_CONFIG, "no dedispersion kernel for spt=%d cu=%d maxi=%d%s", p.spt, p.cu, p.maxi,
+                    p.in_u16 ? " with 16-bit input (spt 8 or 16, channel_unroll 4..32)" : "");
     if (lds_bytes > 64 * 1024)
         AMBER_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes),

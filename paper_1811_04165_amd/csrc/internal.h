@@ -24,6 +24,9 @@ amber_status hip_fail(hipError_t err, const char *what);
         if (e_ != hipSuccess) return ::amber::hip_fail(e_, what); \
     } while (0)
 
+// Cold-plasma dispersion constant, s MHz^2 / (pc cm^-3).
+constexpr double kDispersion = 4.148808e3;
+
 constexpr int kWave = 64;
 constexpr int kMaxThreads = 1024;
 constexpr int64_t kMaxLdsBytes = 160 * 1024;
@@ -36,11 +39,15 @@ struct DedispPlan {
     int win;            // LDS window length in samples per channel (multiple of 16)
     int maxi;           // staging items per work-item (prefetched in registers)
     int omax;           // largest sample offset a DM may read at inside the window
+    int in_u16;         // input samples are uint16 (subband step two)
     int64_t lds_bytes;  // dynamic LDS per work-group
 };
 
-amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info, DedispPlan *out);
-amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out);
+amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info, DedispPlan *out, int in_u16 = 0);
+// The first valid tiles of a shrinking sequence that starts at `start`
+// (default: the library's defaults).
+amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out, int in_u16 = 0,
+                        const amber_tiles *start = nullptr);
 
 // Boxcar / S/N geometry.
 struct BoxcarPlan {
@@ -66,6 +73,18 @@ struct DedispJob {
     int64_t in_stride, in_bytes, dd_stride, n_out;
     int n_dm, n_chan, win, omax, tiles_t, tiles_dm, store_vec, block_start;
     const uint8_t *keep;  // per-channel keep flags (0 = zapped), or NULL: every channel
+    // in_u16: input samples are uint16 (else uint8); out_u16: sums are stored
+    // as uint16 (the caller guarantees they fit).  flush_every: channels summed
+    // into the packed 16-bit partial sums before they are widened (256 for
+    // uint8 input; floor(65535 / largest input value) for uint16).
+    int in_u16, out_u16, flush_every;
+    // groups > 1: the job is `groups` independent problems of the same shape
+    // (the subbands of subband step one, the coarse DMs of step two), each
+    // group_blocks work-groups long in the grid; group g uses delays, input,
+    // output and keep flags advanced by g times the strides below, and in_bytes
+    // counts from group 0's input
+    int groups, group_blocks;
+    int64_t group_delays, group_in, group_out, group_keep;  // int32 elements, bytes, bytes, channels
 };
 
 // One beam's boxcar / S/N work (rows of job j occupy work-groups

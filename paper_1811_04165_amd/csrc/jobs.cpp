@@ -9,7 +9,8 @@ namespace amber {
 void LaunchSet::add_dedisperse(const DedispPlan &p, DedispJob j)
 {
     auto it = std::find_if(d_.begin(), d_.end(), [&](const DGroup &g) {
-        return g.plan.tpd == p.tpd && g.plan.spt == p.spt && g.plan.dpb == p.dpb && g.plan.cu == p.cu;
+        return g.plan.tpd == p.tpd && g.plan.spt == p.spt && g.plan.dpb == p.dpb && g.plan.cu == p.cu &&
+               g.plan.in_u16 == p.in_u16;
     });
     if (it == d_.end()) {
         d_.emplace_back();
@@ -17,7 +18,7 @@ void LaunchSet::add_dedisperse(const DedispPlan &p, DedispJob j)
         it->plan = p;
     }
     j.block_start = (int)it->n_blocks;
-    it->n_blocks += (int64_t)j.tiles_t * j.tiles_dm;
+    it->n_blocks += (int64_t)j.tiles_t * j.tiles_dm * (j.groups > 1 ? j.groups : 1);
     it->plan.maxi = std::max(it->plan.maxi, p.maxi);
     it->lds = std::max(it->lds, p.lds_bytes);
     it->jobs.push_back(j);

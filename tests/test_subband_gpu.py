@@ -1,0 +1,181 @@
+"""Two-step subband dedispersion on the device against the oracle.
+
+Every trial must equal the oracle's composed subband sum bit for bit, for
+several tile choices of each step, ragged lengths and the degenerate grids:
+one subband (step two does nothing: every fine trial is the coarse DM's brute
+force), one channel per subband (step one does nothing: every trial is brute
+force at its own DM).  Step one's scratch rows are checked on their own
+against the oracle's brute-force dedispersion of each subband, and the full
+1536-channel beam is checked on sampled coarse DMs for both the beam's grid
+and Table 2's subbanding grid.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def amber():
+    import paper_1811_04165_amd as amber
+    return amber
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    return torch
+
+
+SMALL = workloads.small().geom          # 256 channels over 1250-1550 MHz
+BEAM = workloads.beam().geom            # 1536 channels
+
+
+def _setup(amber, g, grid, n_out, seed, pulse=None):
+    """Tables (library and oracle), input with n_in = n_out + max_delay."""
+    f = g.freqs()
+    d1, d2, info = amber.subband_delay_tables(f, g.t_samp_s, *grid)
+    o1, o2, _, _ = oracle.subband_delays(f, g.t_samp_s, *grid)
+    n_in = n_out + info.max_delay
+    x = workloads.noise(g.n_chan, n_in, workloads.padded_stride(n_in), seed=seed)
+    if pulse is not None:
+        bd, _ = oracle.delay_table(f, g.t_samp_s, 1, pulse[0], 0.0)
+        workloads.inject(x, bd[0], t0=pulse[1], width=pulse[2], amp=40)
+    return d1, d2, info, o1, o2, x, n_in
+
+
+def _run(amber, torch, d1, d2, info, x, n_in, n_out, **kw):
+    return amber.subband_dedisperse(torch.from_numpy(d1).cuda(), torch.from_numpy(d2).cuda(), info,
+                                    torch.from_numpy(x).cuda(), n_in, n_out, **kw)
+
+
+SMALL_GRID = (16, 16, 0.0, 8.0, 8, 0.0, 1.0)   # 128 trials 0..127 step 1 from 16 subbands of 16 channels
+TILES = [
+    (None, None),
+    (dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=4, channel_unroll=16),
+     dict(threads_per_dm=64, samples_per_thread=16, dms_per_block=8, channel_unroll=8)),
+    (dict(threads_per_dm=128, samples_per_thread=4, dms_per_block=3, channel_unroll=2),
+     dict(threads_per_dm=128, samples_per_thread=8, dms_per_block=3, channel_unroll=4)),
+    (dict(threads_per_dm=64, samples_per_thread=16, dms_per_block=8, channel_unroll=8),
+     dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=16, channel_unroll=32)),  # idle DM rows
+]
+
+
+def _tid(t):
+    a, b = t
+    if a is None:
+        return "auto"
+    return "s1-%d-%d-%d-%d_s2-%d-%d-%d-%d" % tuple(
+        [a[k] for k in ("threads_per_dm", "samples_per_thread", "dms_per_block", "channel_unroll")] +
+        [b[k] for k in ("threads_per_dm", "samples_per_thread", "dms_per_block", "channel_unroll")])
+
+
+@pytest.mark.parametrize("tiles", TILES, ids=_tid)
+def test_subband_small_bit_exact(amber, torch, tiles):
+    n_out = 3001                       # ragged: not a multiple of any time tile
+    d1, d2, info, o1, o2, x, n_in = _setup(amber, SMALL, SMALL_GRID, n_out, seed=61, pulse=(50.0, 1500, 4))
+    ref = oracle.subband_dedisperse(o1, o2, x, n_in, n_out)
+    t1 = amber.make_tiles(**tiles[0]) if tiles[0] else None
+    t2 = amber.make_tiles(**tiles[1]) if tiles[1] else None
+    say("subband small", _tid(tiles), info)
+    got = _run(amber, torch, d1, d2, info, x, n_in, n_out, tiles1=t1, tiles2=t2).cpu().numpy()
+    assert np.array_equal(got, ref)
+
+
+def test_subband_step_one_rows(amber, torch):
+    """Step one's scratch: row (s, j) is the brute-force sum of subband s's
+    channels with the library's step-one delays, for n_out + max_delay2 samples."""
+    n_out = 2000
+    d1, d2, info, o1, o2, x, n_in = _setup(amber, SMALL, SMALL_GRID, n_out, seed=62)
+    n_sub, nc, m = d1.shape
+    n1 = n_out + info.max_delay2
+    work = torch.zeros((n_sub * nc, (n1 + 7) // 2 * 2), dtype=torch.uint16, device="cuda")  # even stride
+    say("subband step-one rows", info)
+    _run(amber, torch, d1, d2, info, x, n_in, n_out, work=work)
+    w = work.cpu().numpy().astype(np.int64)[:, :n1].reshape(n_sub, nc, n1)
+    for s in range(n_sub):
+        ref = oracle.dedisperse(d1[s], x[s * m:(s + 1) * m], n_in, n1)
+        assert np.array_equal(w[s], ref), s
+
+
+def test_subband_one_subband_is_coarse_brute_force(amber, torch):
+    n_out = 1500
+    grid = (1, 6, 0.0, 16.0, 4, 0.0, 4.0)       # every fine trial of coarse DM j: brute force at 16 j
+    d1, d2, info, o1, o2, x, n_in = _setup(amber, SMALL, grid, n_out, seed=63)
+    assert info.max_delay2 == 0
+    bd, mx = oracle.delay_table(SMALL.freqs(), SMALL.t_samp_s, 6, 0.0, 16.0)
+    bf = oracle.dedisperse(bd, x, n_in, n_out)
+    say("one subband", info)
+    got = _run(amber, torch, d1, d2, info, x, n_in, n_out).cpu().numpy().reshape(6, 4, n_out)
+    for k in range(4):
+        assert np.array_equal(got[:, k], bf)
+
+
+def test_subband_one_channel_per_subband_is_brute_force(amber, torch):
+    """m = 1: step one is a copy and step two is brute force at DM_jk
+    (dyadic steps make DM_jk = (16 j + k) * 0.5 exactly)."""
+    n_out = 1800
+    grid = (256, 8, 0.0, 8.0, 16, 0.0, 0.5)
+    d1, d2, info, o1, o2, x, n_in = _setup(amber, SMALL, grid, n_out, seed=64)
+    bd, mx = oracle.delay_table(SMALL.freqs(), SMALL.t_samp_s, 128, 0.0, 0.5)
+    bf = oracle.dedisperse(bd, x, n_in, n_out)
+    say("one channel per subband", info)
+    got = _run(amber, torch, d1, d2, info, x, n_in, n_out).cpu().numpy()
+    assert np.array_equal(got, bf)
+
+
+def test_subband_edge_lengths_and_repeat(amber, torch):
+    for n_out, grid in ((1, SMALL_GRID), (63, (8, 3, 2.0, 5.0, 2, 0.0, 2.5)), (4097, (32, 5, 0.0, 12.0, 3, 1.0, 4.0))):
+        d1, d2, info, o1, o2, x, n_in = _setup(amber, SMALL, grid, n_out, seed=65 + n_out)
+        ref = oracle.subband_dedisperse(o1, o2, x, n_in, n_out)
+        say("edge n_out", n_out, info)
+        a = _run(amber, torch, d1, d2, info, x, n_in, n_out).cpu().numpy()
+        b = _run(amber, torch, d1, d2, info, x, n_in, n_out).cpu().numpy()
+        assert np.array_equal(a, ref) and np.array_equal(a, b)
+    # n_out = 0 launches nothing: the output keeps its contents
+    d1, d2, info, o1, o2, x, n_in = _setup(amber, SMALL, SMALL_GRID, 0, seed=70)
+    out = torch.full((info.n_coarse * info.n_fine, 8), -7, dtype=torch.int32, device="cuda")
+    _run(amber, torch, d1, d2, info, x, n_in, 0, out=out)
+    assert (out.cpu().numpy() == -7).all()
+
+
+def test_subband_masked(amber, torch):
+    n_out = 2500
+    d1, d2, info, o1, o2, x, n_in = _setup(amber, SMALL, SMALL_GRID, n_out, seed=71, pulse=(80.0, 1000, 2))
+    keep = (np.random.default_rng(72).random(SMALL.n_chan) >= 0.2).astype(np.uint8)
+    keep[16:32] = 0                                       # a whole subband
+    xz = x.copy()
+    xz[keep == 0] = 0                                     # zapped channels contribute nothing
+    ref = oracle.subband_dedisperse(o1, o2, xz, n_in, n_out)
+    say("subband masked, zapped", int((keep == 0).sum()))
+    got = _run(amber, torch, d1, d2, info, x, n_in, n_out, keep=torch.from_numpy(keep).cuda()).cpu().numpy()
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("grid", [(32, 128, 0.0, 8.0, 16, 0.0, 0.5), (32, 2048, 0.0, 2.4, 24, 0.0, 0.1)],
+                         ids=["beam-grid-2048dm", "table2-grid-49152dm"])
+def test_subband_beam_sampled(amber, torch, grid):
+    """The 1536-channel, 12208-sample beam at full size; sampled coarse DMs
+    (every fine trial of each) against the oracle."""
+    wl = workloads.beam()
+    n_out = wl.n_out
+    d1, d2, info, o1, o2, x, n_in = _setup(amber, BEAM, grid, n_out, seed=2)
+    say("subband beam full size", info, "n_in", n_in)
+    got = _run(amber, torch, d1, d2, info, x, n_in, n_out)
+    torch.cuda.synchronize()
+    nc, nf = info.n_coarse, info.n_fine
+    js = sorted(set([0, 1, nc - 1] + list(np.random.default_rng(73).choice(nc, size=3, replace=False))))
+    rows = np.array([j * nf + k for j in js for k in range(nf)])
+    got_rows = got[torch.from_numpy(rows).cuda()].cpu().numpy()
+    ref = oracle.subband_dedisperse(o1[:, js, :], o2[js], x, n_in, n_out)
+    assert np.array_equal(got_rows, ref)
