@@ -623,8 +623,14 @@ def subband_report(steps: int, warmup: int, grid_names, bf_steps: int = 3):
     n_out = wl.n_out
 
     def timed(fn, n, w):
-        for _ in range(w):
+        # at least half a second of the same work first: the clocks ramp up
+        # while the host builds tables and inputs
+        t_end = time.perf_counter() + 0.5
+        k = 0
+        while k < w or time.perf_counter() < t_end:
             fn()
+            torch.cuda.synchronize()
+            k += 1
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         b.record()
@@ -685,7 +691,8 @@ def subband_report(steps: int, warmup: int, grid_names, bf_steps: int = 3):
         bdd = torch.from_numpy(bd).cuda()
         dd_bf = torch.empty((n_dm, n_out), dtype=torch.int32, device="cuda")
         print("[bench] brute force %s" % name, file=sys.stderr, flush=True)
-        t_bf = timed(lambda: amber.dedisperse(bdd, binfo, xd, n_in, n_out, out=dd_bf), bf_steps, 1)
+        t_bf = timed(lambda: amber.dedisperse(bdd, binfo, xd, n_in, n_out, out=dd_bf),
+                     steps if n_dm <= 4096 else bf_steps, 1)
         amber.integrate_snr(dd_bf, n_out, widths, out=(snr_sb, pk))
         s_bf = snr_sb.cpu().numpy()
         del bdd, dd_bf, dd_sb

@@ -70,7 +70,6 @@ __device__ __forceinline__ void tile_of_block(int id, int nx, int ny, int remap,
 
 struct StageArgs {
     const uint8_t *in;
-    const uint8_t *keep;
     int64_t in_stride, in_bytes;
     const int32_t *dfirst;
     int64_t t0;
@@ -85,8 +84,7 @@ struct Item {
 
 // Loads staging item q (16 samples + lookahead) of the channel group starting
 // at c0.  Dwords outside the buffer read as zero: they lie past the last
-// row's samples, so no output < n_out depends on them.  A zapped channel's
-// items are zero, so it adds nothing to any sum.
+// row's samples, so no output < n_out depends on them.
 template <bool U16>
 __device__ __forceinline__ void stage_load(const StageArgs &a, int c0, int q, uint32_t (&w)[Item<U16>::dwords])
 {
@@ -98,7 +96,6 @@ __device__ __forceinline__ void stage_load(const StageArgs &a, int c0, int q, ui
     const int it = q - j * a.items_per_row;
     const int c = c0 + j;
     if (c >= a.n_chan) return;
-    if (a.keep && a.keep[c] == 0) return;
     // first sample of the window, rounded down to a dword boundary
     const int64_t g0 = (a.t0 + a.dfirst[c]) & (U16 ? ~(int64_t)1 : ~(int64_t)3);
     const int64_t off = (int64_t)c * a.in_stride + (U16 ? 2 : 1) * (g0 + 16 * (int64_t)it);
@@ -191,7 +188,6 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
 
     StageArgs sa;
     sa.in = job.in;
-    sa.keep = job.keep;
     sa.in_stride = job.in_stride;
     sa.in_bytes = job.in_bytes;
     sa.dfirst = delays + (size_t)i0 * n_chan;
@@ -211,11 +207,22 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
 #pragma unroll
     for (int m = 0; m < MAXI; ++m) stage_load<U16>(sa, 0, tid + m * nthreads, pre[m]);
     const int cl = lane < CU ? lane : CU - 1;
-    int d_next = 0, f_next = 0;
+    // Zapped channels (keep flag 0) are staged like any other; their offsets
+    // are redirected to a zeroed LDS region of 64 * M dwords after the two
+    // copies, so they add nothing.  The flag is loaded once per channel group
+    // beside the delays: a test inside the staging loads would serialise them.
+    const uint8_t *__restrict__ keep = job.keep;
+    const uint32_t zero_off = 4u * (uint32_t)(2 * CU * win2);
+    if (keep) {
+        uint32_t *zl = (uint32_t *)lds_raw + 2 * CU * win2;
+        for (int q = tid; q < 64 * M; q += nthreads) zl[q] = 0u;
+    }
+    int d_next = 0, f_next = 0, z_next = 0;
     {
         const int c = cl < n_chan ? cl : n_chan - 1;
         d_next = dmine[c];
         f_next = sa.dfirst[c];
+        if (keep) z_next = keep[c] == 0;
     }
 
     const uint32_t lane_off = 4u * (uint32_t)lane;
@@ -229,7 +236,8 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
         // LDS byte offset of channel `cl` for this wave's DM
         int o = d_next - f_next + (f_next & (U16 ? 1 : 3));
         o = o < 0 ? 0 : (o > omax ? omax : o);
-        const uint32_t chan_off = 4u * (uint32_t)(((o & 1) * CU + cl) * win2 + (o >> 1) + (wave_t >> 1));
+        uint32_t chan_off = 4u * (uint32_t)(((o & 1) * CU + cl) * win2 + (o >> 1) + (wave_t >> 1));
+        if (z_next) chan_off = zero_off;
         __syncthreads();
         if (c0 + CU < n_chan) {
 #pragma unroll
@@ -237,6 +245,7 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
             const int c = c0 + CU + cl < n_chan ? c0 + CU + cl : n_chan - 1;
             d_next = dmine[c];
             f_next = sa.dfirst[c];
+            if (keep) z_next = keep[c] == 0;
         }
 
         if (active) {
@@ -419,7 +428,11 @@ amber_status launch_dedisperse(const DedispPlan &p, const int32_t *d_delays, int
     (void)n_in;
     DedispJob j = make_dedisp_job(p, d_delays, n_dm, n_chan, d_in, in_stride, d_dd, dd_stride, n_out);
     j.keep = d_keep;
-    return launch_dedisperse_jobs(p, &j, nullptr, 1, (int64_t)j.tiles_t * j.tiles_dm, p.lds_bytes, stream);
+    const int64_t lds = p.lds_bytes + (d_keep ? mask_lds_bytes(p) : 0);
+    if (lds > kMaxLdsBytes)
+        return fail(AMBER_E_CONFIG, "masked dedispersion tile needs %lld B of LDS (limit %lld)", (long long)lds,
+                    (long long)kMaxLdsBytes);
+    return launch_dedisperse_jobs(p, &j, nullptr, 1, (int64_t)j.tiles_t * j.tiles_dm, lds, stream);
 }
 
 }  // namespace amber

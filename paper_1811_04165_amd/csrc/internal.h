@@ -44,6 +44,9 @@ struct DedispPlan {
 };
 
 amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info, DedispPlan *out, int in_u16 = 0);
+// LDS a launch with keep flags adds: the zeroed region zapped channels read
+// (64 lanes x samples_per_thread / 2 dwords).
+inline int64_t mask_lds_bytes(const DedispPlan &p) { return (int64_t)kWave * (p.spt / 2) * 4; }
 // The first valid tiles of a shrinking sequence that starts at `start`
 // (default: the library's defaults).
 amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out, int in_u16 = 0,

@@ -19,27 +19,23 @@ namespace {
 
 constexpr int kMaxSubbandChannels = 257;  // 257 * 255 < 2^16: step-one sums fit uint16
 
-// Start of the tile search for one step: the channel group that pads the
-// channel loop least (counting a few channels' worth of fixed cost per group)
-// and a DM block that splits the trials into equal parts of at most 16.  With
-// 16-bit input the block keeps at least 4 DM rows, even idle ones: the
-// staging of a window is spread over the whole work-group, and fewer
-// work-items would need more staging registers than those kernels have.
+// Start of the tile search for one step.  A sweep of both steps on the
+// 1536-channel beam (32 subbands; 128 x 16 and 2048 x 24 trial grids) put
+// the fastest tiles at 16 samples per work-item and channel groups of 8: with
+// only a few dozen channels (subbands) per work-group, several groups per
+// work-group let the next group's loads overlap the current group's sums,
+// which one large group cannot.  DM blocks split the trials into equal parts
+// of at most 12 (step one: its wide windows) or 16 (step two).  Step two
+// keeps at least 4 DM rows, even idle ones: the staging of a window is spread
+// over the whole work-group, and fewer work-items would need more staging
+// registers than its kernels have.
 amber_tiles step_tiles(int n_dm, int n_chan, int in_u16)
 {
     amber_tiles t = default_tiles();
-    int best = -1;
-    int64_t best_cost = 0;
-    for (int cu = 32; cu >= (in_u16 ? 4 : 1); cu /= 2) {
-        const int64_t groups = (n_chan + cu - 1) / cu;
-        const int64_t cost = groups * cu + 4 * groups;
-        if (best < 0 || cost < best_cost) {
-            best = cu;
-            best_cost = cost;
-        }
-    }
-    t.channel_unroll = best;
-    const int parts = (n_dm + 15) / 16;
+    t.samples_per_thread = 16;
+    t.channel_unroll = n_chan >= 16 ? 8 : 4;
+    const int cap = in_u16 ? 16 : 12;
+    const int parts = (n_dm + cap - 1) / cap;
     t.dms_per_block = (n_dm + parts - 1) / parts;
     if (in_u16 && t.dms_per_block < 4) t.dms_per_block = 4;
     return t;
@@ -218,7 +214,11 @@ amber_status amber_subband_dedisperse(const int32_t *d_delay1, const int32_t *d_
     j2.group_out = (int64_t)nf * dd_stride * 4;
     const int64_t b1 = (int64_t)j1.group_blocks * n_sub, b2 = (int64_t)j2.group_blocks * nc;
     if (b1 > 0x7fffffff || b2 > 0x7fffffff) return fail(AMBER_E_SHAPE, "subband grid too large");
-    if ((s = launch_dedisperse_jobs(p1, &j1, nullptr, 1, b1, p1.lds_bytes, (hipStream_t)stream)) != AMBER_OK)
+    const int64_t lds1 = p1.lds_bytes + (d_keep ? mask_lds_bytes(p1) : 0);
+    if (lds1 > kMaxLdsBytes)
+        return fail(AMBER_E_CONFIG, "masked step-one tile needs %lld B of LDS (limit %lld)", (long long)lds1,
+                    (long long)kMaxLdsBytes);
+    if ((s = launch_dedisperse_jobs(p1, &j1, nullptr, 1, b1, lds1, (hipStream_t)stream)) != AMBER_OK)
         return s;
     return launch_dedisperse_jobs(p2, &j2, nullptr, 1, b2, p2.lds_bytes, (hipStream_t)stream);
 }
