@@ -232,7 +232,8 @@ amber_status amber_subband_delay_tables(const amber_subband_geometry *g, int32_t
  *         scratch; receives step one's sums: row (s, j) holds
  *         sum over c' of in[s m + c'][t + delay1[s][j][c']] for
  *         t < n_out + info->max_delay2 (later columns are not written).
- *         work_stride >= n_out + max_delay2, even; d_work 4-byte aligned.
+ *         work_stride >= n_out + max_delay2, even, >= 32; d_work 4-byte
+ *         aligned.
  * d_dd:   device int32 [n_coarse * n_fine][dd_stride], dd_stride >= n_out.
  * d_keep: device uint8 [n_chan] keep flags as amber_dedisperse_masked, or
  *         NULL for every channel.

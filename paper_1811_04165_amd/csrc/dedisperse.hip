@@ -39,6 +39,16 @@ namespace {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// The same pointer in the global address space.  Loads through generic
+// pointers become flat loads, which count against the LDS counter too: every
+// wait for an LDS read in the sums would then also wait for the next channel
+// group's prefetch, and the two could never overlap.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *global(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)p;
+}
+
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) u32x4 lds_w4;
 typedef __attribute__((address_space(3))) const uint32_t lds_u1;
@@ -82,34 +92,47 @@ struct Item {
     static constexpr int dwords = U16 ? 9 : 5;
 };
 
-// Loads staging item q (16 samples + lookahead) of the channel group starting
-// at c0.  Dwords outside the buffer read as zero: they lie past the last
-// row's samples, so no output < n_out depends on them.
-template <bool U16>
-__device__ __forceinline__ void stage_load(const StageArgs &a, int c0, int q, uint32_t (&w)[Item<U16>::dwords])
+// Issues the loads of staging items tid + m * nthreads (m < MAXI) of the
+// channel group starting at c0: 16 samples + lookahead each.  No load sits
+// under a branch and nothing here reads a loaded value except the delays, so
+// the input loads stay in flight through the group's sums; stage_store
+// applies what the addresses could not.  An item past the last channel reads
+// channel 0 and is zeroed (shift = dwords).  An item that would end past the
+// buffer is read from the buffer's last whole item and shifted down by
+// `shift` dwords; the dwords past the end become zero (they lie past the last
+// row's samples, so no output < n_out depends on them).  The host guarantees
+// at least one whole item of input (in_bytes >= 4 * dwords).
+template <bool U16, int MAXI>
+__device__ __forceinline__ void stage_load(const StageArgs &a, int c0, int tid, int nthreads,
+                                           uint32_t (&w)[MAXI][Item<U16>::dwords], int (&shift)[MAXI])
 {
     constexpr int NW = Item<U16>::dwords;
+    int df[MAXI], cc[MAXI], itm[MAXI];
+    bool valid[MAXI];
 #pragma unroll
-    for (int k = 0; k < NW; ++k) w[k] = 0u;
-    if (q >= a.n_items) return;
-    const int j = q / a.items_per_row;
-    const int it = q - j * a.items_per_row;
-    const int c = c0 + j;
-    if (c >= a.n_chan) return;
-    // first sample of the window, rounded down to a dword boundary
-    const int64_t g0 = (a.t0 + a.dfirst[c]) & (U16 ? ~(int64_t)1 : ~(int64_t)3);
-    const int64_t off = (int64_t)c * a.in_stride + (U16 ? 2 : 1) * (g0 + 16 * (int64_t)it);
-    if (off >= 0 && off + 4 * NW <= a.in_bytes) {
-        const uint32_t *p = reinterpret_cast<const uint32_t *>(a.in + off);
+    for (int m = 0; m < MAXI; ++m) {
+        const int q = tid + m * nthreads;
+        const int j = q / a.items_per_row;
+        const int c = c0 + j;
+        valid[m] = q < a.n_items && c < a.n_chan;
+        cc[m] = valid[m] ? c : 0;
+        itm[m] = valid[m] ? q - j * a.items_per_row : 0;
+        df[m] = global(a.dfirst)[cc[m]];
+    }
+    const int64_t last = a.in_bytes - 4 * NW;  // host guarantees >= 0
 #pragma unroll
-        for (int k = 0; k < NW; ++k) w[k] = p[k];
-    } else {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(a.in);
+    for (int m = 0; m < MAXI; ++m) {
+        // first sample of the window, rounded down to a dword boundary
+        const int64_t g0 = (a.t0 + df[m]) & (U16 ? ~(int64_t)1 : ~(int64_t)3);
+        const int64_t off = (int64_t)cc[m] * a.in_stride + (U16 ? 2 : 1) * (g0 + 16 * (int64_t)itm[m]);
+        // the read stays inside the buffer whatever the delays hold; an item
+        // starting before it (only a table that breaks its contract) is zero
+        const int64_t base = off < 0 ? 0 : (off < last ? off : last);
+        const auto *p = global(reinterpret_cast<const uint32_t *>(a.in + base));
 #pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            const int64_t o = off + 4 * k;
-            w[k] = (o >= 0 && o + 4 <= a.in_bytes) ? src[o >> 2] : 0u;
-        }
+        for (int k = 0; k < NW; ++k) w[m][k] = p[k];
+        const int64_t sh = (off - base) >> 2;
+        shift[m] = (valid[m] && off >= 0) ? (int)(sh < NW ? sh : NW) : NW;
     }
 }
 
@@ -117,9 +140,19 @@ __device__ __forceinline__ void stage_load(const StageArgs &a, int c0, int q, ui
 // copy s, dword m of the item holds samples 2m + s and 2m + s + 1.
 template <int CU, bool U16>
 __device__ __forceinline__ void stage_store(lds_w4 *lds, int win2, int items_per_row, int n_items, int q,
-                                            const uint32_t (&w)[Item<U16>::dwords])
+                                            uint32_t (&w)[Item<U16>::dwords], int shift)
 {
+    constexpr int NW = Item<U16>::dwords;
     if (q >= n_items) return;
+    if (shift != 0) {  // rare: past the last channel, or the buffer's tail
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            uint32_t v = 0u;
+#pragma unroll
+            for (int r = 1; r < NW; ++r) v = (k + r < NW && shift == r) ? w[k + r] : v;
+            w[k] = v;
+        }
+    }
     const int j = q / items_per_row;
     const int it = q - j * items_per_row;
 #pragma unroll
@@ -204,8 +237,8 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
     // Prefetch of the first channel group: input items, and on lane j < CU the
     // delays of channel j for this wave's DM and for the group's first DM.
     uint32_t pre[MAXI][Item<U16>::dwords];
-#pragma unroll
-    for (int m = 0; m < MAXI; ++m) stage_load<U16>(sa, 0, tid + m * nthreads, pre[m]);
+    int pre_shift[MAXI];
+    stage_load<U16, MAXI>(sa, 0, tid, nthreads, pre, pre_shift);
     const int cl = lane < CU ? lane : CU - 1;
     // Zapped channels (keep flag 0) are staged like any other; their offsets
     // are redirected to a zeroed LDS region of 64 * M dwords after the two
@@ -217,12 +250,15 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
         uint32_t *zl = (uint32_t *)lds_raw + 2 * CU * win2;
         for (int q = tid; q < 64 * M; q += nthreads) zl[q] = 0u;
     }
-    int d_next = 0, f_next = 0, z_next = 0;
+    // keep flags are read unconditionally (from the delay table when there
+    // are none) so that no load sits under a branch
+    const uint8_t *kp = keep ? keep : reinterpret_cast<const uint8_t *>(dmine);
+    int d_next = 0, f_next = 0, k_next = 1;
     {
         const int c = cl < n_chan ? cl : n_chan - 1;
-        d_next = dmine[c];
-        f_next = sa.dfirst[c];
-        if (keep) z_next = keep[c] == 0;
+        d_next = global(dmine)[c];
+        f_next = global(sa.dfirst)[c];
+        k_next = global(kp)[keep ? c : 0];
     }
 
     const uint32_t lane_off = 4u * (uint32_t)lane;
@@ -232,20 +268,23 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
     for (int c0 = 0; c0 < n_chan; c0 += CU) {
 #pragma unroll
         for (int m = 0; m < MAXI; ++m)
-            stage_store<CU, U16>(lds, win2, sa.items_per_row, sa.n_items, tid + m * nthreads, pre[m]);
+            stage_store<CU, U16>(lds, win2, sa.items_per_row, sa.n_items, tid + m * nthreads, pre[m], pre_shift[m]);
         // LDS byte offset of channel `cl` for this wave's DM
         int o = d_next - f_next + (f_next & (U16 ? 1 : 3));
         o = o < 0 ? 0 : (o > omax ? omax : o);
         uint32_t chan_off = 4u * (uint32_t)(((o & 1) * CU + cl) * win2 + (o >> 1) + (wave_t >> 1));
-        if (z_next) chan_off = zero_off;
+        if (keep && k_next == 0) chan_off = zero_off;
         __syncthreads();
-        if (c0 + CU < n_chan) {
-#pragma unroll
-            for (int m = 0; m < MAXI; ++m) stage_load<U16>(sa, c0 + CU, tid + m * nthreads, pre[m]);
+        // Prefetch of the next group, also after the last one (its items are
+        // all invalid and read one shared address): a branch here would make
+        // the compiler copy the loaded registers at its join and so wait for
+        // the loads before the sums.
+        stage_load<U16, MAXI>(sa, c0 + CU, tid, nthreads, pre, pre_shift);
+        {
             const int c = c0 + CU + cl < n_chan ? c0 + CU + cl : n_chan - 1;
-            d_next = dmine[c];
-            f_next = sa.dfirst[c];
-            if (keep) z_next = keep[c] == 0;
+            d_next = global(dmine)[c];
+            f_next = global(sa.dfirst)[c];
+            k_next = global(kp)[keep ? c : 0];
         }
 
         if (active) {

@@ -173,8 +173,8 @@ amber_status amber_subband_dedisperse(const int32_t *d_delay1, const int32_t *d_
         return fail(AMBER_E_SHAPE, "n_in=%lld < n_out=%lld + max_delay=%d", (long long)n_in, (long long)n_out,
                     info->max_delay);
     const int64_t n1 = n_out + info->max_delay2;  // step-one samples per row
-    if (work_stride < n1 || work_stride % 2 != 0 || work_stride < 16)
-        return fail(AMBER_E_SHAPE, "work_stride=%lld must be even, >= 16 and >= n_out + max_delay2 = %lld",
+    if (work_stride < n1 || work_stride % 2 != 0 || work_stride < 32)
+        return fail(AMBER_E_SHAPE, "work_stride=%lld must be even, >= 32 and >= n_out + max_delay2 = %lld",
                     (long long)work_stride, (long long)n1);
     if (((uintptr_t)d_work & 3) != 0) return fail(AMBER_E_ARG, "d_work must be 4-byte aligned");
     if (dd_stride < n_out) return fail(AMBER_E_SHAPE, "dd_stride=%lld < n_out=%lld", (long long)dd_stride, (long long)n_out);
