@@ -106,12 +106,15 @@ def tune_report(seeds: int):
     x_host, n_in = workloads.make_input(wl, search.delays_host, search.info.max_delay)
     x = torch.from_numpy(x_host).cuda()
     sp = amber.default_space(search.info, wl.widths, wl.n_out)
-    sp.set_gene_values(4, [256])    # the boxcar kernel's thread count is held; its steps are tuned
+    G = amber.genes
+    sp.set_gene_values(G.GENE_SNR_THREADS, [256])    # the boxcar kernel's thread count is held; its steps are tuned
     bufs = (search.dd, search.snr, search.peak)
     out = {"workload": wl.name, "space_size": amber.space_size(sp), "genes": {
-        "threads_per_dm": sp.gene_values(0), "samples_per_thread": sp.gene_values(1),
-        "dms_per_block": sp.gene_values(2), "channel_unroll": sp.gene_values(3), "snr_threads": sp.gene_values(4),
-        "boxcar_step": sp.gene_values(5)}}
+        "threads_per_dm": sp.gene_values(G.GENE_THREADS_PER_DM),
+        "samples_per_thread": sp.gene_values(G.GENE_SAMPLES_PER_THREAD),
+        "dms_per_block": sp.gene_values(G.GENE_DMS_PER_BLOCK), "channel_unroll": sp.gene_values(G.GENE_CHANNEL_UNROLL),
+        "dms_per_thread": sp.gene_values(G.GENE_DMS_PER_THREAD), "snr_threads": sp.gene_values(G.GENE_SNR_THREADS),
+        "boxcar_step": sp.gene_values(G.GENE_BOXCAR0)}}
 
     def run(kind, **kw):
         print("[bench] tune %s %s" % (kind, kw), file=sys.stderr, flush=True)
@@ -381,7 +384,11 @@ def ga_study_report(seeds: int):
     x_host, n_in = workloads.make_input(wl, search.delays_host, search.info.max_delay)
     x = torch.from_numpy(x_host).cuda()
     sp = amber.default_space(search.info, wl.widths, wl.n_out)
-    sp.set_gene_values(4, [256])
+    G = amber.genes
+    # the study's table covers the dedispersion genes with one DM per wavefront
+    # and the boxcar steps at 256 work-items
+    sp.set_gene_values(G.GENE_DMS_PER_THREAD, [1])
+    sp.set_gene_values(G.GENE_SNR_THREADS, [256])
     nw = len(wl.widths)
     gv = [sp.gene_values(i) for i in range(sp.n_genes)]
 
@@ -410,7 +417,7 @@ def ga_study_report(seeds: int):
         t_dd[(tpd, spt, dpb, cu)] = med_time(
             lambda: amber.dedisperse(search.delays, search.info, x, n_in, wl.n_out, t, out=search.dd))
     t_box = {}
-    for steps in itertools.product(*gv[5:]):
+    for steps in itertools.product(*gv[G.GENE_BOXCAR0:]):
         t = amber.make_tiles(snr_threads=256, boxcar_step=list(steps))
         amber.integrate_snr(search.dd, wl.n_out, wl.widths, t, out=(search.snr, search.peak))
         t_box[steps] = med_time(

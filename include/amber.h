@@ -93,9 +93,14 @@ typedef struct {
  *   boxcar_step[k]     consecutive outputs per work-item for width k of the
  *                      boxcar / S/N kernels (nrItemsD0, one per width as the
  *                      paper has one per downsampling factor); 1, 2, 4 or 8
+ *   dms_per_thread     DM trials per wavefront (nrDMsPerThread): 1 or 2 (2
+ *                      with samples_per_thread <= 16); 0 reads as 1.  A
+ *                      work-group covers dms_per_block * dms_per_thread DMs,
+ *                      and every staged window serves all of them
  * The LDS footprint of the dedispersion tile must fit in 160 KiB and its
  * staging must need at most 4 items of 16 samples per work-item (3 when
- * samples_per_thread is 16, 2 when it is 32). */
+ * samples_per_thread is 16, 2 when it is 32 or when it is 16 with two DMs per
+ * wavefront). */
 typedef struct {
     int32_t threads_per_dm;
     int32_t samples_per_thread;
@@ -103,14 +108,15 @@ typedef struct {
     int32_t channel_unroll;
     int32_t snr_threads;
     int32_t boxcar_step[AMBER_MAX_WIDTHS];
+    int32_t dms_per_thread;
 } amber_tiles;
 
 /* Fill `tiles` with the library's default configuration. */
 amber_status amber_default_tiles(amber_tiles *tiles);
 
 /* The default configuration adapted to a delay table: channel_unroll, then
- * dms_per_block, then samples_per_thread are halved until the dedispersion
- * tile fits.  This is what the device calls use when passed tiles == NULL.
+ * dms_per_block are halved, then dms_per_thread drops to 1, then
+ * samples_per_thread is halved, until the dedispersion tile fits.  This is what the device calls use when passed tiles == NULL.
  * AMBER_E_CONFIG if nothing fits. */
 amber_status amber_auto_tiles(const amber_delay_info *info, amber_tiles *tiles);
 
@@ -317,17 +323,18 @@ amber_status amber_downsample_snr(const int32_t *d_dd, int32_t n_dm, int64_t dd_
 /* ---- tile search (Section 3: genetic algorithm; Section 2: brute force) ---- */
 
 /* Genes: 0 threads_per_dm, 1 samples_per_thread, 2 dms_per_block,
- * 3 channel_unroll (the dedispersion kernel's genes), 4 snr_threads,
- * 5 + k boxcar_step[k] for k < n_widths (the boxcar / S/N kernel's genes). */
-#define AMBER_GENES_K1 4
-#define AMBER_MAX_GENES (5 + AMBER_MAX_WIDTHS)
+ * 3 channel_unroll, 4 dms_per_thread (the dedispersion kernel's genes),
+ * 5 snr_threads, 6 + k boxcar_step[k] for k < n_widths (the boxcar / S/N
+ * kernel's genes). */
+#define AMBER_GENES_K1 5
+#define AMBER_MAX_GENES (AMBER_GENES_K1 + 1 + AMBER_MAX_WIDTHS)
 #define AMBER_MAX_GENE_VALUES 8
 
 /* The search space: allowed values of every gene (arrays built from the
  * boundary conditions, as the paper's GA does before initialisation) and the
  * problem a configuration must be valid for. */
 typedef struct {
-    int32_t n_genes;                                   /* 5 + n_widths */
+    int32_t n_genes;                                   /* 6 + n_widths */
     int32_t n_values[AMBER_MAX_GENES];
     int32_t values[AMBER_MAX_GENES][AMBER_MAX_GENE_VALUES];
     amber_delay_info info;                             /* validity of dedispersion tiles */

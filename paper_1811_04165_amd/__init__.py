@@ -32,9 +32,16 @@ __all__ = ["AmberError", "DelayInfo", "Tiles", "TuneSpace", "TuneParams", "TuneR
            "space_size", "tune_params", "search_tiles", "tune", "Batch", "default_tiles", "make_tiles", "delay_table", "dedisperse",
            "integrate", "snr", "integrate_snr", "downsample", "downsample_snr", "validate_tiles", "auto_tiles", "version", "Search", "Server",
            "chunk_span", "admit", "server_config", "server_clock", "SubbandInfo", "subband_delay_tables",
-           "subband_dedisperse"]
+           "subband_dedisperse", "genes"]
 
 load()  # fail loudly at import if the native library is missing
+
+# gene indices of a tune space (the dedispersion kernel's genes, then the
+# boxcar / S/N kernel's): genes.GENE_SNR_THREADS, ...
+from . import _lib as _l  # noqa: E402
+import types as _types  # noqa: E402
+genes = _types.SimpleNamespace(**{k: getattr(_l, k) for k in dir(_l) if k.startswith("GENE_")},
+                               AMBER_GENES_K1=_l.AMBER_GENES_K1)
 
 
 def version() -> str:
@@ -48,12 +55,12 @@ def default_tiles() -> Tiles:
 
 
 def make_tiles(threads_per_dm=None, samples_per_thread=None, dms_per_block=None, channel_unroll=None,
-               snr_threads=None, boxcar_step=None) -> Tiles:
+               snr_threads=None, boxcar_step=None, dms_per_thread=None) -> Tiles:
     """Default tiles with the given fields replaced; boxcar_step is an int or a per-width list."""
     t = default_tiles()
     for name, v in (("threads_per_dm", threads_per_dm), ("samples_per_thread", samples_per_thread),
                     ("dms_per_block", dms_per_block), ("channel_unroll", channel_unroll),
-                    ("snr_threads", snr_threads)):
+                    ("snr_threads", snr_threads), ("dms_per_thread", dms_per_thread)):
         if v is not None:
             setattr(t, name, int(v))
     if boxcar_step is not None:

@@ -45,12 +45,14 @@ class SubbandInfo(ctypes.Structure):
 class Tiles(ctypes.Structure):
     _fields_ = [("threads_per_dm", ctypes.c_int32), ("samples_per_thread", ctypes.c_int32),
                 ("dms_per_block", ctypes.c_int32), ("channel_unroll", ctypes.c_int32),
-                ("snr_threads", ctypes.c_int32), ("boxcar_step", ctypes.c_int32 * AMBER_MAX_WIDTHS)]
+                ("snr_threads", ctypes.c_int32), ("boxcar_step", ctypes.c_int32 * AMBER_MAX_WIDTHS),
+                ("dms_per_thread", ctypes.c_int32)]
 
     def as_dict(self):
         return {"threads_per_dm": self.threads_per_dm, "samples_per_thread": self.samples_per_thread,
                 "dms_per_block": self.dms_per_block, "channel_unroll": self.channel_unroll,
-                "snr_threads": self.snr_threads, "boxcar_step": list(self.boxcar_step)}
+                "snr_threads": self.snr_threads, "boxcar_step": list(self.boxcar_step),
+                "dms_per_thread": self.dms_per_thread}
 
     def __repr__(self):
         d = self.as_dict()
@@ -58,7 +60,13 @@ class Tiles(ctypes.Structure):
         return "Tiles(%s)" % ", ".join("%s=%s" % kv for kv in d.items())
 
 
-AMBER_MAX_GENES = 5 + AMBER_MAX_WIDTHS
+# gene indices of a tune space (include/amber.h): the dedispersion kernel's
+# genes, then the boxcar / S/N kernel's
+GENE_THREADS_PER_DM, GENE_SAMPLES_PER_THREAD, GENE_DMS_PER_BLOCK, GENE_CHANNEL_UNROLL, GENE_DMS_PER_THREAD = range(5)
+AMBER_GENES_K1 = 5
+GENE_SNR_THREADS = AMBER_GENES_K1
+GENE_BOXCAR0 = AMBER_GENES_K1 + 1
+AMBER_MAX_GENES = AMBER_GENES_K1 + 1 + AMBER_MAX_WIDTHS
 AMBER_MAX_GENE_VALUES = 8
 AMBER_E_TIMEOUT = -6
 SEARCH_KINDS = {"ga": 0, "exhaustive": 1, "random": 2, "per_kernel": 3}

@@ -15,12 +15,15 @@ thread_local std::string g_error;
 amber_tiles make_default_tiles()
 {
     amber_tiles t{};
+    // a sweep on the 1536-channel beam (2048 DMs): two DMs per wavefront with
+    // channel groups of 16 beat the best one-DM tile by 11 % (1.34 vs 1.51 ms)
     t.threads_per_dm = 64;
     t.samples_per_thread = 8;
     t.dms_per_block = 16;
-    t.channel_unroll = 32;
+    t.channel_unroll = 16;
     t.snr_threads = 256;
     for (int k = 0; k < AMBER_MAX_WIDTHS; ++k) t.boxcar_step[k] = 4;
+    t.dms_per_thread = 2;
     return t;
 }
 
@@ -70,7 +73,11 @@ amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out, int in_u
         }
         if (t.channel_unroll > min_cu) t.channel_unroll /= 2;
         else if (t.dms_per_block > 1) { t.dms_per_block /= 2; t.channel_unroll = first.channel_unroll; }
-        else if (t.samples_per_thread > min_spt) {
+        else if (t.dms_per_thread > 1) {
+            t.dms_per_thread = 1;
+            t.dms_per_block = first.dms_per_block;
+            t.channel_unroll = first.channel_unroll;
+        } else if (t.samples_per_thread > min_spt) {
             t.samples_per_thread /= 2;
             t.channel_unroll = first.channel_unroll;
         } else {
@@ -86,6 +93,7 @@ amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info,
     p.spt = t.samples_per_thread;
     p.dpb = t.dms_per_block;
     p.cu = t.channel_unroll;
+    p.dpt = t.dms_per_thread == 0 ? 1 : t.dms_per_thread;
     if (p.tpd < kWave || p.tpd > kMaxThreads || p.tpd % kWave != 0)
         return fail(AMBER_E_CONFIG, "threads_per_dm=%d must be a multiple of 64 in [64, 1024]", p.tpd);
     if (p.spt != 4 && p.spt != 8 && p.spt != 16 && p.spt != 32)
@@ -97,6 +105,11 @@ amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info,
         return fail(AMBER_E_CONFIG, "channel_unroll=%d must be a power of two <= 32", p.cu);
     if (info.max_step < 0 || info.max_delay < 0)
         return fail(AMBER_E_ARG, "delay info has negative max_step or max_delay");
+    if (p.dpt != 1 && p.dpt != 2)
+        return fail(AMBER_E_CONFIG, "dms_per_thread=%d must be 1 or 2", p.dpt);
+    if (p.dpt == 2 && p.spt > 16)
+        return fail(AMBER_E_CONFIG, "dms_per_thread=2 takes samples_per_thread <= 16");
+    if (in_u16 && p.dpt != 1) return fail(AMBER_E_CONFIG, "16-bit input takes dms_per_thread=1");
     if (in_u16 && ((p.spt != 8 && p.spt != 16) || p.cu < 4))
         return fail(AMBER_E_CONFIG, "16-bit input takes samples_per_thread 8 or 16 and channel_unroll >= 4 "
                     "(got %d, %d)", p.spt, p.cu);
@@ -106,7 +119,7 @@ amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info,
     // Offsets a DM of the tile reads at, relative to the first DM's window
     // start (which is rounded down to a dword: 4 uint8 or 2 uint16 samples):
     // [0, omax].
-    const int64_t omax = (int64_t)(p.dpb - 1) * info.max_step + (in_u16 ? 1 : 3);
+    const int64_t omax = (int64_t)(p.dpb * p.dpt - 1) * info.max_step + (in_u16 ? 1 : 3);
     if (omax > (int64_t)1 << 24)
         return fail(AMBER_E_CONFIG, "delay steps too large for one tile (max_step=%d)", info.max_step);
     // a DM reads dwords up to (o >> 1) + tile_t / 2 - 1 of a copy; the copy
@@ -120,7 +133,7 @@ amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info,
     const int64_t items = p.cu * (win / 16);
     p.maxi = (int)((items + p.threads - 1) / p.threads);
     // prefetch registers beside the accumulators
-    const int maxi_cap = in_u16 ? 2 : (p.spt >= 32 ? 2 : (p.spt >= 16 ? 3 : 4));
+    const int maxi_cap = in_u16 ? 2 : (p.spt >= 32 ? 2 : (p.spt >= 16 ? (p.dpt == 2 ? 2 : 3) : 4));
     if (p.maxi > maxi_cap)
         return fail(AMBER_E_CONFIG, "staging needs %d items per work-item (max %d): reduce channel_unroll or "
                     "enlarge the work-group", p.maxi, maxi_cap);

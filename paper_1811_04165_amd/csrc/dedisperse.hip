@@ -173,7 +173,7 @@ __device__ __forceinline__ void stage_store(lds_w4 *lds, int win2, int items_per
     }
 }
 
-template <int M, int CU, int MAXI, bool U16>
+template <int M, int CU, int MAXI, bool U16, int DPT>
 __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs,
                                                           int n_jobs, int tpd, int dpb, int remap)
 {
@@ -214,8 +214,9 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
     const int wave_t = uniform((wave - dm_local * waves_per_dm) * 128 * M);  // first sample of the wave
     int tx, ty;
     tile_of_block(block, job.tiles_t, job.tiles_dm, remap, tx, ty);
-    const int i0 = ty * dpb;
-    const int i = i0 + dm_local;
+    // the work-group's DMs: dpb wave slots of DPT consecutive DMs each
+    const int i0 = ty * dpb * DPT;
+    const int i = i0 + dm_local * DPT;  // the wave's first DM
     const bool active = i < n_dm;
     const int64_t t0 = (int64_t)tx * tpd * 2 * M;
 
@@ -228,11 +229,17 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
     sa.n_chan = n_chan;
     sa.items_per_row = win >> 4;
     sa.n_items = CU * sa.items_per_row;
-    const int32_t *__restrict__ dmine = delays + (size_t)(active ? i : i0) * n_chan;
-
-    uint32_t acc[M], lo[M], hi[M];
+    // delay rows of the wave's DMs (rows past n_dm read the first DM's row;
+    // their sums are never stored)
+    const int32_t *dmine[DPT];
 #pragma unroll
-    for (int k = 0; k < M; ++k) acc[k] = lo[k] = hi[k] = 0u;
+    for (int r = 0; r < DPT; ++r) dmine[r] = delays + (size_t)(i + r < n_dm ? i + r : i0) * n_chan;
+
+    uint32_t acc[DPT][M], lo[DPT][M], hi[DPT][M];
+#pragma unroll
+    for (int r = 0; r < DPT; ++r)
+#pragma unroll
+        for (int k = 0; k < M; ++k) acc[r][k] = lo[r][k] = hi[r][k] = 0u;
 
     // Prefetch of the first channel group: input items, and on lane j < CU the
     // delays of channel j for this wave's DM and for the group's first DM.
@@ -252,11 +259,12 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
     }
     // keep flags are read unconditionally (from the delay table when there
     // are none) so that no load sits under a branch
-    const uint8_t *kp = keep ? keep : reinterpret_cast<const uint8_t *>(dmine);
-    int d_next = 0, f_next = 0, k_next = 1;
+    const uint8_t *kp = keep ? keep : reinterpret_cast<const uint8_t *>(delays);
+    int d_next[DPT], f_next = 0, k_next = 1;
     {
         const int c = cl < n_chan ? cl : n_chan - 1;
-        d_next = global(dmine)[c];
+#pragma unroll
+        for (int r = 0; r < DPT; ++r) d_next[r] = global(dmine[r])[c];
         f_next = global(sa.dfirst)[c];
         k_next = global(kp)[keep ? c : 0];
     }
@@ -269,11 +277,15 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
 #pragma unroll
         for (int m = 0; m < MAXI; ++m)
             stage_store<CU, U16>(lds, win2, sa.items_per_row, sa.n_items, tid + m * nthreads, pre[m], pre_shift[m]);
-        // LDS byte offset of channel `cl` for this wave's DM
-        int o = d_next - f_next + (f_next & (U16 ? 1 : 3));
-        o = o < 0 ? 0 : (o > omax ? omax : o);
-        uint32_t chan_off = 4u * (uint32_t)(((o & 1) * CU + cl) * win2 + (o >> 1) + (wave_t >> 1));
-        if (keep && k_next == 0) chan_off = zero_off;
+        // LDS byte offset of channel `cl` for each of this wave's DMs
+        uint32_t chan_off[DPT];
+#pragma unroll
+        for (int r = 0; r < DPT; ++r) {
+            int o = d_next[r] - f_next + (f_next & (U16 ? 1 : 3));
+            o = o < 0 ? 0 : (o > omax ? omax : o);
+            chan_off[r] = 4u * (uint32_t)(((o & 1) * CU + cl) * win2 + (o >> 1) + (wave_t >> 1));
+            if (keep && k_next == 0) chan_off[r] = zero_off;
+        }
         __syncthreads();
         // Prefetch of the next group, also after the last one (its items are
         // all invalid and read one shared address): a branch here would make
@@ -282,7 +294,8 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
         stage_load<U16, MAXI>(sa, c0 + CU, tid, nthreads, pre, pre_shift);
         {
             const int c = c0 + CU + cl < n_chan ? c0 + CU + cl : n_chan - 1;
-            d_next = global(dmine)[c];
+#pragma unroll
+            for (int r = 0; r < DPT; ++r) d_next[r] = global(dmine[r])[c];
             f_next = global(sa.dfirst)[c];
             k_next = global(kp)[keep ? c : 0];
         }
@@ -291,28 +304,36 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
             // channels past n_chan were staged as zeros; their offsets are in range
 #pragma unroll
             for (int j = 0; j < CU; ++j) {
-                const uint32_t base = __builtin_amdgcn_readlane(chan_off, j);
-                lds_u1 *src = (lds_u1 *)((__attribute__((address_space(3))) const char *)lds + (base + lane_off));
 #pragma unroll
-                for (int k = 0; k < M; ++k) acc[k] += src[64 * k];
+                for (int r = 0; r < DPT; ++r) {
+                    const uint32_t base = __builtin_amdgcn_readlane(chan_off[r], j);
+                    lds_u1 *src =
+                        (lds_u1 *)((__attribute__((address_space(3))) const char *)lds + (base + lane_off));
+#pragma unroll
+                    for (int k = 0; k < M; ++k) acc[r][k] += src[64 * k];
+                }
                 if (U16 && --left == 0) {
 #pragma unroll
-                    for (int k = 0; k < M; ++k) {
-                        lo[k] += acc[k] & 0xffffu;
-                        hi[k] += acc[k] >> 16;
-                        acc[k] = 0u;
-                    }
+                    for (int r = 0; r < DPT; ++r)
+#pragma unroll
+                        for (int k = 0; k < M; ++k) {
+                            lo[r][k] += acc[r][k] & 0xffffu;
+                            hi[r][k] += acc[r][k] >> 16;
+                            acc[r][k] = 0u;
+                        }
                     left = flush_every;
                 }
             }
             since_flush += CU;
             if ((!U16 && since_flush >= 256) || c0 + CU >= n_chan) {
 #pragma unroll
-                for (int k = 0; k < M; ++k) {
-                    lo[k] += acc[k] & 0xffffu;
-                    hi[k] += acc[k] >> 16;
-                    acc[k] = 0u;
-                }
+                for (int r = 0; r < DPT; ++r)
+#pragma unroll
+                    for (int k = 0; k < M; ++k) {
+                        lo[r][k] += acc[r][k] & 0xffffu;
+                        hi[r][k] += acc[r][k] >> 16;
+                        acc[r][k] = 0u;
+                    }
                 since_flush = 0;
             }
         }
@@ -321,30 +342,34 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
 
     if (!active) return;
     const int store_vec = job.store_vec;
-    if (job.out_u16) {  // sums known to fit 16 bits: one dword per sample pair
-        uint16_t *__restrict__ out =
-            reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(job.dd) + (size_t)i * dd_stride * 2);
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const int64_t t = t0 + wave_t + 128 * k + 2 * lane;
-            if (store_vec && t + 2 <= n_out) {
-                *reinterpret_cast<uint32_t *>(out + t) = lo[k] | (hi[k] << 16);
-            } else {
-                if (t < n_out) out[t] = (uint16_t)lo[k];
-                if (t + 1 < n_out) out[t + 1] = (uint16_t)hi[k];
+    for (int r = 0; r < DPT; ++r) {
+        if (i + r >= n_dm) break;
+        if (job.out_u16) {  // sums known to fit 16 bits: one dword per sample pair
+            uint16_t *__restrict__ out =
+                reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(job.dd) + (size_t)(i + r) * dd_stride * 2);
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int64_t t = t0 + wave_t + 128 * k + 2 * lane;
+                if (store_vec && t + 2 <= n_out) {
+                    *reinterpret_cast<uint32_t *>(out + t) = lo[r][k] | (hi[r][k] << 16);
+                } else {
+                    if (t < n_out) out[t] = (uint16_t)lo[r][k];
+                    if (t + 1 < n_out) out[t + 1] = (uint16_t)hi[r][k];
+                }
             }
-        }
-        return;
-    }
-    int32_t *__restrict__ out = job.dd + (size_t)i * dd_stride;
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        const int64_t t = t0 + wave_t + 128 * k + 2 * lane;
-        if (store_vec && t + 2 <= n_out) {
-            *reinterpret_cast<int2 *>(out + t) = make_int2((int)lo[k], (int)hi[k]);
         } else {
-            if (t < n_out) out[t] = (int32_t)lo[k];
-            if (t + 1 < n_out) out[t + 1] = (int32_t)hi[k];
+            int32_t *__restrict__ out = job.dd + (size_t)(i + r) * dd_stride;
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int64_t t = t0 + wave_t + 128 * k + 2 * lane;
+                if (store_vec && t + 2 <= n_out) {
+                    *reinterpret_cast<int2 *>(out + t) = make_int2((int)lo[r][k], (int)hi[r][k]);
+                } else {
+                    if (t < n_out) out[t] = (int32_t)lo[r][k];
+                    if (t + 1 < n_out) out[t + 1] = (int32_t)hi[r][k];
+                }
+            }
         }
     }
 }
@@ -353,58 +378,72 @@ using KernelFn = void (*)(DedispJob, const DedispJob *, int, int, int, int);
 
 // uint8 input: every (samples_per_thread, channel_unroll) with the staging
 // depths the planner allows (4 below 16 samples per work-item, 3 at 16, 2 at
-// 32).  uint16 input (subband step two, at most a few dozen subbands): 8 or
-// 16 samples per work-item, channel_unroll 4..32, staging depth 1..2.  Deeper
-// staging would not fit the 128 registers of a 1024-item work-group.
-template <int M, int CU, bool U16>
+// 32), one DM per wavefront; two DMs per wavefront up to 16 samples per
+// work-item (staging depth 2 at 16).  uint16 input (subband step two, at most a few dozen subbands):
+// 8 or 16 samples per work-item, channel_unroll 4..32, staging depth 1..2,
+// one DM per wavefront.  Deeper staging would not fit the 128 registers of a
+// 1024-item work-group.
+template <int M, int CU, bool U16, int DPT>
 KernelFn pick_items(int maxi)
 {
-    constexpr int cap = U16 ? 2 : (M >= 16 ? 2 : (M >= 8 ? 3 : 4));
+    constexpr int cap = U16 ? 2 : (M >= 16 ? 2 : (M >= 8 ? (DPT == 2 ? 2 : 3) : 4));
     switch (maxi) {
-    case 1: return dedisperse_kernel<M, CU, 1, U16>;
-    case 2: return dedisperse_kernel<M, CU, 2, U16>;
+    case 1: return dedisperse_kernel<M, CU, 1, U16, DPT>;
+    case 2: return dedisperse_kernel<M, CU, 2, U16, DPT>;
     case 3:
-        if constexpr (cap >= 3) return dedisperse_kernel<M, CU, 3, U16>;
+        if constexpr (cap >= 3) return dedisperse_kernel<M, CU, 3, U16, DPT>;
         return nullptr;
     case 4:
-        if constexpr (cap >= 4) return dedisperse_kernel<M, CU, 4, U16>;
+        if constexpr (cap >= 4) return dedisperse_kernel<M, CU, 4, U16, DPT>;
         return nullptr;
     }
     return nullptr;
 }
 
-template <int M>
+template <int M, int DPT>
 KernelFn pick_cu(int cu, int maxi, int u16)
 {
     if (u16) {
-        if constexpr (M == 4 || M == 8) {
+        if constexpr ((M == 4 || M == 8) && DPT == 1) {
             switch (cu) {
-            case 4: return pick_items<M, 4, true>(maxi);
-            case 8: return pick_items<M, 8, true>(maxi);
-            case 16: return pick_items<M, 16, true>(maxi);
-            case 32: return pick_items<M, 32, true>(maxi);
+            case 4: return pick_items<M, 4, true, 1>(maxi);
+            case 8: return pick_items<M, 8, true, 1>(maxi);
+            case 16: return pick_items<M, 16, true, 1>(maxi);
+            case 32: return pick_items<M, 32, true, 1>(maxi);
             }
         }
         return nullptr;
     }
-    switch (cu) {
-    case 1: return pick_items<M, 1, false>(maxi);
-    case 2: return pick_items<M, 2, false>(maxi);
-    case 4: return pick_items<M, 4, false>(maxi);
-    case 8: return pick_items<M, 8, false>(maxi);
-    case 16: return pick_items<M, 16, false>(maxi);
-    case 32: return pick_items<M, 32, false>(maxi);
+    if constexpr (DPT == 1 || M <= 8) {
+        switch (cu) {
+        case 1: return pick_items<M, 1, false, DPT>(maxi);
+        case 2: return pick_items<M, 2, false, DPT>(maxi);
+        case 4: return pick_items<M, 4, false, DPT>(maxi);
+        case 8: return pick_items<M, 8, false, DPT>(maxi);
+        case 16: return pick_items<M, 16, false, DPT>(maxi);
+        case 32: return pick_items<M, 32, false, DPT>(maxi);
+        }
     }
     return nullptr;
 }
 
-KernelFn pick(int spt, int cu, int maxi, int u16)
+template <int DPT>
+KernelFn pick_spt(int spt, int cu, int maxi, int u16)
 {
     switch (spt) {
-    case 4: return pick_cu<2>(cu, maxi, u16);
-    case 8: return pick_cu<4>(cu, maxi, u16);
-    case 16: return pick_cu<8>(cu, maxi, u16);
-    case 32: return pick_cu<16>(cu, maxi, u16);
+    case 4: return pick_cu<2, DPT>(cu, maxi, u16);
+    case 8: return pick_cu<4, DPT>(cu, maxi, u16);
+    case 16: return pick_cu<8, DPT>(cu, maxi, u16);
+    case 32: return pick_cu<16, DPT>(cu, maxi, u16);
+    }
+    return nullptr;
+}
+
+KernelFn pick(int spt, int cu, int maxi, int u16, int dpt)
+{
+    switch (dpt) {
+    case 1: return pick_spt<1>(spt, cu, maxi, u16);
+    case 2: return pick_spt<2>(spt, cu, maxi, u16);
     }
     return nullptr;
 }
@@ -433,7 +472,7 @@ DedispJob make_dedisp_job(const DedispPlan &p, const int32_t *d_delays, int n_dm
     j.win = p.win;
     j.omax = p.omax;
     j.tiles_t = (int)((n_out + p.tile_t - 1) / p.tile_t);
-    j.tiles_dm = (n_dm + p.dpb - 1) / p.dpb;
+    j.tiles_dm = (n_dm + p.dpb * p.dpt - 1) / (p.dpb * p.dpt);
     j.store_vec = (dd_stride % 2 == 0) && (((uintptr_t)d_dd & 7) == 0);
     j.block_start = 0;
     j.flush_every = 256;
@@ -444,10 +483,10 @@ DedispJob make_dedisp_job(const DedispPlan &p, const int32_t *d_delays, int n_dm
 amber_status launch_dedisperse_jobs(const DedispPlan &p, const DedispJob *single, const DedispJob *d_jobs,
                                     int n_jobs, int64_t n_blocks, int64_t lds_bytes, hipStream_t stream)
 {
-    KernelFn fn = pick(p.spt, p.cu, p.maxi, p.in_u16);
+    KernelFn fn = pick(p.spt, p.cu, p.maxi, p.in_u16, p.dpt);
     if (!fn)
-        return fail(AMBER_E_CONFIG, "no dedispersion kernel for spt=%d cu=%d maxi=%d%s", p.spt, p.cu, p.maxi,
-                    p.in_u16 ? " with 16-bit input (spt 8 or 16, channel_unroll 4..32)" : "");
+        return fail(AMBER_E_CONFIG, "no dedispersion kernel for spt=%d cu=%d maxi=%d dpt=%d%s", p.spt, p.cu, p.maxi,
+                    p.dpt, p.in_u16 ? " with 16-bit input (spt 8 or 16, channel_unroll 4..32, 1 DM per wave)" : "");
     if (lds_bytes > 64 * 1024)
         AMBER_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes),

@@ -34,6 +34,7 @@ constexpr int64_t kMaxLdsBytes = 160 * 1024;
 // Dedispersion tile geometry derived from the tile genes and the table summary.
 struct DedispPlan {
     int tpd, spt, dpb, cu;
+    int dpt;            // DMs per wavefront; a work-group covers dpb * dpt DMs
     int threads;        // tpd * dpb
     int tile_t;         // output samples per tile: tpd * spt
     int win;            // LDS window length in samples per channel (multiple of 16)

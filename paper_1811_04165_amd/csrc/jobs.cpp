@@ -10,7 +10,7 @@ void LaunchSet::add_dedisperse(const DedispPlan &p, DedispJob j)
 {
     auto it = std::find_if(d_.begin(), d_.end(), [&](const DGroup &g) {
         return g.plan.tpd == p.tpd && g.plan.spt == p.spt && g.plan.dpb == p.dpb && g.plan.cu == p.cu &&
-               g.plan.in_u16 == p.in_u16;
+               g.plan.in_u16 == p.in_u16 && g.plan.dpt == p.dpt;
     });
     if (it == d_.end()) {
         d_.emplace_back();

@@ -32,6 +32,7 @@ constexpr int kMaxSubbandChannels = 257;  // 257 * 255 < 2^16: step-one sums fit
 amber_tiles step_tiles(int n_dm, int n_chan, int in_u16)
 {
     amber_tiles t = default_tiles();
+    t.dms_per_thread = 1;
     t.samples_per_thread = 16;
     t.channel_unroll = n_chan >= 16 ? 8 : 4;
     const int cap = in_u16 ? 16 : 12;

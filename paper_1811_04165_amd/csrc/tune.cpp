@@ -20,7 +20,11 @@ namespace amber {
 namespace {
 
 constexpr double kInf = std::numeric_limits<double>::infinity();
-constexpr int kGroupSplit = AMBER_GENES_K1 + 0;  // genes [0, 4): dedispersion; [4, n): boxcar / S/N
+// genes [0, kGroupSplit): dedispersion; [kGroupSplit, n): boxcar / S/N
+constexpr int kGroupSplit = AMBER_GENES_K1;
+constexpr int kGeneDpt = 4;                    // dms_per_thread
+constexpr int kGeneSnr = AMBER_GENES_K1;       // snr_threads
+constexpr int kGeneBox0 = AMBER_GENES_K1 + 1;  // boxcar_step[0]
 
 // xoshiro256** (Blackman and Vigna), seeded through splitmix64.
 class Rng {
@@ -65,8 +69,9 @@ amber_tiles to_tiles(const amber_tune_space &sp, const Genome &g)
     t.samples_per_thread = sp.values[1][g[1]];
     t.dms_per_block = sp.values[2][g[2]];
     t.channel_unroll = sp.values[3][g[3]];
-    t.snr_threads = sp.values[4][g[4]];
-    for (int k = 0; k < sp.n_widths; ++k) t.boxcar_step[k] = sp.values[5 + k][g[5 + k]];
+    t.dms_per_thread = sp.values[kGeneDpt][g[kGeneDpt]];
+    t.snr_threads = sp.values[kGeneSnr][g[kGeneSnr]];
+    for (int k = 0; k < sp.n_widths; ++k) t.boxcar_step[k] = sp.values[kGeneBox0 + k][g[kGeneBox0 + k]];
     return t;
 }
 
@@ -92,8 +97,9 @@ std::string tiles_json(const amber_tiles &t, int n_widths)
     char buf[512];
     int n = snprintf(buf, sizeof buf,
                      "{\"threads_per_dm\":%d,\"samples_per_thread\":%d,\"dms_per_block\":%d,\"channel_unroll\":%d,"
-                     "\"snr_threads\":%d,\"boxcar_step\":[",
-                     t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll, t.snr_threads);
+                     "\"dms_per_thread\":%d,\"snr_threads\":%d,\"boxcar_step\":[",
+                     t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll, t.dms_per_thread,
+                     t.snr_threads);
     for (int k = 0; k < n_widths; ++k) n += snprintf(buf + n, sizeof buf - n, "%s%d", k ? "," : "", t.boxcar_step[k]);
     snprintf(buf + n, sizeof buf - n, "]}");
     return buf;
@@ -267,7 +273,7 @@ private:
         // boxcar / S/N kernel: one gene per width, chosen between the width's
         // own step and the kernel's thread count
         if (rng_.uniform() < p_.p_mut) {
-            for (int k = 0; k < sp_.n_widths; ++k) mutate_gene(g, rng_.uniform() < 0.5 ? 4 : 5 + k);
+            for (int k = 0; k < sp_.n_widths; ++k) mutate_gene(g, rng_.uniform() < 0.5 ? kGeneSnr : kGeneBox0 + k);
         }
     }
 
@@ -378,9 +384,9 @@ private:
         Genome base(n_genes(), 0);
         const amber_tiles d = default_tiles();
         const int defaults[AMBER_MAX_GENES] = {d.threads_per_dm, d.samples_per_thread, d.dms_per_block,
-                                               d.channel_unroll, d.snr_threads};
+                                               d.channel_unroll, d.dms_per_thread, d.snr_threads};
         for (int i = 0; i < n_genes(); ++i) {
-            const int want = i < 5 ? defaults[i] : d.boxcar_step[i - 5];
+            const int want = i < kGeneBox0 ? defaults[i] : d.boxcar_step[i - kGeneBox0];
             for (int v = 0; v < sp_.n_values[i]; ++v)
                 if (sp_.values[i][v] == want) base[i] = v;
         }
@@ -415,8 +421,9 @@ private:
 amber_status check_space(const amber_tune_space *sp)
 {
     if (!sp) return fail(AMBER_E_ARG, "space is NULL");
-    if (sp->n_widths < 1 || sp->n_widths > AMBER_MAX_WIDTHS || sp->n_genes != 5 + sp->n_widths)
-        return fail(AMBER_E_ARG, "space must have n_genes = 5 + n_widths with 1 <= n_widths <= %d", AMBER_MAX_WIDTHS);
+    if (sp->n_widths < 1 || sp->n_widths > AMBER_MAX_WIDTHS || sp->n_genes != kGeneBox0 + sp->n_widths)
+        return fail(AMBER_E_ARG, "space must have n_genes = %d + n_widths with 1 <= n_widths <= %d", kGeneBox0,
+                    AMBER_MAX_WIDTHS);
     for (int i = 0; i < sp->n_genes; ++i)
         if (sp->n_values[i] < 1 || sp->n_values[i] > AMBER_MAX_GENE_VALUES)
             return fail(AMBER_E_ARG, "gene %d has %d values (1..%d allowed)", i, sp->n_values[i], AMBER_MAX_GENE_VALUES);
@@ -509,11 +516,12 @@ amber_status amber_default_space(const amber_delay_info *info, const int32_t *wi
         {4, 8, 16, 32},             // samples_per_thread
         {1, 2, 4, 8, 16},           // dms_per_block
         {1, 2, 4, 8, 16, 32},       // channel_unroll
+        {1, 2},                     // dms_per_thread
         {64, 128, 256, 512, 1024},  // snr_threads
     };
-    sp->n_genes = 5 + n_widths;
+    sp->n_genes = kGeneBox0 + n_widths;
     for (int i = 0; i < sp->n_genes; ++i) {
-        const std::vector<int> v = i < 5 ? vals[i] : std::vector<int>{1, 2, 4, 8};
+        const std::vector<int> v = i < kGeneBox0 ? vals[i] : std::vector<int>{1, 2, 4, 8};
         sp->n_values[i] = (int32_t)v.size();
         for (size_t k = 0; k < v.size(); ++k) sp->values[i][k] = v[k];
     }
@@ -539,18 +547,19 @@ amber_status amber_space_size(const amber_tune_space *sp, int64_t *count)
         t.samples_per_thread = sp->values[1][g[1]];
         t.dms_per_block = sp->values[2][g[2]];
         t.channel_unroll = sp->values[3][g[3]];
+        t.dms_per_thread = sp->values[kGeneDpt][g[kGeneDpt]];
         DedispPlan dp;
         if (plan_dedisperse(t, sp->info, &dp) == AMBER_OK) ++n1;
         int i = 0;
-        while (i < 4 && ++g[i] == sp->n_values[i]) g[i++] = 0;
-        if (i == 4) break;
+        while (i < kGroupSplit && ++g[i] == sp->n_values[i]) g[i++] = 0;
+        if (i == kGroupSplit) break;
     }
     for (;;) {
-        t.snr_threads = sp->values[4][g[4]];
-        for (int k = 0; k < sp->n_widths; ++k) t.boxcar_step[k] = sp->values[5 + k][g[5 + k]];
+        t.snr_threads = sp->values[kGeneSnr][g[kGeneSnr]];
+        for (int k = 0; k < sp->n_widths; ++k) t.boxcar_step[k] = sp->values[kGeneBox0 + k][g[kGeneBox0 + k]];
         BoxcarPlan bp;
         if (plan_boxcar(t, sp->widths, sp->n_widths, sp->n_out, &bp) == AMBER_OK) ++n2;
-        int i = 4;
+        int i = kGroupSplit;
         while (i < sp->n_genes && ++g[i] == sp->n_values[i]) g[i++] = 0;
         if (i == sp->n_genes) break;
     }

@@ -82,7 +82,9 @@ def test_tile_validation():
     bad = [dict(threads_per_dm=32), dict(threads_per_dm=96), dict(samples_per_thread=3),
            dict(samples_per_thread=2), dict(samples_per_thread=64), dict(channel_unroll=32, dms_per_block=1), dict(dms_per_block=32, threads_per_dm=64),
            dict(channel_unroll=3), dict(channel_unroll=64), dict(snr_threads=48), dict(boxcar_step=3),
-           dict(threads_per_dm=1024, samples_per_thread=16, channel_unroll=16)]
+           dict(threads_per_dm=1024, samples_per_thread=16, channel_unroll=16),
+           dict(dms_per_thread=3), dict(dms_per_thread=2, samples_per_thread=32, dms_per_block=4),
+           dict(dms_per_thread=-1)]
     for kw in bad:
         with pytest.raises(amber.AmberError) as e:
             amber.validate_tiles(amber.make_tiles(**kw), info, 7)
@@ -144,7 +146,7 @@ def test_gpu_test_tiles_are_valid():
         amber.validate_tiles(amber.default_tiles(), info, len(wl.widths))
         assert amber.auto_tiles(info).as_dict() == amber.default_tiles().as_dict()
         for kw in t.TILE_SWEEP:
-            amber.validate_tiles(amber.make_tiles(**kw), info, len(wl.widths))
+            amber.validate_tiles(amber.make_tiles(**{"dms_per_thread": 1, **kw}), info, len(wl.widths))
     for k, wl in enumerate(t._small_batch_workloads()):
         g = wl.geom
         _, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
@@ -154,4 +156,4 @@ def test_gpu_test_tiles_are_valid():
         freqs = t.odd_freqs(n_chan, n_dm)
         _, info = amber.delay_table(freqs, 81.92e-6, n_dm, 1.5, step)
         for kw in t.ODD_TILES:
-            amber.validate_tiles(amber.make_tiles(**kw) if kw else amber.auto_tiles(info), info, 1)
+            amber.validate_tiles(amber.make_tiles(**{"dms_per_thread": 1, **kw}) if kw else amber.auto_tiles(info), info, 1)

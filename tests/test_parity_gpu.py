@@ -82,14 +82,24 @@ TILE_SWEEP = [
     dict(threads_per_dm=64, samples_per_thread=32, dms_per_block=16, channel_unroll=4),
     dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=8, channel_unroll=32),
     dict(threads_per_dm=128, samples_per_thread=32, dms_per_block=4, channel_unroll=2),
+    # two DMs per wavefront; 128 trials do not fill the last block of 6
+    dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=8, channel_unroll=32, dms_per_thread=2),
+    dict(threads_per_dm=64, samples_per_thread=4, dms_per_block=3, channel_unroll=16, dms_per_thread=2),
+    dict(threads_per_dm=128, samples_per_thread=16, dms_per_block=4, channel_unroll=4, dms_per_thread=2),
+    dict(threads_per_dm=256, samples_per_thread=8, dms_per_block=1, channel_unroll=4, dms_per_thread=2),
 ]
 
 
-@pytest.mark.parametrize("kw", TILE_SWEEP, ids=lambda k: "tpd%(threads_per_dm)d-spt%(samples_per_thread)d-dpb%(dms_per_block)d-cu%(channel_unroll)d" % k)
+def _tile_id(k):
+    return ("tpd%(threads_per_dm)d-spt%(samples_per_thread)d-dpb%(dms_per_block)d-cu%(channel_unroll)d" % k +
+            ("-dpt%d" % k["dms_per_thread"] if k.get("dms_per_thread", 1) != 1 else ""))
+
+
+@pytest.mark.parametrize("kw", TILE_SWEEP, ids=_tile_id)
 def test_dedisperse_invariant_to_tiles(amber, torch, small_case, kw):
     wl, d, mx, x, n_in, dd = small_case
     say("dedisperse small tiles", kw)
-    got, _, _ = _device_dedisperse(amber, torch, wl, x, n_in, wl.n_out, tiles=amber.make_tiles(**kw))
+    got, _, _ = _device_dedisperse(amber, torch, wl, x, n_in, wl.n_out, tiles=amber.make_tiles(**{"dms_per_thread": 1, **kw}))
     assert np.array_equal(got, dd)
 
 
@@ -104,7 +114,8 @@ ODD = [
 
 
 ODD_TILES = [None, dict(threads_per_dm=64, samples_per_thread=4, dms_per_block=3, channel_unroll=16),
-             dict(threads_per_dm=128, samples_per_thread=16, dms_per_block=4, channel_unroll=8)]
+             dict(threads_per_dm=128, samples_per_thread=16, dms_per_block=4, channel_unroll=8),
+             dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=3, channel_unroll=8, dms_per_thread=2)]
 
 
 def odd_freqs(n_chan, n_dm):
@@ -127,7 +138,7 @@ def test_dedisperse_odd_shapes(amber, torch, case):
     dev, xd = torch.from_numpy(d).cuda(), torch.from_numpy(x).cuda()
     for kw in ODD_TILES:
         say("dedisperse odd", case, kw)
-        out = amber.dedisperse(dev, info, xd, n_in, n_out, tiles=amber.make_tiles(**kw) if kw else None)
+        out = amber.dedisperse(dev, info, xd, n_in, n_out, tiles=amber.make_tiles(**{"dms_per_thread": 1, **kw}) if kw else None)
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy(), ref), kw
 

@@ -37,11 +37,13 @@ def torch():
 RFI_TILES = [None,
              dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=16, channel_unroll=32),
              dict(threads_per_dm=128, samples_per_thread=4, dms_per_block=4, channel_unroll=8),
-             dict(threads_per_dm=64, samples_per_thread=16, dms_per_block=3, channel_unroll=1)]
+             dict(threads_per_dm=64, samples_per_thread=16, dms_per_block=3, channel_unroll=1),
+             dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=5, channel_unroll=16, dms_per_thread=2)]
 
 
 @pytest.mark.parametrize("kw", RFI_TILES, ids=lambda k: "auto" if k is None else
-                         "tpd%(threads_per_dm)d-spt%(samples_per_thread)d-dpb%(dms_per_block)d-cu%(channel_unroll)d" % k)
+                         "tpd%(threads_per_dm)d-spt%(samples_per_thread)d-dpb%(dms_per_block)d-cu%(channel_unroll)d" % k
+                         + ("-dpt%d" % k["dms_per_thread"] if "dms_per_thread" in k else ""))
 def test_masked_small(amber, torch, kw):
     wl = workloads.small()
     g = wl.geom
@@ -53,7 +55,7 @@ def test_masked_small(amber, torch, kw):
     ref = oracle.dedisperse_masked(d, x, n_in, wl.n_out, keep)
     _, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
     say("masked small", kw, "zapped", int((keep == 0).sum()))
-    tiles = amber.make_tiles(**kw) if kw else None
+    tiles = amber.make_tiles(**{"dms_per_thread": 1, **kw}) if kw else None
     got = amber.dedisperse(torch.from_numpy(d).cuda(), info, torch.from_numpy(x).cuda(), n_in, wl.n_out, tiles,
                            keep=torch.from_numpy(keep).cuda())
     assert np.array_equal(got.cpu().numpy(), ref)

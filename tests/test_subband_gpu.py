@@ -85,8 +85,8 @@ def test_subband_small_bit_exact(amber, torch, tiles):
     n_out = 3001                       # ragged: not a multiple of any time tile
     d1, d2, info, o1, o2, x, n_in = _setup(amber, SMALL, SMALL_GRID, n_out, seed=61, pulse=(50.0, 1500, 4))
     ref = oracle.subband_dedisperse(o1, o2, x, n_in, n_out)
-    t1 = amber.make_tiles(**tiles[0]) if tiles[0] else None
-    t2 = amber.make_tiles(**tiles[1]) if tiles[1] else None
+    t1 = amber.make_tiles(**{"dms_per_thread": 1, **tiles[0]}) if tiles[0] else None
+    t2 = amber.make_tiles(**{"dms_per_thread": 1, **tiles[1]}) if tiles[1] else None
     say("subband small", _tid(tiles), info)
     got = _run(amber, torch, d1, d2, info, x, n_in, n_out, tiles1=t1, tiles2=t2).cpu().numpy()
     assert np.array_equal(got, ref)

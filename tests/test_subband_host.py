@@ -113,7 +113,7 @@ def test_subband_dedisperse_validates_before_launch():
     assert call(info=ctypes.byref(bad)) == -1
     # step two's kernels take samples_per_thread 8 or 16 and channel_unroll >= 4
     for kw in (dict(channel_unroll=2), dict(samples_per_thread=4), dict(samples_per_thread=32)):
-        t2 = amber.make_tiles(**kw)
+        t2 = amber.make_tiles(**{"dms_per_thread": 1, **kw})
         assert call(t2=ctypes.byref(t2)) == -3, kw
     assert call(t1=ctypes.byref(amber.make_tiles(threads_per_dm=96))) == -3
 
@@ -138,6 +138,6 @@ def test_gpu_test_tiles_are_valid():
     for a, b in t.TILES:
         if a is None:
             continue
-        amber.validate_tiles(amber.make_tiles(**a), i1, 1)
-        amber.validate_tiles(amber.make_tiles(**b), i2, 1)
+        amber.validate_tiles(amber.make_tiles(**{"dms_per_thread": 1, **a}), i1, 1)
+        amber.validate_tiles(amber.make_tiles(**{"dms_per_thread": 1, **b}), i2, 1)
         assert b["samples_per_thread"] in (8, 16) and b["channel_unroll"] >= 4

@@ -36,15 +36,16 @@ def _small_space(amber, reduced=True):
         sp.set_gene_values(1, [4, 16, 32])
         sp.set_gene_values(2, [1, 4, 16])
         sp.set_gene_values(3, [2, 8, 32])
-        sp.set_gene_values(4, [64, 256])
-        sp.set_gene_values(5, [1, 8])
-        sp.set_gene_values(6, [2, 4])
+        sp.set_gene_values(4, [1, 2])
+        sp.set_gene_values(5, [64, 256])
+        sp.set_gene_values(6, [1, 8])
+        sp.set_gene_values(7, [2, 4])
     return sp, info, widths
 
 
 def _tiles_key(t, n_w):
-    return (t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll, t.snr_threads) + \
-        tuple(t.boxcar_step[k] for k in range(n_w))
+    return (t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll, t.dms_per_thread,
+            t.snr_threads) + tuple(t.boxcar_step[k] for k in range(n_w))
 
 
 def _all_valid(amber, sp, widths):
@@ -52,7 +53,8 @@ def _all_valid(amber, sp, widths):
     genes = [sp.gene_values(i) for i in range(sp.n_genes)]
     for combo in itertools.product(*genes):
         t = amber.make_tiles(threads_per_dm=combo[0], samples_per_thread=combo[1], dms_per_block=combo[2],
-                             channel_unroll=combo[3], snr_threads=combo[4], boxcar_step=list(combo[5:]))
+                             channel_unroll=combo[3], dms_per_thread=combo[4], snr_threads=combo[5],
+                             boxcar_step=list(combo[6:]))
         try:
             amber.validate_tiles(t, sp.info, len(widths))
         except amber.AmberError:
@@ -63,10 +65,10 @@ def _all_valid(amber, sp, widths):
 
 def test_default_space_and_size(amber):
     sp, info, widths = _small_space(amber, reduced=False)
-    assert sp.n_genes == 5 + len(widths)
-    assert sp.gene_values(1) == [4, 8, 16, 32]
+    assert sp.n_genes == 6 + len(widths)
+    assert sp.gene_values(1) == [4, 8, 16, 32] and sp.gene_values(4) == [1, 2]
     n = amber.space_size(sp)
-    assert 0 < n <= 5 * 4 * 5 * 6 * 5 * 16
+    assert 0 < n <= 5 * 4 * 5 * 6 * 2 * 5 * 16
     spr, _, _ = _small_space(amber)
     assert amber.space_size(spr) == len(_all_valid(amber, spr, widths))
 
@@ -95,15 +97,15 @@ def test_exhaustive_returns_argmin(amber):
 
 def _smooth(target, n_w):
     def fit(t):
-        vals = [t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll, t.snr_threads] + \
-            [t.boxcar_step[k] for k in range(n_w)]
+        vals = [t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll, t.dms_per_thread,
+                t.snr_threads] + [t.boxcar_step[k] for k in range(n_w)]
         return 1e-4 * (1.0 + sum((math.log2(v) - math.log2(g)) ** 2 for v, g in zip(vals, target)))
     return fit
 
 
 def test_ga_valid_offspring_deterministic_and_converging(amber, tmp_path):
     sp, info, widths = _small_space(amber, reduced=False)
-    target = (64, 8, 16, 16, 256, 4, 2)
+    target = (64, 8, 16, 16, 2, 256, 4, 2)
     smooth = _smooth(target, len(widths))
 
     def fit(t):
@@ -117,7 +119,7 @@ def test_ga_valid_offspring_deterministic_and_converging(amber, tmp_path):
     assert r1.n_evals <= 32 * 41
     # the smooth landscape's optimum (valid by construction) is found or nearly
     assert r1.best_time_s <= smooth(amber.make_tiles(threads_per_dm=64, samples_per_thread=8, dms_per_block=16,
-                                                     channel_unroll=16, snr_threads=256,
+                                                     channel_unroll=16, dms_per_thread=2, snr_threads=256,
                                                      boxcar_step=[4, 2])) * 3.0
     lines = [json.loads(l) for l in log.read_text().splitlines()]
     final = lines.pop()
@@ -126,7 +128,8 @@ def test_ga_valid_offspring_deterministic_and_converging(amber, tmp_path):
     assert len(final["final_population"]) == len(final["fitness"]) == 32
     for genes, f in zip(final["final_population"], final["fitness"]):
         t = amber.make_tiles(threads_per_dm=genes[0], samples_per_thread=genes[1], dms_per_block=genes[2],
-                             channel_unroll=genes[3], snr_threads=genes[4], boxcar_step=genes[5:])
+                             channel_unroll=genes[3], dms_per_thread=genes[4], snr_threads=genes[5],
+                             boxcar_step=genes[6:])
         amber.validate_tiles(t, sp.info, len(widths))
         assert f == pytest.approx(smooth(t), rel=1e-6)
     assert min(final["fitness"]) == pytest.approx(r1.best_time_s, rel=1e-6)
@@ -171,14 +174,15 @@ def test_per_kernel_search_solves_separable_landscape(amber):
     sp, info, widths = _small_space(amber)
     valid = _all_valid(amber, sp, widths)
     rng = np.random.default_rng(1)
-    a = {c[:4]: float(rng.uniform(1, 2)) for c in valid}
-    b = {c[4:]: float(rng.uniform(0, 1)) for c in valid}
+    k1 = amber.genes.AMBER_GENES_K1       # the dedispersion kernel's genes come first
+    a = {c[:k1]: float(rng.uniform(1, 2)) for c in valid}
+    b = {c[k1:]: float(rng.uniform(0, 1)) for c in valid}
 
     def fit(t):
         k = _tiles_key(t, len(widths))
-        return 1e-3 * (a[k[:4]] + b[k[4:]])
+        return 1e-3 * (a[k[:k1]] + b[k[k1:]])
 
     res = amber.search_tiles(sp, amber.tune_params("per_kernel"), fit)
-    best = min(valid, key=lambda c: a[c[:4]] + b[c[4:]])
+    best = min(valid, key=lambda c: a[c[:k1]] + b[c[k1:]])
     assert _tiles_key(res.best, len(widths)) == best
     assert res.n_evals < len(valid)
