@@ -170,8 +170,10 @@ amber_status plan_boxcar(const amber_tiles &t, const int32_t *widths, int32_t n_
     if (p.chunk < 2 * ((maxw + 15) / 16 * 16))
         return fail(AMBER_E_CONFIG, "snr_threads=%d gives chunks of %d samples, too short for width %d", p.threads,
                     p.chunk, maxw);
-    const int64_t n = (int64_t)p.chunk + maxw + 16;  // prefix elements, padded one per 64
-    p.lds_bytes = (n + (n >> 6) + 2) * 4;
+    // prefix elements: the chunk, plus the reads past it of a work-item's
+    // last, partial step; four pad dwords per 64
+    const int64_t n = (int64_t)p.chunk + maxw + 16;
+    p.lds_bytes = (n + 16) * 4;
     *out = p;
     return AMBER_OK;
 }

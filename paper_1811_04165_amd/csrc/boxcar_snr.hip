@@ -7,15 +7,22 @@
 // overlap by H >= max width samples so every output of a chunk finds its whole
 // window inside it; all widths are served from the same prefix array.
 //
-// The prefix array lives in LDS with one pad dword after every 64 (element i
-// at qix(i) = i + i / 64), so that lanes writing 16 consecutive elements each
-// and lanes reading at a stride of 1, 2, 4 or 8 elements hit distinct banks.
+// The prefix array lives in LDS unpadded.  Lane l of the prefix pass owns
+// samples 16 l - 1 .. 16 l + 14 of the chunk (the first lane's first is
+// zero), so its 16 prefix values are Q[16 l .. 16 l + 15], four aligned
+// 16-byte stores.  The statistics read Q[u .. u + 3] and Q[u + w .. u + w + 3]
+// (u a multiple of 4) as one aligned 16-byte load each when 4 divides w, and
+// as dword loads at immediate offsets otherwise, so no per-element index
+// arithmetic remains.  (A layout padded by 4 dwords per 64, or assembling
+// widths 1 to 3 in registers from two aligned groups, measured slower.)
 //
-// S/N statistics per (width, row): the maximum with its first index, packed
-// as one int64 key (value << 32 | ~t) so that a plain max keeps the earliest
-// peak, and FP64 sums of (x - r) and (x - r)^2 about an integer reference r
-// close to the series mean, reduced across wavefronts through LDS and
-// finished in FP64.
+// S/N statistics per (width, row): per work-item the running maximum with its
+// first index (strictly greater replaces it, and each work-item visits its
+// outputs in increasing t), and FP64 sums of (x - r) and (x - r)^2 about an
+// integer reference r close to the series mean.  For the reduction across
+// wavefronts the maximum is packed as one int64 key (value << 32 | ~t) so
+// that a plain max keeps the earliest peak; the finish is FP64.  Bounds are
+// tested per element only in a work-item's last, partial step.
 #include "internal.h"
 
 #include <cfloat>
@@ -24,7 +31,8 @@
 namespace amber {
 namespace {
 
-__device__ __forceinline__ int qix(int i) { return i + (i >> 6); }
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 
 // Widths of the sliding boxcars, or (dec != 0) decimation factors: then entry
 // k is the series of sums of w[k] consecutive samples starting at multiples
@@ -61,6 +69,42 @@ __device__ __forceinline__ void stat_add(Stat &s, int32_t x, int64_t t, double r
     const double d = (double)x - r;
     s.s1 += d;
     s.s2 = fma(d, d, s.s2);
+}
+
+// Running statistics of one work-item: values arrive in increasing t, so a
+// strictly greater value is the only one that replaces the maximum.  Values
+// are > INT32_MIN (|box| < 2^31 by the callers' contract).
+struct Run {
+    int32_t vmax;
+    uint32_t tmax;
+    double s1, s2;
+};
+
+__device__ __forceinline__ void run_init(Run &s)
+{
+    s.vmax = INT32_MIN;
+    s.tmax = 0xffffffffu;
+    s.s1 = 0.0;
+    s.s2 = 0.0;
+}
+
+__device__ __forceinline__ void run_add(Run &s, int32_t x, uint32_t t, double r)
+{
+    const bool up = x > s.vmax;
+    s.vmax = up ? x : s.vmax;
+    s.tmax = up ? t : s.tmax;
+    const double d = (double)x - r;
+    s.s1 += d;
+    s.s2 = fma(d, d, s.s2);
+}
+
+__device__ __forceinline__ Stat run_stat(const Run &s)
+{
+    Stat o;
+    o.key = pack_key(s.vmax, s.tmax);  // the initial state packs to LLONG_MIN
+    o.s1 = s.s1;
+    o.s2 = s.s2;
+    return o;
 }
 
 __device__ __forceinline__ Stat wave_reduce(Stat s)
@@ -118,29 +162,35 @@ __device__ __forceinline__ void block_reduce(Stat (&st)[NW], int n_w, Stat *scra
 }
 
 // Loads samples [cs, cs + chunk) of one row (zero past n_out) and writes the
-// exclusive prefix Q[0..chunk] to LDS (padded layout).  16 contiguous samples
-// per thread.
+// exclusive prefix Q[0 .. chunk) to LDS.  Work-item l loads samples
+// 16 l .. 16 l + 15 and takes sample 16 l - 1 from its left neighbour (zero
+// for the first), so that its 16 prefix values are Q[16 l .. 16 l + 15].
 __device__ __forceinline__ void load_prefix(const int32_t *__restrict__ row, int64_t cs, int64_t n_out, bool vec_ok,
                                             uint32_t *Q, uint32_t *wave_tot)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, waves = blockDim.x >> 6;
     const int64_t base = cs + (int64_t)tid * 16;
-    uint32_t v[16];
+    uint32_t x[16];
     if (vec_ok && base + 16 <= n_out) {
         const int4 *p = reinterpret_cast<const int4 *>(row + base);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int4 x = p[q];
-            v[4 * q + 0] = (uint32_t)x.x; v[4 * q + 1] = (uint32_t)x.y;
-            v[4 * q + 2] = (uint32_t)x.z; v[4 * q + 3] = (uint32_t)x.w;
+            const int4 v = p[q];
+            x[4 * q + 0] = (uint32_t)v.x; x[4 * q + 1] = (uint32_t)v.y;
+            x[4 * q + 2] = (uint32_t)v.z; x[4 * q + 3] = (uint32_t)v.w;
         }
     } else {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) v[e] = (base + e < n_out) ? (uint32_t)row[base + e] : 0u;
+        for (int e = 0; e < 16; ++e) x[e] = (base + e < n_out) ? (uint32_t)row[base + e] : 0u;
     }
+    // sample 16 l - 1: the left lane's last; a wave's first lane reads it
+    uint32_t left = __shfl_up(x[15], 1, 64);
+    if (lane == 0) left = (tid > 0 && base - 1 < n_out) ? (uint32_t)row[base - 1] : 0u;
+    uint32_t v[16];
+    v[0] = left;
 #pragma unroll
-    for (int e = 1; e < 16; ++e) v[e] += v[e - 1];
-    // inclusive scan of thread totals within the wave
+    for (int e = 1; e < 16; ++e) v[e] = v[e - 1] + x[e - 1];
+    // inclusive scan of work-item totals (samples 16 l - 1 .. 16 l + 14) within the wave
     uint32_t incl = v[15];
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -152,47 +202,69 @@ __device__ __forceinline__ void load_prefix(const int32_t *__restrict__ row, int
     if (tid == 0) {
         uint32_t run = 0;
         for (int w = 0; w < waves; ++w) {
-            const uint32_t x = wave_tot[w];
+            const uint32_t y = wave_tot[w];
             wave_tot[w] = run;
-            run += x;
+            run += y;
         }
     }
     __syncthreads();
     const uint32_t excl = incl - v[15] + wave_tot[wave];
+    u32x4 *dst = reinterpret_cast<u32x4 *>(Q + tid * 16);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) Q[qix(tid * 16 + 1 + e)] = v[e] + excl;
-    if (tid == 0) Q[0] = 0u;
+    for (int q = 0; q < 4; ++q)
+        dst[q] = u32x4{v[4 * q] + excl, v[4 * q + 1] + excl, v[4 * q + 2] + excl, v[4 * q + 3] + excl};
     __syncthreads();
 }
 
+// Loads Q[base .. base + S) (logical indices).  S >= 4 and base a multiple
+// of 4: one aligned 16-byte load per group of four; otherwise dword loads.
+template <int S>
+__device__ __forceinline__ void load_q(const uint32_t *Q, int base, bool aligned, uint32_t (&v)[S])
+{
+    if (S >= 4 && aligned) {
+#pragma unroll
+        for (int q = 0; q < S / 4; ++q) {
+            const u32x4 x = *reinterpret_cast<const u32x4 *>(Q + base + 4 * q);
+            v[4 * q + 0] = x.x;
+            v[4 * q + 1] = x.y;
+            v[4 * q + 2] = x.z;
+            v[4 * q + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < S; ++s) v[s] = Q[base + s];
+    }
+}
+
 // Accumulates width w over the chunk's outputs [cs, cs + outs) with S
-// consecutive outputs per thread per step.
+// consecutive outputs per work-item per step.
 template <int S>
 __device__ __forceinline__ void width_stats(const uint32_t *Q, int w, int outs, int64_t cs, int64_t n_valid, double r,
-                                            Stat &st)
+                                            Run &st)
 {
+    const bool w_aligned = (w & 3) == 0;
     for (int g = threadIdx.x; g * S < outs; g += blockDim.x) {
         const int u = g * S;
         uint32_t a[S], b[S];
-        const int pu = qix(u);  // u .. u + S - 1 share one 64-element block
+        load_q<S>(Q, u, true, a);
+        load_q<S>(Q, u + w, w_aligned, b);
+        const uint32_t t0 = (uint32_t)(cs + u);
+        if (u + S <= outs && cs + u + S <= n_valid) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            a[s] = Q[pu + s];
-            b[s] = Q[qix(u + s + w)];
-        }
+            for (int s = 0; s < S; ++s) run_add(st, (int32_t)(b[s] - a[s]), t0 + s, r);
+        } else {  // the last, partial step
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int64_t t = cs + u + s;
-            if (u + s < outs && t < n_valid) stat_add(st, (int32_t)(b[s] - a[s]), t, r);
+            for (int s = 0; s < S; ++s)
+                if (u + s < outs && cs + u + s < n_valid) run_add(st, (int32_t)(b[s] - a[s]), t0 + s, r);
         }
     }
 }
 
 // Accumulates the decimated series of factor f over the bins j whose first
-// sample j f lies in [cs, cs + outs), j < n_bins, S bins per thread per step.
+// sample j f lies in [cs, cs + outs), j < n_bins, S bins per work-item per step.
 template <int S>
 __device__ __forceinline__ void dec_stats(const uint32_t *Q, int f, int outs, int64_t cs, int64_t n_bins, double r,
-                                          Stat &st)
+                                          Run &st)
 {
     const int64_t j_lo = (cs + f - 1) / f;
     int64_t j_end = (cs + outs + f - 1) / f;
@@ -203,14 +275,14 @@ __device__ __forceinline__ void dec_stats(const uint32_t *Q, int f, int outs, in
             const int64_t j = j_lo + jj + s;
             if (j < j_end) {
                 const int u = (int)(j * f - cs);
-                stat_add(st, (int32_t)(Q[qix(u + f)] - Q[qix(u)]), j, r);
+                run_add(st, (int32_t)(Q[u + f] - Q[u]), (uint32_t)j, r);
             }
         }
     }
 }
 
 __device__ __forceinline__ void dec_stats_any(int step, const uint32_t *Q, int f, int outs, int64_t cs,
-                                              int64_t n_bins, double r, Stat &st)
+                                              int64_t n_bins, double r, Run &st)
 {
     switch (step) {
     case 1: dec_stats<1>(Q, f, outs, cs, n_bins, r, st); break;
@@ -221,7 +293,7 @@ __device__ __forceinline__ void dec_stats_any(int step, const uint32_t *Q, int f
 }
 
 __device__ __forceinline__ void width_stats_any(int step, const uint32_t *Q, int w, int outs, int64_t cs,
-                                                int64_t n_valid, double r, Stat &st)
+                                                int64_t n_valid, double r, Run &st)
 {
     switch (step) {
     case 1: width_stats<1>(Q, w, outs, cs, n_valid, r, st); break;
@@ -234,8 +306,10 @@ __device__ __forceinline__ void width_stats_any(int step, const uint32_t *Q, int
 // ---- fused boxcar + S/N: one work-group per dedispersed row ----------------
 // One beam per launch, or a table of beams whose rows are laid out back to
 // back in the grid.
-template <int NW>
-__global__ __launch_bounds__(1024) void integrate_snr_kernel(BoxJob single, const BoxJob *__restrict__ jobs, int n_jobs,
+// MAXT: the work-group size bound the kernel is compiled for; smaller bounds
+// leave more registers per work-item for the NW running statistics.
+template <int NW, int MAXT>
+__global__ __launch_bounds__(MAXT) void integrate_snr_kernel(BoxJob single, const BoxJob *__restrict__ jobs, int n_jobs,
                                                              WidthSet ws, int chunk, int halo)
 {
     extern __shared__ uint4 lds4[];
@@ -255,9 +329,9 @@ __global__ __launch_bounds__(1024) void integrate_snr_kernel(BoxJob single, cons
     const int outs = chunk - halo;
     const double d0 = (double)row[0];
 
-    Stat st[NW];
+    Run st[NW];
 #pragma unroll
-    for (int k = 0; k < NW; ++k) stat_init(st[k]);
+    for (int k = 0; k < NW; ++k) run_init(st[k]);
 
     for (int64_t cs = 0; cs < n_out; cs += outs) {
         load_prefix(row, cs, n_out, job.vec_ok != 0, Q, wave_tot);
@@ -273,7 +347,10 @@ __global__ __launch_bounds__(1024) void integrate_snr_kernel(BoxJob single, cons
         }
         __syncthreads();
     }
-    block_reduce<NW>(st, ws.n, scratch);
+    Stat sr[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) sr[k] = run_stat(st[k]);
+    block_reduce<NW>(sr, ws.n, scratch);
     if ((int)threadIdx.x < ws.n) {
         const int k = threadIdx.x;
         const int w = ws.w[k];
@@ -304,13 +381,13 @@ __global__ __launch_bounds__(1024) void integrate_kernel(const int32_t *__restri
             j_end = j_end < n_bins ? j_end : n_bins;
             for (int64_t j = j_lo + threadIdx.x; j < j_end; j += blockDim.x) {
                 const int u = (int)(j * w - cs);
-                out[j] = (int32_t)(Q[qix(u + w)] - Q[qix(u)]);
+                out[j] = (int32_t)(Q[u + w] - Q[u]);
             }
         } else {
             const int64_t n_valid = n_out - w + 1;
             for (int u = threadIdx.x; u < outs; u += blockDim.x) {
                 const int64_t t = cs + u;
-                if (t < n_valid) out[t] = (int32_t)(Q[qix(u + w)] - Q[qix(u)]);
+                if (t < n_valid) out[t] = (int32_t)(Q[u + w] - Q[u]);
             }
         }
     }
@@ -398,6 +475,24 @@ amber_status launch_integrate_snr_jobs(const BoxcarPlan &p, const amber_tiles &t
     amber_status s = check_chunk(p);
     if (s != AMBER_OK) return s;
     if (n_rows > 0x7fffffff) return fail(AMBER_E_SHAPE, "too many rows (%lld)", (long long)n_rows);
+    // One beam with more than 8 series: passes of at most 8 series through
+    // the 8-series kernel (each pass re-reads the rows, but the statistics of
+    // 16 series per work-item need registers enough to halve the resident
+    // work-groups).
+    if (single && n_widths > 8) {
+        for (int k0 = 0; k0 < n_widths; k0 += 8) {
+            BoxJob j = *single;
+            j.snr += (size_t)k0 * j.n_dm;
+            if (j.peak) j.peak += (size_t)k0 * j.n_dm;
+            amber_tiles tk = t;
+            const int nk = n_widths - k0 < 8 ? n_widths - k0 : 8;
+            for (int k = 0; k < nk; ++k) tk.boxcar_step[k] = t.boxcar_step[k0 + k];
+            if ((s = launch_integrate_snr_jobs(p, tk, &j, nullptr, 1, n_rows, widths + k0, nk, stream, decimate)) !=
+                AMBER_OK)
+                return s;
+        }
+        return AMBER_OK;
+    }
     const WidthSet ws = make_widths(t, widths, n_widths, decimate);
     const int halo = halo_of(p);
     // the stats scratch reuses the prefix buffer after the last chunk
@@ -406,19 +501,23 @@ amber_status launch_integrate_snr_jobs(const BoxcarPlan &p, const amber_tiles &t
     if (lds < need) lds = need;
     const BoxJob one = single ? *single : BoxJob{};
     const dim3 grid((unsigned)n_rows);
-    if (n_widths <= 4) {
-        if ((s = allow_lds(integrate_snr_kernel<4>, lds, "hipFuncSetAttribute(integrate_snr)")) != AMBER_OK) return s;
-        hipLaunchKernelGGL(integrate_snr_kernel<4>, grid, dim3(p.threads), (size_t)lds, stream, one, d_jobs, n_jobs, ws,
-                           p.chunk, halo);
-    } else if (n_widths <= 8) {
-        if ((s = allow_lds(integrate_snr_kernel<8>, lds, "hipFuncSetAttribute(integrate_snr)")) != AMBER_OK) return s;
-        hipLaunchKernelGGL(integrate_snr_kernel<8>, grid, dim3(p.threads), (size_t)lds, stream, one, d_jobs, n_jobs, ws,
-                           p.chunk, halo);
-    } else {
-        if ((s = allow_lds(integrate_snr_kernel<16>, lds, "hipFuncSetAttribute(integrate_snr)")) != AMBER_OK) return s;
-        hipLaunchKernelGGL(integrate_snr_kernel<16>, grid, dim3(p.threads), (size_t)lds, stream, one, d_jobs, n_jobs,
-                           ws, p.chunk, halo);
-    }
+    const int maxt = p.threads <= 256 ? 256 : (p.threads <= 512 ? 512 : 1024);
+    auto go = [&](auto kernel) -> amber_status {
+        amber_status st = allow_lds(kernel, lds, "hipFuncSetAttribute(integrate_snr)");
+        if (st != AMBER_OK) return st;
+        hipLaunchKernelGGL(kernel, grid, dim3(p.threads), (size_t)lds, stream, one, d_jobs, n_jobs, ws, p.chunk, halo);
+        return AMBER_OK;
+    };
+    if (n_widths <= 4)
+        s = maxt == 256 ? go(integrate_snr_kernel<4, 256>)
+                        : (maxt == 512 ? go(integrate_snr_kernel<4, 512>) : go(integrate_snr_kernel<4, 1024>));
+    else if (n_widths <= 8)
+        s = maxt == 256 ? go(integrate_snr_kernel<8, 256>)
+                        : (maxt == 512 ? go(integrate_snr_kernel<8, 512>) : go(integrate_snr_kernel<8, 1024>));
+    else
+        s = maxt == 256 ? go(integrate_snr_kernel<16, 256>)
+                        : (maxt == 512 ? go(integrate_snr_kernel<16, 512>) : go(integrate_snr_kernel<16, 1024>));
+    if (s != AMBER_OK) return s;
     AMBER_HIP(hipGetLastError(), "integrate_snr launch");
     return AMBER_OK;
 }
