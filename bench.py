@@ -729,6 +729,81 @@ def subband_report(steps: int, warmup: int, grid_names, bf_steps: int = 3):
             "higher_is_better": True, "workload": wl.name, "steps": steps, "subband": out}
 
 
+def tune_subband_report(seeds: int, grid_name: str = "table2-grid"):
+    """Tile search of the subband pipeline on the 1536-channel beam: GA
+    (several seeds) vs random search (same budget as each GA run) vs
+    per-kernel brute force over both steps' genes (boxcar / S/N genes held at
+    the library's), finalists re-timed interleaved, beside the automatic
+    tiles."""
+    import torch
+    import paper_1811_04165_amd as amber
+    import workloads
+    wl = workloads.beam()
+    g = wl.geom
+    grid = SUBBAND_GRIDS[grid_name]
+    d1, d2, info = amber.subband_delay_tables(g.freqs(), g.t_samp_s, *grid)
+    n_out = wl.n_out
+    n_in = n_out + info.max_delay
+    x = torch.from_numpy(workloads.noise(g.n_chan, n_in, workloads.padded_stride(n_in), seed=12)).cuda()
+    d1d, d2d = torch.from_numpy(d1).cuda(), torch.from_numpy(d2).cuda()
+    n_dm = info.n_coarse * info.n_fine
+    n1 = n_out + info.max_delay2
+    work = torch.empty((info.n_subbands * info.n_coarse, (n1 + 63) // 64 * 64), dtype=torch.uint16, device="cuda")
+    dd = torch.empty((n_dm, n_out), dtype=torch.int32, device="cuda")
+    snr = torch.empty((len(wl.widths), n_dm), dtype=torch.float32, device="cuda")
+    peak = torch.empty((len(wl.widths), n_dm), dtype=torch.int32, device="cuda")
+    sp = amber.default_subband_space(info, wl.widths, n_out)
+    G = amber.genes
+    d = amber.default_tiles()
+    sp.set_gene_values(G.SB_GENE_SNR_THREADS, [d.snr_threads])
+    for k in range(len(wl.widths)):
+        sp.set_gene_values(G.SB_GENE_BOXCAR0 + k, [d.boxcar_step[k]])
+    bufs = dict(work=work, out=dd, snr=snr, peak=peak)
+
+    def run(kind, **kw):
+        print("[bench] subband tune %s %s" % (kind, kw), file=sys.stderr, flush=True)
+        return amber.tune_subband(sp, d1d, d2d, x, n_in, amber.tune_params(kind, **kw), **bufs)
+
+    ga = [run("ga", seed=s) for s in range(1, seeds + 1)]
+    rnd = [run("random", seed=100 + s, max_evals=ga[s - 1].n_evals) for s in range(1, seeds + 1)]
+    pk = run("per_kernel")
+
+    def path(t1, t2):
+        amber.subband_dedisperse(d1d, d2d, info, x, n_in, n_out, tiles1=t1, tiles2=t2, out=dd, work=work)
+        amber.integrate_snr(dd, n_out, wl.widths, out=(snr, peak))
+
+    finalists = [(r.step1, r.step2) for r in ga + rnd + [pk]] + [(None, None)]
+    print("[bench] interleaved re-timing of %d finalists" % len(finalists), file=sys.stderr, flush=True)
+    for t1, t2 in finalists:
+        path(t1, t2)
+    times = [[] for _ in finalists]
+    for _ in range(10):
+        for k, (t1, t2) in enumerate(finalists):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            path(t1, t2)
+            b.record()
+            b.synchronize()
+            times[k].append(a.elapsed_time(b) / 1e3)
+    med = [statistics.median(t) for t in times]
+    n = seeds
+    t_ga, t_rnd, t_pk, t_auto = med[:n], med[n:2 * n], med[2 * n], med[2 * n + 1]
+    nw = len(wl.widths)
+    out = {"workload": "%s, %s" % (wl.name, grid_name), "space_size": amber.subband_space_size(sp),
+           "genes": {"step1": [sp.gene_values(i) for i in range(G.SB_GENE_STEP2)],
+                     "step2": [sp.gene_values(i) for i in range(G.SB_GENE_STEP2, G.SB_GENE_SNR_THREADS)]},
+           "retimed_s": {"ga": t_ga, "random": t_rnd, "per_kernel": t_pk, "automatic_tiles": t_auto},
+           "ga_median_over_per_kernel": statistics.median(t_ga) / t_pk,
+           "random_median_over_per_kernel": statistics.median(t_rnd) / t_pk,
+           "automatic_over_ga_median": t_auto / statistics.median(t_ga),
+           "cost": {"ga_evals_median": statistics.median([r.n_evals for r in ga]),
+                    "ga_wall_s_median": statistics.median([r.wall_s for r in ga]),
+                    "per_kernel_evals": pk.n_evals, "per_kernel_wall_s": pk.wall_s},
+           "best": {"ga_seed1": ga[0].as_dict(nw), "per_kernel": pk.as_dict(nw)}}
+    return {"metric": "subband GA tune time", "unit": "s", "value": out["cost"]["ga_wall_s_median"],
+            "higher_is_better": False, "tune_subband": out}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -756,6 +831,8 @@ def main() -> int:
     ap.add_argument("--serve-rates", type=str, default="400,1600", help="offered chunks/s, comma separated")
     ap.add_argument("--rfi", action="store_true",
                     help="instead of the single-beam step: dedispersion with zapped channels beside plain")
+    ap.add_argument("--tune-subband", action="store_true",
+                    help="GA vs random vs per-kernel search over both subband steps' genes (Table 2 grid)")
     ap.add_argument("--subband", type=str, default="", metavar="GRIDS",
                     help="two-step subband dedispersion vs brute force on the beam, for the comma-separated "
                          "grids beam-grid, table2-grid")
@@ -793,6 +870,9 @@ def main() -> int:
         return 0
     if args.downsample:
         print(json.dumps(downsample_report(args.steps, args.warmup)))
+        return 0
+    if args.tune_subband:
+        print(json.dumps(tune_subband_report(5)))
         return 0
     if args.subband:
         print(json.dumps(subband_report(args.steps, args.warmup, [n for n in args.subband.split(",") if n])))

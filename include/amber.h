@@ -408,6 +408,69 @@ amber_status amber_tune(const amber_tune_space *space, const int32_t *d_delays, 
  * p_cross 0.8, p_mut 0.1, pool 20 %, 1 warm-up and 3 timed runs). */
 amber_status amber_default_tune_params(amber_tune_params *p);
 
+/* ---- tile search of the subband pipeline ------------------------------------
+ * The paper's pipeline dedisperses in two steps, each a kernel with its own
+ * genes (Section 2 footnote, Table 3), followed by the smoothing / S/N
+ * kernels.  Genes: 0..4 step one's threads_per_dm, samples_per_thread,
+ * dms_per_block, channel_unroll, dms_per_thread; 5..8 step two's
+ * threads_per_dm, samples_per_thread, dms_per_block, channel_unroll (one DM
+ * per wavefront); 9 snr_threads; 10 + k boxcar_step[k].  The search kinds,
+ * parameters and operators are those of amber_search_tiles, with crossover
+ * and mutation applied per kernel (three kernels). */
+#define AMBER_SUBBAND_GENES_STEP1 5
+#define AMBER_SUBBAND_GENES_STEP2 4
+#define AMBER_MAX_SUBBAND_GENES (AMBER_SUBBAND_GENES_STEP1 + AMBER_SUBBAND_GENES_STEP2 + 1 + AMBER_MAX_WIDTHS)
+
+typedef struct {
+    int32_t n_genes;                                           /* 10 + n_widths */
+    int32_t n_values[AMBER_MAX_SUBBAND_GENES];
+    int32_t values[AMBER_MAX_SUBBAND_GENES][AMBER_MAX_GENE_VALUES];
+    amber_subband_info info;                                   /* validity of both steps' tiles */
+    int32_t n_widths;
+    int32_t widths[AMBER_MAX_WIDTHS];                          /* validity of boxcar tiles */
+    int64_t n_out;
+} amber_subband_tune_space;
+
+typedef struct {
+    amber_tiles step1;    /* step one's tiles; its snr_threads and boxcar_step
+                             hold the boxcar / S/N genes */
+    amber_tiles step2;    /* step two's tiles */
+    double best_time_s;
+    int64_t n_evals;
+    int64_t n_failed;
+    int64_t space_size;
+    double wall_s;
+} amber_subband_tune_result;
+
+/* Fitness callback of the subband search (as amber_fitness_fn). */
+typedef int32_t (*amber_subband_fitness_fn)(const amber_tiles *step1, const amber_tiles *step2, void *user,
+                                            double *seconds);
+
+/* The default subband search space for a problem: powers of two (and the
+ * automatic choices' DM blocks 6 and 12) within the kernels' bounds. */
+amber_status amber_default_subband_space(const amber_subband_info *info, const int32_t *widths, int32_t n_widths,
+                                         int64_t n_out, amber_subband_tune_space *space);
+
+/* Number of valid joint configurations of a subband space. */
+amber_status amber_subband_space_size(const amber_subband_tune_space *space, int64_t *count);
+
+/* Runs the search of p->search over a subband space with a caller-supplied
+ * fitness (host only).  Logging as amber_search_tiles. */
+amber_status amber_search_subband_tiles(const amber_subband_tune_space *space, const amber_tune_params *p,
+                                        amber_subband_fitness_fn fn, void *user, amber_subband_tune_result *result,
+                                        const char *log_jsonl_path);
+
+/* amber_search_subband_tiles with the device evaluator: fitness = GPU time
+ * (HIP events, median of p->reps after p->warmup runs) of
+ * amber_subband_dedisperse followed by amber_integrate_snr of its n_coarse *
+ * n_fine trials, on the caller's buffers (as for those calls).  Synchronises
+ * `stream`. */
+amber_status amber_tune_subband(const amber_subband_tune_space *space, const int32_t *d_delay1,
+                                const int32_t *d_delay2, const uint8_t *d_in, int64_t in_stride, int64_t n_in,
+                                uint16_t *d_work, int64_t work_stride, int32_t *d_dd, int64_t dd_stride,
+                                float *d_snr, int32_t *d_peak_t, const amber_tune_params *p,
+                                amber_subband_tune_result *result, const char *log_jsonl_path, void *stream);
+
 /* ---- batched beams: several independent beams in one graph launch ---------- */
 
 /* One beam of a batch: its delay table and buffers, as for amber_dedisperse

@@ -25,14 +25,16 @@ from typing import Optional, Sequence
 import numpy as np
 
 from ._lib import (AMBER_E_TIMEOUT, AMBER_MAX_WIDTHS, FITNESS_FN, Beam, ChunkResult, PendingChunk, SEARCH_KINDS,
-                   AmberError, DelayInfo, Geometry, ServerConfig, ServerStats, StreamBeam, SubbandGeometry, SubbandInfo,
-                   Tiles, TuneParams, TuneResult, TuneSpace, check, load)
+                   SUBBAND_FITNESS_FN, AmberError, DelayInfo, Geometry, ServerConfig, ServerStats, StreamBeam,
+                   SubbandGeometry, SubbandInfo, SubbandTuneResult, SubbandTuneSpace, Tiles, TuneParams, TuneResult,
+                   TuneSpace, check, load)
 
 __all__ = ["AmberError", "DelayInfo", "Tiles", "TuneSpace", "TuneParams", "TuneResult", "default_space",
            "space_size", "tune_params", "search_tiles", "tune", "Batch", "default_tiles", "make_tiles", "delay_table", "dedisperse",
            "integrate", "snr", "integrate_snr", "downsample", "downsample_snr", "validate_tiles", "auto_tiles", "version", "Search", "Server",
            "chunk_span", "admit", "server_config", "server_clock", "SubbandInfo", "subband_delay_tables",
-           "subband_dedisperse", "genes"]
+           "subband_dedisperse", "genes", "default_subband_space",
+           "subband_space_size", "search_subband_tiles", "tune_subband"]
 
 load()  # fail loudly at import if the native library is missing
 
@@ -40,7 +42,7 @@ load()  # fail loudly at import if the native library is missing
 # boxcar / S/N kernel's): genes.GENE_SNR_THREADS, ...
 from . import _lib as _l  # noqa: E402
 import types as _types  # noqa: E402
-genes = _types.SimpleNamespace(**{k: getattr(_l, k) for k in dir(_l) if k.startswith("GENE_")},
+genes = _types.SimpleNamespace(**{k: getattr(_l, k) for k in dir(_l) if k.startswith(("GENE_", "SB_GENE"))},
                                AMBER_GENES_K1=_l.AMBER_GENES_K1)
 
 
@@ -387,6 +389,68 @@ def tune(space: TuneSpace, delays, x, n_in: int, params: TuneParams, log_path: O
     check(load().amber_tune(ctypes.byref(space), delays.data_ptr(), x.data_ptr(), x.stride(0), int(n_in),
                             dd.data_ptr(), dd.stride(0), s.data_ptr(), p.data_ptr(), ctypes.byref(params),
                             ctypes.byref(res), log_path.encode() if log_path else None, _stream_handle(stream)))
+    return res
+
+
+def default_subband_space(info: SubbandInfo, widths: Sequence[int], n_out: int) -> SubbandTuneSpace:
+    """The default search space of the subband pipeline (both steps' genes and the boxcar / S/N genes)."""
+    w, wp = _widths_arr(widths)
+    sp = SubbandTuneSpace()
+    check(load().amber_default_subband_space(ctypes.byref(info), wp, len(w), int(n_out), ctypes.byref(sp)))
+    return sp
+
+
+def subband_space_size(space: SubbandTuneSpace) -> int:
+    n = ctypes.c_int64()
+    check(load().amber_subband_space_size(ctypes.byref(space), ctypes.byref(n)))
+    return n.value
+
+
+def search_subband_tiles(space: SubbandTuneSpace, params: TuneParams, fitness,
+                         log_path: Optional[str] = None) -> SubbandTuneResult:
+    """Host-only subband search with a Python fitness(step1_tiles, step2_tiles) -> seconds (None: failure)."""
+    def cb(t1, t2, user, out_p):
+        try:
+            v = fitness(t1.contents, t2.contents)
+            if v is None:
+                return 1
+            out_p[0] = float(v)
+            return 0
+        except Exception:
+            return 1
+
+    cfn = SUBBAND_FITNESS_FN(cb)
+    res = SubbandTuneResult()
+    check(load().amber_search_subband_tiles(ctypes.byref(space), ctypes.byref(params), cfn, None, ctypes.byref(res),
+                                            log_path.encode() if log_path else None))
+    return res
+
+
+def tune_subband(space: SubbandTuneSpace, delay1, delay2, x, n_in: int, params: TuneParams, work=None, out=None,
+                 snr=None, peak=None, log_path: Optional[str] = None, stream=None) -> SubbandTuneResult:
+    """Device search: fitness = GPU time of subband dedispersion + fused boxcar/S/N on x."""
+    torch = _torch()
+    _check_dev(delay1, torch.int32, "delay1", 3)
+    _check_dev(delay2, torch.int32, "delay2", 3)
+    _check_dev(x, torch.uint8, "x", 2)
+    info, n_out, n_w = space.info, space.n_out, space.n_widths
+    n_dm = info.n_coarse * info.n_fine
+    n1 = n_out + info.max_delay2
+    if work is None:
+        work = torch.empty((info.n_subbands * info.n_coarse, (n1 + 63) // 64 * 64), dtype=torch.uint16,
+                           device=x.device)
+    if out is None:
+        out = torch.empty((n_dm, n_out), dtype=torch.int32, device=x.device)
+    if snr is None:
+        snr = torch.empty((n_w, n_dm), dtype=torch.float32, device=x.device)
+    if peak is None:
+        peak = torch.empty((n_w, n_dm), dtype=torch.int32, device=x.device)
+    res = SubbandTuneResult()
+    check(load().amber_tune_subband(ctypes.byref(space), delay1.data_ptr(), delay2.data_ptr(), x.data_ptr(),
+                                    x.stride(0), int(n_in), work.data_ptr(), work.stride(0), out.data_ptr(),
+                                    out.stride(0), snr.data_ptr(), peak.data_ptr(), ctypes.byref(params),
+                                    ctypes.byref(res), log_path.encode() if log_path else None,
+                                    _stream_handle(stream)))
     return res
 
 

@@ -149,6 +149,40 @@ class PendingChunk(ctypes.Structure):
 
 FITNESS_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.POINTER(Tiles), ctypes.c_void_p, ctypes.POINTER(ctypes.c_double))
 
+# gene indices of a subband tune space: step one's dedispersion genes, step
+# two's, then the boxcar / S/N kernel's
+SB_GENES_STEP1, SB_GENES_STEP2 = 5, 4
+SB_GENE_STEP2 = SB_GENES_STEP1
+SB_GENE_SNR_THREADS = SB_GENES_STEP1 + SB_GENES_STEP2
+SB_GENE_BOXCAR0 = SB_GENE_SNR_THREADS + 1
+AMBER_MAX_SUBBAND_GENES = SB_GENE_BOXCAR0 + AMBER_MAX_WIDTHS
+
+
+class SubbandTuneSpace(ctypes.Structure):
+    _fields_ = [("n_genes", ctypes.c_int32), ("n_values", ctypes.c_int32 * AMBER_MAX_SUBBAND_GENES),
+                ("values", (ctypes.c_int32 * AMBER_MAX_GENE_VALUES) * AMBER_MAX_SUBBAND_GENES),
+                ("info", SubbandInfo), ("n_widths", ctypes.c_int32), ("widths", ctypes.c_int32 * AMBER_MAX_WIDTHS),
+                ("n_out", ctypes.c_int64)]
+    gene_values = TuneSpace.gene_values
+    set_gene_values = TuneSpace.set_gene_values
+
+
+class SubbandTuneResult(ctypes.Structure):
+    _fields_ = [("step1", Tiles), ("step2", Tiles), ("best_time_s", ctypes.c_double), ("n_evals", ctypes.c_int64),
+                ("n_failed", ctypes.c_int64), ("space_size", ctypes.c_int64), ("wall_s", ctypes.c_double)]
+
+    def as_dict(self, n_widths=AMBER_MAX_WIDTHS):
+        keys = ("threads_per_dm", "samples_per_thread", "dms_per_block", "channel_unroll")
+        s1, s2 = self.step1.as_dict(), self.step2.as_dict()
+        return {"step1": {k: s1[k] for k in keys + ("dms_per_thread",)}, "step2": {k: s2[k] for k in keys},
+                "snr_threads": s1["snr_threads"], "boxcar_step": s1["boxcar_step"][:n_widths],
+                "best_time_s": self.best_time_s, "n_evals": self.n_evals, "n_failed": self.n_failed,
+                "space_size": self.space_size, "wall_s": self.wall_s}
+
+
+SUBBAND_FITNESS_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.POINTER(Tiles), ctypes.POINTER(Tiles), ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_double))
+
 # (name, restype, argtypes) of every exported symbol the header declares.
 SIGNATURES = [
     ("amber_last_error", ctypes.c_char_p, []),
@@ -192,6 +226,17 @@ SIGNATURES = [
     ("amber_default_tune_params", ctypes.c_int, [ctypes.POINTER(TuneParams)]),
     ("amber_search_tiles", ctypes.c_int, [ctypes.POINTER(TuneSpace), ctypes.POINTER(TuneParams), FITNESS_FN,
                                           ctypes.c_void_p, ctypes.POINTER(TuneResult), ctypes.c_char_p]),
+    ("amber_default_subband_space", ctypes.c_int, [ctypes.POINTER(SubbandInfo), c_i32p, ctypes.c_int32,
+                                                   ctypes.c_int64, ctypes.POINTER(SubbandTuneSpace)]),
+    ("amber_subband_space_size", ctypes.c_int, [ctypes.POINTER(SubbandTuneSpace), ctypes.POINTER(ctypes.c_int64)]),
+    ("amber_search_subband_tiles", ctypes.c_int, [ctypes.POINTER(SubbandTuneSpace), ctypes.POINTER(TuneParams),
+                                                  SUBBAND_FITNESS_FN, ctypes.c_void_p,
+                                                  ctypes.POINTER(SubbandTuneResult), ctypes.c_char_p]),
+    ("amber_tune_subband", ctypes.c_int, [ctypes.POINTER(SubbandTuneSpace), ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.POINTER(TuneParams),
+                                          ctypes.POINTER(SubbandTuneResult), ctypes.c_char_p, ctypes.c_void_p]),
     ("amber_batch_create", ctypes.c_int, [ctypes.POINTER(Beam), ctypes.c_int32, c_i32p, ctypes.c_int32,
                                           ctypes.POINTER(Tiles), ctypes.POINTER(ctypes.c_void_p)]),
     ("amber_batch_run", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),

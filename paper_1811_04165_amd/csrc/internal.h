@@ -48,6 +48,10 @@ amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info,
 // LDS a launch with keep flags adds: the zeroed region zapped channels read
 // (64 lanes x samples_per_thread / 2 dwords).
 inline int64_t mask_lds_bytes(const DedispPlan &p) { return (int64_t)kWave * (p.spt / 2) * 4; }
+// The start of the automatic tile choice of one subband step (n_dm trials over
+// n_chan channels or subbands; in_u16 for step two).
+amber_tiles subband_step_tiles(int n_dm, int n_chan, int in_u16);
+
 // The first valid tiles of a shrinking sequence that starts at `start`
 // (default: the library's defaults).
 amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out, int in_u16 = 0,

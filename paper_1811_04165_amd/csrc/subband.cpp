@@ -29,7 +29,9 @@ constexpr int kMaxSubbandChannels = 257;  // 257 * 255 < 2^16: step-one sums fit
 // keeps at least 4 DM rows, even idle ones: the staging of a window is spread
 // over the whole work-group, and fewer work-items would need more staging
 // registers than its kernels have.
-amber_tiles step_tiles(int n_dm, int n_chan, int in_u16)
+}  // namespace
+
+amber_tiles subband_step_tiles(int n_dm, int n_chan, int in_u16)
 {
     amber_tiles t = default_tiles();
     t.dms_per_thread = 1;
@@ -42,13 +44,15 @@ amber_tiles step_tiles(int n_dm, int n_chan, int in_u16)
     return t;
 }
 
+namespace {
+
 amber_status plan_step(const amber_tiles *given, const amber_delay_info &info, int in_u16, DedispPlan *p)
 {
     amber_tiles t;
     if (given) {
         t = *given;
     } else {
-        const amber_tiles start = step_tiles(info.n_dm, info.n_chan, in_u16);
+        const amber_tiles start = subband_step_tiles(info.n_dm, info.n_chan, in_u16);
         amber_status s = auto_tiles(info, &t, in_u16, &start);
         if (s != AMBER_OK) return s;
     }

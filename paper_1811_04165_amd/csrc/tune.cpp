@@ -105,12 +105,32 @@ std::string tiles_json(const amber_tiles &t, int n_widths)
     return buf;
 }
 
+// A search problem: the genes and their value arrays, the kernels they
+// belong to (kernel k owns genes [bounds[k], bounds[k + 1]); the last kernel
+// is the boxcar / S/N kernel, whose first gene is its work-group size and the
+// others one step per width), validity and fitness of a genome, and the
+// library's default value of every gene (the start of per-kernel search).
+class Problem {
+public:
+    virtual ~Problem() = default;
+    virtual int n_genes() const = 0;
+    virtual int n_values(int i) const = 0;
+    virtual int value(int i, int v) const = 0;
+    virtual const std::vector<int> &bounds() const = 0;
+    virtual bool valid(const Genome &g) const = 0;
+    virtual int32_t fitness(const Genome &g, double *seconds) = 0;
+    virtual std::string json(const Genome &g) const = 0;
+    virtual int default_value(int i) const = 0;
+};
+
 class Searcher {
 public:
-    Searcher(const amber_tune_space &sp, const amber_tune_params &p, amber_fitness_fn fn, void *user, FILE *log)
-        : sp_(sp), p_(p), fn_(fn), user_(user), log_(log), rng_(p.seed), t0_(clock_now())
+    Searcher(Problem &pb, const amber_tune_params &p, FILE *log)
+        : pb_(pb), p_(p), log_(log), rng_(p.seed), t0_(clock_now())
     {
     }
+
+    const Genome &best() const { return best_; }
 
     amber_status run(amber_tune_result *res)
     {
@@ -125,7 +145,6 @@ public:
         if (s != AMBER_OK) return s;
         if (best_.empty() || !std::isfinite(best_fit_))
             return fail(AMBER_E_CONFIG, "no configuration of the space could be evaluated");
-        res->best = to_tiles(sp_, best_);
         res->best_time_s = best_fit_;
         res->n_evals = n_evals_;
         res->n_failed = n_failed_;
@@ -139,17 +158,19 @@ private:
         return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
     }
     double elapsed() const { return clock_now() - t0_; }
-    int n_genes() const { return sp_.n_genes; }
-    bool valid(const Genome &g) const { return valid_tiles(sp_, to_tiles(sp_, g)); }
+    int n_genes() const { return pb_.n_genes(); }
+    bool valid(const Genome &g) const { return pb_.valid(g); }
+    int n_kernels() const { return (int)pb_.bounds().size() - 1; }
+    int lo(int k) const { return pb_.bounds()[k]; }
+    int hi(int k) const { return pb_.bounds()[k + 1]; }
 
     double evaluate(const Genome &g)
     {
         const std::string k = key_of(g);
         auto it = cache_.find(k);
         if (it != cache_.end()) return it->second;
-        const amber_tiles t = to_tiles(sp_, g);
         double sec = kInf;
-        const int32_t rc = fn_(&t, user_, &sec);
+        const int32_t rc = pb_.fitness(g, &sec);
         ++n_evals_;
         if (rc != 0 || !std::isfinite(sec) || sec < 0.0 || (p_.eval_timeout_s > 0.0 && sec > p_.eval_timeout_s)) {
             sec = kInf;
@@ -167,7 +188,7 @@ private:
     void log_line(int generation)
     {
         if (!log_) return;
-        const std::string best = best_.empty() ? "null" : tiles_json(to_tiles(sp_, best_), sp_.n_widths);
+        const std::string best = best_.empty() ? "null" : pb_.json(best_);
         fprintf(log_, "{\"generation\":%d,\"evals\":%lld,\"failed\":%lld,\"best_time_s\":%.9g,\"wall_s\":%.6f,\"best\":%s}\n",
                 generation, (long long)n_evals_, (long long)n_failed_, std::isfinite(best_fit_) ? best_fit_ : -1.0,
                 elapsed(), best.c_str());
@@ -184,7 +205,7 @@ private:
             out += i ? ",[" : "[";
             for (int k = 0; k < n_genes(); ++k) {
                 if (k) out += ",";
-                out += std::to_string(sp_.values[k][pop[i][k]]);
+                out += std::to_string(pb_.value(k, pop[i][k]));
             }
             out += "]";
         }
@@ -203,7 +224,7 @@ private:
     {
         g.assign(n_genes(), 0);
         for (int attempt = 0; attempt < 100000; ++attempt) {
-            for (int i = 0; i < n_genes(); ++i) g[i] = rng_.below(sp_.n_values[i]);
+            for (int i = 0; i < n_genes(); ++i) g[i] = rng_.below(pb_.n_values(i));
             if (valid(g)) return true;
         }
         return false;
@@ -251,7 +272,7 @@ private:
     // if there is one.
     void mutate_gene(Genome &g, int i)
     {
-        const int n = sp_.n_values[i];
+        const int n = pb_.n_values(i);
         if (n < 2) return;
         const int old = g[i];
         std::vector<int> cand;
@@ -268,12 +289,15 @@ private:
 
     void mutate(Genome &g)
     {
-        // dedispersion kernel: one of its genes
-        if (rng_.uniform() < p_.p_mut) mutate_gene(g, rng_.below(kGroupSplit));
+        // dedispersion kernels: one of each kernel's genes
+        for (int k = 0; k + 1 < n_kernels(); ++k)
+            if (rng_.uniform() < p_.p_mut) mutate_gene(g, lo(k) + rng_.below(hi(k) - lo(k)));
         // boxcar / S/N kernel: one gene per width, chosen between the width's
         // own step and the kernel's thread count
+        const int kb = n_kernels() - 1;
         if (rng_.uniform() < p_.p_mut) {
-            for (int k = 0; k < sp_.n_widths; ++k) mutate_gene(g, rng_.uniform() < 0.5 ? kGeneSnr : kGeneBox0 + k);
+            for (int w = 0; w + 1 < hi(kb) - lo(kb); ++w)
+                mutate_gene(g, rng_.uniform() < 0.5 ? lo(kb) : lo(kb) + 1 + w);
         }
     }
 
@@ -303,10 +327,9 @@ private:
             }
             std::vector<Genome> off(n);
             for (int i = 0; i < n; ++i) off[i] = pop[sel[i]];
-            for (int i = 0; i + 1 < n; i += 2) {
-                if (rng_.uniform() < p_.p_cross) crossover_group(off[i], off[i + 1], 0, kGroupSplit);
-                if (rng_.uniform() < p_.p_cross) crossover_group(off[i], off[i + 1], kGroupSplit, n_genes());
-            }
+            for (int i = 0; i + 1 < n; i += 2)
+                for (int k = 0; k < n_kernels(); ++k)
+                    if (rng_.uniform() < p_.p_cross) crossover_group(off[i], off[i + 1], lo(k), hi(k));
             std::vector<double> off_fit(n);
             for (int i = 0; i < n; ++i) {
                 mutate(off[i]);
@@ -346,7 +369,7 @@ private:
         for (;;) {
             if (valid(g)) f(g);
             int i = lo;
-            while (i < hi && ++g[i] == sp_.n_values[i]) g[i++] = 0;
+            while (i < hi && ++g[i] == pb_.n_values(i)) g[i++] = 0;
             if (i == hi) return;
         }
     }
@@ -375,40 +398,37 @@ private:
         return AMBER_OK;
     }
 
-    // Paper-style brute force: each kernel's genes exhaustively with the other
-    // kernel's genes held (first the dedispersion kernel with the library's
-    // default boxcar genes, then the boxcar / S/N kernel with the best
-    // dedispersion genes found).
+    // Paper-style brute force: each kernel's genes exhaustively, in kernel
+    // order, with the other kernels' genes held: the library's defaults for
+    // kernels not yet searched, the best found for those already searched.
     amber_status per_kernel()
     {
         Genome base(n_genes(), 0);
-        const amber_tiles d = default_tiles();
-        const int defaults[AMBER_MAX_GENES] = {d.threads_per_dm, d.samples_per_thread, d.dms_per_block,
-                                               d.channel_unroll, d.dms_per_thread, d.snr_threads};
         for (int i = 0; i < n_genes(); ++i) {
-            const int want = i < kGeneBox0 ? defaults[i] : d.boxcar_step[i - kGeneBox0];
-            for (int v = 0; v < sp_.n_values[i]; ++v)
-                if (sp_.values[i][v] == want) base[i] = v;
+            const int want = pb_.default_value(i);
+            for (int v = 0; v < pb_.n_values(i); ++v)
+                if (pb_.value(i, v) == want) base[i] = v;
         }
-        Genome best1;
-        double fit1 = kInf;
-        enumerate(base, 0, kGroupSplit, [&](const Genome &g) {
-            const double f = evaluate(g);
-            if (f < fit1) {
-                fit1 = f;
-                best1 = g;
-            }
-        });
-        if (best1.empty()) return fail(AMBER_E_CONFIG, "no valid dedispersion configuration with the default boxcar genes");
-        enumerate(best1, kGroupSplit, n_genes(), [&](const Genome &g) { evaluate(g); });
+        for (int k = 0; k < n_kernels(); ++k) {
+            Genome best_k;
+            double fit_k = kInf;
+            enumerate(base, lo(k), hi(k), [&](const Genome &g) {
+                const double f = evaluate(g);
+                if (f < fit_k) {
+                    fit_k = f;
+                    best_k = g;
+                }
+            });
+            if (best_k.empty())
+                return fail(AMBER_E_CONFIG, "no valid configuration of kernel %d with the other kernels' defaults", k);
+            base = best_k;
+        }
         log_line(-1);
         return AMBER_OK;
     }
 
-    const amber_tune_space &sp_;
+    Problem &pb_;
     const amber_tune_params &p_;
-    amber_fitness_fn fn_;
-    void *user_;
     FILE *log_;
     Rng rng_;
     double t0_;
@@ -416,6 +436,40 @@ private:
     Genome best_;
     double best_fit_ = kInf;
     int64_t n_evals_ = 0, n_failed_ = 0;
+};
+
+// The hot path's search: one dedispersion tile and the boxcar / S/N genes,
+// all in one amber_tiles.
+class TilesProblem : public Problem {
+public:
+    TilesProblem(const amber_tune_space &sp, amber_fitness_fn fn, void *user)
+        : sp_(sp), fn_(fn), user_(user), bounds_{0, kGroupSplit, sp.n_genes}
+    {
+    }
+    int n_genes() const override { return sp_.n_genes; }
+    int n_values(int i) const override { return sp_.n_values[i]; }
+    int value(int i, int v) const override { return sp_.values[i][v]; }
+    const std::vector<int> &bounds() const override { return bounds_; }
+    bool valid(const Genome &g) const override { return valid_tiles(sp_, to_tiles(sp_, g)); }
+    int32_t fitness(const Genome &g, double *sec) override
+    {
+        const amber_tiles t = to_tiles(sp_, g);
+        return fn_(&t, user_, sec);
+    }
+    std::string json(const Genome &g) const override { return tiles_json(to_tiles(sp_, g), sp_.n_widths); }
+    int default_value(int i) const override
+    {
+        const amber_tiles &d = default_tiles();
+        const int k1[] = {d.threads_per_dm, d.samples_per_thread, d.dms_per_block, d.channel_unroll,
+                          d.dms_per_thread, d.snr_threads};
+        return i < kGeneBox0 ? k1[i] : d.boxcar_step[i - kGeneBox0];
+    }
+
+private:
+    const amber_tune_space &sp_;
+    amber_fitness_fn fn_;
+    void *user_;
+    std::vector<int> bounds_;
 };
 
 amber_status check_space(const amber_tune_space *sp)
@@ -428,6 +482,207 @@ amber_status check_space(const amber_tune_space *sp)
         if (sp->n_values[i] < 1 || sp->n_values[i] > AMBER_MAX_GENE_VALUES)
             return fail(AMBER_E_ARG, "gene %d has %d values (1..%d allowed)", i, sp->n_values[i], AMBER_MAX_GENE_VALUES);
     return AMBER_OK;
+}
+
+// ---- subband pipeline ------------------------------------------------------------
+constexpr int kSbStep2 = AMBER_SUBBAND_GENES_STEP1;                // first gene of step two
+constexpr int kSbSnr = AMBER_SUBBAND_GENES_STEP1 + AMBER_SUBBAND_GENES_STEP2;
+constexpr int kSbBox0 = kSbSnr + 1;
+
+struct SubbandTiles {
+    amber_tiles step1, step2;  // step1 also carries the boxcar / S/N genes
+};
+
+SubbandTiles sb_tiles(const amber_subband_tune_space &sp, const Genome &g)
+{
+    SubbandTiles t{default_tiles(), default_tiles()};
+    auto v = [&](int i) { return sp.values[i][g[i]]; };
+    t.step1.threads_per_dm = v(0);
+    t.step1.samples_per_thread = v(1);
+    t.step1.dms_per_block = v(2);
+    t.step1.channel_unroll = v(3);
+    t.step1.dms_per_thread = v(4);
+    t.step2.threads_per_dm = v(kSbStep2 + 0);
+    t.step2.samples_per_thread = v(kSbStep2 + 1);
+    t.step2.dms_per_block = v(kSbStep2 + 2);
+    t.step2.channel_unroll = v(kSbStep2 + 3);
+    t.step2.dms_per_thread = 1;
+    t.step1.snr_threads = t.step2.snr_threads = v(kSbSnr);
+    for (int k = 0; k < sp.n_widths; ++k) t.step1.boxcar_step[k] = t.step2.boxcar_step[k] = v(kSbBox0 + k);
+    return t;
+}
+
+amber_delay_info sb_info1(const amber_subband_info &i)
+{
+    return amber_delay_info{i.n_coarse, i.n_chan / i.n_subbands, i.max_delay1, i.max_step1};
+}
+amber_delay_info sb_info2(const amber_subband_info &i)
+{
+    return amber_delay_info{i.n_fine, i.n_subbands, i.max_delay2, i.max_step2};
+}
+
+bool sb_valid_step(const amber_subband_tune_space &sp, const amber_tiles &t, int step)
+{
+    DedispPlan dp;
+    const bool ok = step == 1 ? plan_dedisperse(t, sb_info1(sp.info), &dp, 0) == AMBER_OK
+                              : plan_dedisperse(t, sb_info2(sp.info), &dp, 1) == AMBER_OK;
+    clear_error();
+    return ok;
+}
+
+bool sb_valid_box(const amber_subband_tune_space &sp, const amber_tiles &t)
+{
+    BoxcarPlan bp;
+    const bool ok = plan_boxcar(t, sp.widths, sp.n_widths, sp.n_out, &bp) == AMBER_OK;
+    clear_error();
+    return ok;
+}
+
+std::string sb_json(const SubbandTiles &t, int n_widths)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf,
+             "{\"step1\":{\"threads_per_dm\":%d,\"samples_per_thread\":%d,\"dms_per_block\":%d,"
+             "\"channel_unroll\":%d,\"dms_per_thread\":%d},\"step2\":{\"threads_per_dm\":%d,"
+             "\"samples_per_thread\":%d,\"dms_per_block\":%d,\"channel_unroll\":%d},\"box\":",
+             t.step1.threads_per_dm, t.step1.samples_per_thread, t.step1.dms_per_block, t.step1.channel_unroll,
+             t.step1.dms_per_thread, t.step2.threads_per_dm, t.step2.samples_per_thread, t.step2.dms_per_block,
+             t.step2.channel_unroll);
+    return std::string(buf) + tiles_json(t.step1, n_widths) + "}";
+}
+
+class SubbandProblem : public Problem {
+public:
+    SubbandProblem(const amber_subband_tune_space &sp, amber_subband_fitness_fn fn, void *user)
+        : sp_(sp), fn_(fn), user_(user), bounds_{0, kSbStep2, kSbSnr, sp.n_genes}
+    {
+        const amber_subband_info &i = sp.info;
+        d1_ = subband_step_tiles(i.n_coarse, i.n_chan / i.n_subbands, 0);
+        d2_ = subband_step_tiles(i.n_fine, i.n_subbands, 1);
+    }
+    int n_genes() const override { return sp_.n_genes; }
+    int n_values(int i) const override { return sp_.n_values[i]; }
+    int value(int i, int v) const override { return sp_.values[i][v]; }
+    const std::vector<int> &bounds() const override { return bounds_; }
+    bool valid(const Genome &g) const override
+    {
+        const SubbandTiles t = sb_tiles(sp_, g);
+        return sb_valid_step(sp_, t.step1, 1) && sb_valid_step(sp_, t.step2, 2) && sb_valid_box(sp_, t.step1);
+    }
+    int32_t fitness(const Genome &g, double *sec) override
+    {
+        const SubbandTiles t = sb_tiles(sp_, g);
+        return fn_(&t.step1, &t.step2, user_, sec);
+    }
+    std::string json(const Genome &g) const override { return sb_json(sb_tiles(sp_, g), sp_.n_widths); }
+    int default_value(int i) const override
+    {
+        const amber_tiles &d = default_tiles();
+        const int v[] = {d1_.threads_per_dm, d1_.samples_per_thread, d1_.dms_per_block, d1_.channel_unroll,
+                         d1_.dms_per_thread, d2_.threads_per_dm, d2_.samples_per_thread, d2_.dms_per_block,
+                         d2_.channel_unroll, d.snr_threads};
+        return i < kSbBox0 ? v[i] : d.boxcar_step[i - kSbBox0];
+    }
+
+private:
+    const amber_subband_tune_space &sp_;
+    amber_subband_fitness_fn fn_;
+    void *user_;
+    std::vector<int> bounds_;
+    amber_tiles d1_, d2_;
+};
+
+amber_status check_subband_space(const amber_subband_tune_space *sp)
+{
+    if (!sp) return fail(AMBER_E_ARG, "space is NULL");
+    if (sp->n_widths < 1 || sp->n_widths > AMBER_MAX_WIDTHS || sp->n_genes != kSbBox0 + sp->n_widths)
+        return fail(AMBER_E_ARG, "space must have n_genes = %d + n_widths with 1 <= n_widths <= %d", kSbBox0,
+                    AMBER_MAX_WIDTHS);
+    const amber_subband_info &i = sp->info;
+    if (i.n_subbands < 1 || i.n_chan < 1 || i.n_chan % i.n_subbands != 0 || i.n_coarse < 1 || i.n_fine < 1)
+        return fail(AMBER_E_ARG, "space has an invalid subband info");
+    for (int g = 0; g < sp->n_genes; ++g)
+        if (sp->n_values[g] < 1 || sp->n_values[g] > AMBER_MAX_GENE_VALUES)
+            return fail(AMBER_E_ARG, "gene %d has %d values (1..%d allowed)", g, sp->n_values[g], AMBER_MAX_GENE_VALUES);
+    return AMBER_OK;
+}
+
+// Times run() on `stream` with HIP events: p.warmup untimed runs, then the
+// median of p.reps timed runs.  Returns nonzero on failure (err receives a
+// device error, which ends the search).
+struct EventTimer {
+    std::vector<hipEvent_t> ev;
+    int warmup = 0, reps = 1;
+    hipStream_t stream = nullptr;
+    amber_status error = AMBER_OK;
+
+    amber_status init(int w, int r, hipStream_t s)
+    {
+        warmup = w;
+        reps = r;
+        stream = s;
+        ev.resize(2 * r);
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail(AMBER_E_DEVICE, "hipEventCreate failed");
+        return AMBER_OK;
+    }
+    ~EventTimer()
+    {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    template <typename F>
+    int32_t time(F run, double *seconds)
+    {
+        for (int w = 0; w < warmup; ++w)
+            if (run() != AMBER_OK) return 1;
+        std::vector<float> ms(reps);
+        for (int r = 0; r < reps; ++r) {
+            if (hipEventRecord(ev[2 * r], stream) != hipSuccess) return 1;
+            if (run() != AMBER_OK) return 1;
+            if (hipEventRecord(ev[2 * r + 1], stream) != hipSuccess) return 1;
+        }
+        if (hipEventSynchronize(ev[2 * reps - 1]) != hipSuccess) {
+            error = AMBER_E_DEVICE;
+            return 1;
+        }
+        for (int r = 0; r < reps; ++r)
+            if (hipEventElapsedTime(&ms[r], ev[2 * r], ev[2 * r + 1]) != hipSuccess) return 1;
+        std::sort(ms.begin(), ms.end());
+        *seconds = 1e-3 * (double)ms[reps / 2];
+        return 0;
+    }
+};
+
+struct SubbandEval {
+    const amber_subband_tune_space *sp;
+    const int32_t *d_delay1, *d_delay2;
+    const uint8_t *d_in;
+    int64_t in_stride, n_in;
+    uint16_t *d_work;
+    int64_t work_stride;
+    int32_t *d_dd;
+    int64_t dd_stride;
+    float *d_snr;
+    int32_t *d_peak;
+    EventTimer timer;
+};
+
+amber_status run_subband_path(SubbandEval &e, const amber_tiles &t1, const amber_tiles &t2)
+{
+    const amber_subband_tune_space &sp = *e.sp;
+    amber_status s = amber_subband_dedisperse(e.d_delay1, e.d_delay2, &sp.info, e.d_in, e.in_stride, e.n_in, e.d_work,
+                                              e.work_stride, e.d_dd, e.dd_stride, sp.n_out, nullptr, &t1, &t2,
+                                              e.timer.stream);
+    if (s != AMBER_OK) return s;
+    return amber_integrate_snr(e.d_dd, sp.info.n_coarse * sp.info.n_fine, e.dd_stride, sp.n_out, sp.widths,
+                               sp.n_widths, e.d_snr, e.d_peak, &t1, e.timer.stream);
+}
+
+int32_t subband_device_fitness(const amber_tiles *t1, const amber_tiles *t2, void *user, double *seconds)
+{
+    SubbandEval &e = *static_cast<SubbandEval *>(user);
+    return e.timer.time([&] { return run_subband_path(e, *t1, *t2); }, seconds);
 }
 
 // ---- device evaluator ---------------------------------------------------------
@@ -585,8 +840,10 @@ amber_status amber_search_tiles(const amber_tune_space *space, const amber_tune_
     *result = amber_tune_result{};
     int64_t size = 0;
     amber_space_size(space, &size);
-    Searcher srch(*space, *p, fn, user, log);
+    TilesProblem pb(*space, fn, user);
+    Searcher srch(pb, *p, log);
     s = srch.run(result);
+    if (s == AMBER_OK) result->best = to_tiles(*space, srch.best());
     result->space_size = size;
     if (log) fclose(log);
     return s;
@@ -627,6 +884,142 @@ amber_status amber_tune(const amber_tune_space *space, const int32_t *d_delays, 
     std::string msg = s != AMBER_OK ? amber_last_error() : "";
     for (auto &ev : e.ev) (void)hipEventDestroy(ev);
     if (e.error != AMBER_OK) return fail(e.error, "device error during the search");
+    if (s != AMBER_OK) return fail(s, "%s", msg.c_str());
+    return AMBER_OK;
+}
+
+amber_status amber_default_subband_space(const amber_subband_info *info, const int32_t *widths, int32_t n_widths,
+                                         int64_t n_out, amber_subband_tune_space *sp)
+{
+    clear_error();
+    if (!info || !widths || !sp) return fail(AMBER_E_ARG, "NULL argument");
+    if (n_widths < 1 || n_widths > AMBER_MAX_WIDTHS) return fail(AMBER_E_ARG, "n_widths=%d out of range", n_widths);
+    *sp = amber_subband_tune_space{};
+    const std::vector<std::vector<int>> vals = {
+        {64, 128, 256},             // step one: threads_per_dm
+        {4, 8, 16},                 //           samples_per_thread
+        {2, 4, 8, 12, 16},          //           dms_per_block
+        {4, 8, 16, 32},             //           channel_unroll
+        {1, 2},                     //           dms_per_thread
+        {64, 128, 256},             // step two: threads_per_dm
+        {8, 16},                    //           samples_per_thread
+        {4, 6, 8, 12, 16},          //           dms_per_block
+        {4, 8, 16, 32},             //           channel_unroll
+        {64, 128, 256, 512, 1024},  // snr_threads
+    };
+    sp->n_genes = kSbBox0 + n_widths;
+    for (int i = 0; i < sp->n_genes; ++i) {
+        const std::vector<int> v = i < kSbBox0 ? vals[i] : std::vector<int>{1, 2, 4, 8};
+        sp->n_values[i] = (int32_t)v.size();
+        for (size_t k = 0; k < v.size(); ++k) sp->values[i][k] = v[k];
+    }
+    sp->info = *info;
+    sp->n_widths = n_widths;
+    for (int k = 0; k < n_widths; ++k) sp->widths[k] = widths[k];
+    sp->n_out = n_out;
+    return check_subband_space(sp);
+}
+
+amber_status amber_subband_space_size(const amber_subband_tune_space *sp, int64_t *count)
+{
+    clear_error();
+    amber_status s = check_subband_space(sp);
+    if (s != AMBER_OK) return s;
+    if (!count) return fail(AMBER_E_ARG, "count is NULL");
+    // the three kernels' validity is independent: count each kernel's genes
+    const int bounds[] = {0, kSbStep2, kSbSnr, sp->n_genes};
+    int64_t total = 1;
+    for (int k = 0; k < 3; ++k) {
+        int64_t n = 0;
+        Genome g(sp->n_genes, 0);
+        for (;;) {
+            const SubbandTiles t = sb_tiles(*sp, g);
+            if (k == 0 ? sb_valid_step(*sp, t.step1, 1) : (k == 1 ? sb_valid_step(*sp, t.step2, 2) : sb_valid_box(*sp, t.step1)))
+                ++n;
+            int i = bounds[k];
+            while (i < bounds[k + 1] && ++g[i] == sp->n_values[i]) g[i++] = 0;
+            if (i == bounds[k + 1]) break;
+        }
+        total *= n;
+    }
+    *count = total;
+    return AMBER_OK;
+}
+
+amber_status amber_search_subband_tiles(const amber_subband_tune_space *space, const amber_tune_params *p,
+                                        amber_subband_fitness_fn fn, void *user, amber_subband_tune_result *result,
+                                        const char *log_jsonl_path)
+{
+    clear_error();
+    amber_status s = check_subband_space(space);
+    if (s != AMBER_OK) return s;
+    if (!p || !fn || !result) return fail(AMBER_E_ARG, "NULL params, fitness or result");
+    if (!(p->p_cross >= 0 && p->p_cross <= 1 && p->p_mut >= 0 && p->p_mut <= 1 && p->pool_frac > 0 && p->pool_frac <= 1))
+        return fail(AMBER_E_ARG, "probabilities must lie in [0, 1] and pool_frac in (0, 1]");
+    FILE *log = nullptr;
+    if (log_jsonl_path && *log_jsonl_path) {
+        log = fopen(log_jsonl_path, "a");
+        if (!log) return fail(AMBER_E_ARG, "cannot open log %s", log_jsonl_path);
+    }
+    *result = amber_subband_tune_result{};
+    int64_t size = 0;
+    amber_subband_space_size(space, &size);
+    SubbandProblem pb(*space, fn, user);
+    Searcher srch(pb, *p, log);
+    amber_tune_result r{};
+    s = srch.run(&r);
+    if (s == AMBER_OK) {
+        const SubbandTiles t = sb_tiles(*space, srch.best());
+        result->step1 = t.step1;
+        result->step2 = t.step2;
+    }
+    result->best_time_s = r.best_time_s;
+    result->n_evals = r.n_evals;
+    result->n_failed = r.n_failed;
+    result->wall_s = r.wall_s;
+    result->space_size = size;
+    if (log) fclose(log);
+    return s;
+}
+
+amber_status amber_tune_subband(const amber_subband_tune_space *space, const int32_t *d_delay1,
+                                const int32_t *d_delay2, const uint8_t *d_in, int64_t in_stride, int64_t n_in,
+                                uint16_t *d_work, int64_t work_stride, int32_t *d_dd, int64_t dd_stride,
+                                float *d_snr, int32_t *d_peak_t, const amber_tune_params *p,
+                                amber_subband_tune_result *result, const char *log_jsonl_path, void *stream)
+{
+    clear_error();
+    amber_status s = check_subband_space(space);
+    if (s != AMBER_OK) return s;
+    if (!p || !d_delay1 || !d_delay2 || !d_in || !d_work || !d_dd || !d_snr || !result)
+        return fail(AMBER_E_ARG, "NULL argument");
+    if (p->reps < 1 || p->reps > 64 || p->warmup < 0) return fail(AMBER_E_ARG, "reps must be in [1, 64], warmup >= 0");
+    SubbandEval e;
+    e.sp = space;
+    e.d_delay1 = d_delay1;
+    e.d_delay2 = d_delay2;
+    e.d_in = d_in;
+    e.in_stride = in_stride;
+    e.n_in = n_in;
+    e.d_work = d_work;
+    e.work_stride = work_stride;
+    e.d_dd = d_dd;
+    e.dd_stride = dd_stride;
+    e.d_snr = d_snr;
+    e.d_peak = d_peak_t;
+    if ((s = e.timer.init(p->warmup, p->reps, (hipStream_t)stream)) != AMBER_OK) return s;
+    // the path must run with the automatic tiles: catches bad buffers before searching
+    s = amber_subband_dedisperse(d_delay1, d_delay2, &space->info, d_in, in_stride, n_in, d_work, work_stride, d_dd,
+                                 dd_stride, space->n_out, nullptr, nullptr, nullptr, stream);
+    if (s == AMBER_OK)
+        s = amber_integrate_snr(d_dd, space->info.n_coarse * space->info.n_fine, dd_stride, space->n_out,
+                                space->widths, space->n_widths, d_snr, d_peak_t, nullptr, stream);
+    if (s != AMBER_OK) return s;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        return fail(AMBER_E_DEVICE, "the subband path failed on the automatic tiles");
+    s = amber_search_subband_tiles(space, p, subband_device_fitness, &e, result, log_jsonl_path);
+    std::string msg = s != AMBER_OK ? amber_last_error() : "";
+    if (e.timer.error != AMBER_OK) return fail(e.timer.error, "device error during the search");
     if (s != AMBER_OK) return fail(s, "%s", msg.c_str());
     return AMBER_OK;
 }

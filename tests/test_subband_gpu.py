@@ -179,3 +179,17 @@ def test_subband_beam_sampled(amber, torch, grid):
     got_rows = got[torch.from_numpy(rows).cuda()].cpu().numpy()
     ref = oracle.subband_dedisperse(o1[:, js, :], o2[js], x, n_in, n_out)
     assert np.array_equal(got_rows, ref)
+
+
+def test_subband_tune_on_device_keeps_parity(amber, torch):
+    """The device search over both steps' genes (a short GA) returns tiles
+    whose pipeline is still bit-exact against the oracle."""
+    n_out = 2048
+    d1, d2, info, o1, o2, x, n_in = _setup(amber, SMALL, SMALL_GRID, n_out, seed=81)
+    sp = amber.default_subband_space(info, (1, 4, 16), n_out)
+    say("subband device tune", amber.subband_space_size(sp))
+    d1d, d2d, xd = torch.from_numpy(d1).cuda(), torch.from_numpy(d2).cuda(), torch.from_numpy(x).cuda()
+    res = amber.tune_subband(sp, d1d, d2d, xd, n_in, amber.tune_params("ga", seed=4, pop=8, generations=3))
+    assert res.n_evals > 0 and res.best_time_s > 0
+    got = amber.subband_dedisperse(d1d, d2d, info, xd, n_in, n_out, tiles1=res.step1, tiles2=res.step2).cpu().numpy()
+    assert np.array_equal(got, oracle.subband_dedisperse(o1, o2, x, n_in, n_out))
