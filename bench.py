@@ -34,6 +34,11 @@ HBM_PEAK_GBS = 8000.0
 # -> 157.3 T sample-additions/s.
 ALU_PEAK_TOPS = 256 * 128 * 2.4e9 * 2 / 1e12
 
+# LDS: 128 B/clk/CU for the 32-bit read forms the dedispersion kernel issues
+# (ds_read_b32, ds_read2st64_b32; microbenchmarked at 110-125 B/clk/CU;
+# 64- and 128-bit reads reach about twice that but need aligned data)
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
+
 METRIC = "DM-trial·samples/s per GPU + % HBM roofline; GA tune time; p99 chunk latency"
 UNIT = "DM-trial·samples/s"
 PMC_FILE = os.path.join(ROOT, "profiles", "dedisperse_beam_traffic.json")
@@ -58,20 +63,50 @@ def measured_traffic(launch_ops: float):
     return rec.get("hbm_bytes_per_launch")
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_stages(d, x, n_in, wl, threads: int):
+    """One oracle pass over the rows of `d`, timed per stage."""
+    import oracle
+    t0 = time.perf_counter()
+    dd = oracle.dedisperse(d, x, n_in, wl.n_out, threads)
+    t1 = time.perf_counter()
+    box = [oracle.boxcar(dd, w, threads) for w in wl.widths]
+    t2 = time.perf_counter()
+    for b in box:
+        oracle.snr(b, threads)
+    t3 = time.perf_counter()
+    return {"dedisperse_s": t1 - t0, "integrate_s": t2 - t1, "snr_s": t3 - t2, "total_s": t3 - t0}
+
+
 def cpu_baseline(x, n_in, wl, budget_rows: int):
     """The oracle (unchanged) on the first `budget_rows` DM trials of the same
-    beam: delay table, dedispersion, boxcar and S/N for every width."""
-    import numpy as np
+    beam, timed per stage: median of five passes on every host core, then one
+    pass on a single core over a quarter of those trials.  The delay table
+    (host FP64, negligible) is built outside the timed passes."""
     import oracle
     g = wl.geom
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    t0 = time.perf_counter()
-    d, mx = oracle.delay_table(g.freqs(), g.t_samp_s, budget_rows, g.dm_first, g.dm_step)
-    oracle.search(d, x, n_in, wl.n_out, wl.widths, threads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": budget_rows * wl.n_out / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
-            "sample": "first %d of %d DM trials of the 1536-ch beam (all %d samples, widths %s); %.1f s" % (
-                budget_rows, g.n_dm, wl.n_out, list(wl.widths), dt)}
+    d, _ = oracle.delay_table(g.freqs(), g.t_samp_s, budget_rows, g.dm_first, g.dm_step)
+    runs = [_oracle_stages(d, x, n_in, wl, threads) for _ in range(5)]
+    med = {k: statistics.median(r[k] for r in runs) for k in runs[0]}
+    rows1 = max(1, budget_rows // 4)
+    one = _oracle_stages(d[:rows1], x, n_in, wl, 1)
+    return {"value": budget_rows * wl.n_out / med["total_s"], "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": "first %d of %d DM trials of the 1536-ch beam (all %d samples, widths %s), median of 5 "
+                      "passes (%.1f s each); single core: first %d trials, one pass (%.1f s)" % (
+                          budget_rows, g.n_dm, wl.n_out, list(wl.widths), med["total_s"], rows1, one["total_s"]),
+            "cpu_model": _cpu_model(), "stages_s": med,
+            "single_core": {"value": rows1 * wl.n_out / one["total_s"], "cores": 1, "stages_s": one}}
 
 
 def time_configs(search, x, configs, reps: int):
@@ -350,8 +385,9 @@ def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitter
         for name, cfg in (("served", dict(max_inflight=64, max_batch=16, n_streams=4)),
                           ("one_at_a_time", dict(max_inflight=1, max_batch=1, n_streams=1))):
             print("[bench] serve %s at %g chunks/s" % (name, rate), file=sys.stderr, flush=True)
-            # overload points run briefly: a backlog holds one pinned staging buffer per queued chunk
-            dur = seconds if rate == rates[0] else min(seconds, 3.0)
+            # points past twice the first rate run briefly: past a path's
+            # capacity its backlog holds one pinned staging buffer per queued chunk
+            dur = seconds if rate <= 2 * rates[0] else min(seconds, 3.0)
             out.setdefault(str(rate), {})[name] = run(rate, warmup_s + dur, **cfg)
     base = out[str(rates[0])]
     return {"metric": "p99 chunk latency", "unit": "ms", "value": base["served"]["latency_ms"]["p99"],
@@ -826,9 +862,10 @@ def main() -> int:
     ap.add_argument("--serve", action="store_true",
                     help="instead of the single-beam step: the streaming service under Poisson arrivals, "
                          "continuous batching vs one chunk at a time")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
-    ap.add_argument("--serve-warmup", type=float, default=1.0)
-    ap.add_argument("--serve-rates", type=str, default="400,1600", help="offered chunks/s, comma separated")
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-rates", type=str, default="400,800,1600",
+                    help="offered chunks/s, comma separated; rates above twice the first run briefly")
     ap.add_argument("--rfi", action="store_true",
                     help="instead of the single-beam step: dedispersion with zapped channels beside plain")
     ap.add_argument("--tune-subband", action="store_true",
@@ -939,6 +976,9 @@ def main() -> int:
     ops = float(g.n_chan) * samples
     achieved = ops / (k1_avg / 1e3) / 1e12
     traffic = measured_traffic(ops)
+    # LDS reads: every addition reads its 16-bit sample from LDS once
+    lds_bytes = 2.0 * ops
+    lds_tbs = lds_bytes / (k1_avg / 1e3) / 1e12
     # whole-path HBM bytes: input once, dd written and read once, S/N tables
     path_bytes = g.n_chan * x.stride(0) + 2 * 4 * samples + 8 * len(wl.widths) * g.n_dm
     k23_avg = statistics.mean(k23_ms)
@@ -956,7 +996,9 @@ def main() -> int:
                    "widths": list(wl.widths), "tiles": tiles.as_dict(), "pulses_found": found},
         "roofline": {"bound": "alu", "kernel": "dedisperse", "achieved": achieved, "peak": ALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
-                     "avg_launch_ms": k1_avg, "ops_per_launch": ops},
+                     "avg_launch_ms": k1_avg, "ops_per_launch": ops,
+                     "lds": {"bytes_per_launch": lds_bytes, "achieved": lds_tbs, "peak": LDS_PEAK_TBS,
+                             "unit": "TB/s", "frac": lds_tbs / LDS_PEAK_TBS}},
         "kernels": {
             "dedisperse_ms": k1_avg,
             "dedisperse_median_ms": statistics.median(k1_ms),
