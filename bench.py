@@ -9,7 +9,9 @@ the timed region.
 
 Prints one JSON line: DM-trial*samples/s, the roofline position of the
 dominant kernel (dedispersion, integer-ALU bound) from HIP events around its
-launches, and the CPU oracle timed on a bounded sample of the same workload.
+launches, the CPU oracle timed on a bounded sample of the same workload, and
+(after the timed region) the wall time of one GA tile search and the p50/p99
+chunk latency of a few seconds of serving.
 """
 from __future__ import annotations
 
@@ -128,10 +130,9 @@ def time_configs(search, x, configs, reps: int):
     return [statistics.median(v) for v in times]
 
 
-def tune_report(seeds: int):
-    """GA (several seeds) vs exhaustive vs random (same budget as each GA run)
-    vs per-kernel brute force, on the 256-channel / 128-DM workload, with the
-    finalists re-timed interleaved."""
+def _small_tune_setup():
+    """The tile-search workload (256 channels, 128 DM trials) on the device and
+    its search space (the boxcar kernel's thread count held, its steps tuned)."""
     import torch
     import paper_1811_04165_amd as amber
     import workloads
@@ -141,9 +142,38 @@ def tune_report(seeds: int):
     x_host, n_in = workloads.make_input(wl, search.delays_host, search.info.max_delay)
     x = torch.from_numpy(x_host).cuda()
     sp = amber.default_space(search.info, wl.widths, wl.n_out)
+    sp.set_gene_values(amber.genes.GENE_SNR_THREADS, [256])
+    return wl, search, x, n_in, sp, (search.dd, search.snr, search.peak)
+
+
+def ga_tune_summary():
+    """One GA search (population 32, 40 generations, seed 1) on the tile-search
+    workload: its wall time and evaluations, and its best tiles re-timed
+    interleaved with the library's default tiles."""
+    import paper_1811_04165_amd as amber
+    wl, search, x, n_in, sp, bufs = _small_tune_setup()
+    r = amber.tune(sp, search.delays, x, n_in, amber.tune_params("ga", seed=1), buffers=bufs)
+    t_ga, t_def = time_configs(search, x, [r.best, amber.auto_tiles(search.info, search.n_out)], reps=30)
+    return {"workload": wl.name, "search": "ga pop 32 x 40 generations, seed 1", "space_size": amber.space_size(sp),
+            "wall_s": r.wall_s, "evals": r.n_evals, "best_s": t_ga, "default_tiles_s": t_def,
+            "best": r.as_dict(len(wl.widths))["best"]}
+
+
+def serve_summary(seconds: float = 5.0, warmup_s: float = 1.0):
+    """The streaming service with continuous batching at the workload's rate
+    (400 chunks/s from 40 beams), briefly."""
+    r = serve_report(40, seconds, warmup_s, [400.0], modes=("served",))["serve"]["by_rate"]["400.0"]["served"]
+    return {"offered_chunks_per_s": 400.0, "seconds": seconds, "warmup_s": warmup_s,
+            "chunks_per_s": r["chunks_per_s"], "value": r["value"], "latency_ms": r["latency_ms"]}
+
+
+def tune_report(seeds: int):
+    """GA (several seeds) vs exhaustive vs random (same budget as each GA run)
+    vs per-kernel brute force, on the 256-channel / 128-DM workload, with the
+    finalists re-timed interleaved."""
+    import paper_1811_04165_amd as amber
+    wl, search, x, n_in, sp, bufs = _small_tune_setup()
     G = amber.genes
-    sp.set_gene_values(G.GENE_SNR_THREADS, [256])    # the boxcar kernel's thread count is held; its steps are tuned
-    bufs = (search.dd, search.snr, search.peak)
     out = {"workload": wl.name, "space_size": amber.space_size(sp), "genes": {
         "threads_per_dm": sp.gene_values(G.GENE_THREADS_PER_DM),
         "samples_per_thread": sp.gene_values(G.GENE_SAMPLES_PER_THREAD),
@@ -180,7 +210,7 @@ def tune_report(seeds: int):
         "ga_cost_fraction_of_exhaustive": statistics.median([r.wall_s for r in ga]) / ex.wall_s,
         "best": {"ga_seed1": ga[0].as_dict(nw)["best"], "exhaustive": ex.as_dict(nw)["best"],
                  "per_kernel": pk.as_dict(nw)["best"]},
-        "default_tiles_s": time_configs(search, x, [amber.auto_tiles(search.info)], reps=100)[0],
+        "default_tiles_s": time_configs(search, x, [amber.auto_tiles(search.info, search.n_out)], reps=100)[0],
     })
     return {"metric": "GA tune time", "unit": "s", "value": out["cost"]["ga_wall_s_median"], "tune": out}
 
@@ -281,7 +311,8 @@ def batched_report(n_beams: int, steps: int, warmup: int):
                 "tune_per_class": tune_cost}}
 
 
-def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitters: int = 4):
+def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitters: int = 4,
+                 modes=("served", "one_at_a_time")):
     """Streaming: Poisson arrivals of 0.5-s chunks from beams of 768 ch / 1024
     DM trials and 1536 ch / 2048 DM trials, served with continuous batching
     vs the same service restricted to one chunk at a time (plain per-chunk
@@ -384,6 +415,8 @@ def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitter
     for rate in rates:
         for name, cfg in (("served", dict(max_inflight=64, max_batch=16, n_streams=4)),
                           ("one_at_a_time", dict(max_inflight=1, max_batch=1, n_streams=1))):
+            if name not in modes:
+                continue
             print("[bench] serve %s at %g chunks/s" % (name, rate), file=sys.stderr, flush=True)
             # points past twice the first rate run briefly: past a path's
             # capacity its backlog holds one pinned staging buffer per queued chunk
@@ -876,6 +909,8 @@ def main() -> int:
     ap.add_argument("--downsample", action="store_true",
                     help="instead of the single-beam step: decimating downsampling + S/N over the factor ladder "
                          "on the dedispersed beam")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="1: also run one GA tile search (tune time) and 5 s of serving (p99 chunk latency)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run a plain device-to-device copy of this many bytes 5 times (for scaling "
                          "hardware byte counters read under a profiler)")
@@ -1009,6 +1044,11 @@ def main() -> int:
         },
         "hbm_frac_path": path_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS,
     }
+    if args.extras:
+        print("[bench] GA tune on the 256-channel workload", file=sys.stderr, flush=True)
+        rec["ga_tune"] = ga_tune_summary()
+        print("[bench] serving at 400 chunks/s", file=sys.stderr, flush=True)
+        rec["serve"] = serve_summary()
     if args.copy_calibration > 0:
         src = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

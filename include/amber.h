@@ -114,11 +114,18 @@ typedef struct {
 /* Fill `tiles` with the library's default configuration. */
 amber_status amber_default_tiles(amber_tiles *tiles);
 
-/* The default configuration adapted to a delay table: channel_unroll, then
- * dms_per_block are halved, then dms_per_thread drops to 1, then
- * samples_per_thread is halved, until the dedispersion tile fits.  This is what the device calls use when passed tiles == NULL.
- * AMBER_E_CONFIG if nothing fits. */
-amber_status amber_auto_tiles(const amber_delay_info *info, amber_tiles *tiles);
+/* The default configuration adapted to a delay table and a series length:
+ * channel_unroll, then dms_per_block are halved, then dms_per_thread drops to
+ * 1, then samples_per_thread is halved, until the dedispersion tile fits.
+ * Then, if n_out > 0 and the dedispersion launch would have fewer than 384
+ * work-groups (1.5 per CU of the 256), the tile is made smaller until it has
+ * that many or neither step is left: samples_per_thread halved down to 4
+ * (channel_unroll 32), then dms_per_thread 1 (channel_unroll 32); a step
+ * whose channel_unroll 32 does not fit keeps the previous channel_unroll.
+ * n_out <= 0 skips this.  This is what
+ * the device calls use when passed tiles == NULL (with their own n_out; the
+ * streaming service with its chunk length).  AMBER_E_CONFIG if nothing fits. */
+amber_status amber_auto_tiles(const amber_delay_info *info, int64_t n_out, amber_tiles *tiles);
 
 /* Check `tiles` against the kernels' space for a problem of this shape;
  * AMBER_OK or AMBER_E_CONFIG (with the reason in amber_last_error). */
@@ -151,7 +158,7 @@ amber_status amber_delay_table(const amber_geometry *g, int32_t *delays, amber_d
  *            multiple of 4; n_in >= n_out + info->max_delay.
  * d_dd:      device int32 [n_dm][dd_stride]; dd_stride >= n_out.  Columns
  *            >= n_out are not written.
- * tiles:     NULL = amber_auto_tiles(info).
+ * tiles:     NULL = amber_auto_tiles(info, n_out).
  * Reads stay inside the n_chan * in_stride input bytes and the LDS tile even
  * if the table does not match info; results are then meaningless but the call
  * cannot fault. */
@@ -492,7 +499,7 @@ typedef struct amber_batch amber_batch;  /* opaque */
  * (each work-group finds its beam in a job table), and beams whose boxcar /
  * S/N tiles coincide share one launch; all beams use the same widths.
  * tiles: per-beam array (e.g. a tuned configuration per shape class) or NULL
- * for amber_auto_tiles of each beam.  The job tables live in device memory
+ * for amber_auto_tiles(info, n_out) of each beam.  The job tables live in device memory
  * owned by the batch (allocated here, freed by amber_batch_destroy).
  * Arguments are validated as the single-beam calls validate them. */
 amber_status amber_batch_create(const amber_beam *beams, int32_t n_beams, const int32_t *widths, int32_t n_widths,
@@ -544,7 +551,7 @@ typedef struct {
     int32_t n_dm;
     double dm_first, dm_step;
     int64_t chunk;            /* samples per chunk L; widths <= L */
-    const amber_tiles *tiles; /* NULL = amber_auto_tiles */
+    const amber_tiles *tiles; /* NULL = amber_auto_tiles(info, chunk) */
 } amber_stream_beam;
 
 typedef struct {

@@ -72,10 +72,11 @@ def make_tiles(threads_per_dm=None, samples_per_thread=None, dms_per_block=None,
     return t
 
 
-def auto_tiles(info: DelayInfo) -> Tiles:
-    """The default tiles adapted to this delay table (what tiles=None uses)."""
+def auto_tiles(info: DelayInfo, n_out: int = 0) -> Tiles:
+    """The default tiles adapted to this delay table and, when n_out > 0, made
+    smaller until the dedispersion grid fills the chip (what tiles=None uses)."""
     t = Tiles()
-    check(load().amber_auto_tiles(ctypes.byref(info), ctypes.byref(t)))
+    check(load().amber_auto_tiles(ctypes.byref(info), int(n_out), ctypes.byref(t)))
     return t
 
 

@@ -188,7 +188,7 @@ SIGNATURES = [
     ("amber_last_error", ctypes.c_char_p, []),
     ("amber_version", ctypes.c_char_p, []),
     ("amber_default_tiles", ctypes.c_int, [ctypes.POINTER(Tiles)]),
-    ("amber_auto_tiles", ctypes.c_int, [ctypes.POINTER(DelayInfo), ctypes.POINTER(Tiles)]),
+    ("amber_auto_tiles", ctypes.c_int, [ctypes.POINTER(DelayInfo), ctypes.c_int64, ctypes.POINTER(Tiles)]),
     ("amber_validate_tiles", ctypes.c_int, [ctypes.POINTER(Tiles), ctypes.POINTER(DelayInfo), ctypes.c_int32]),
     ("amber_delay_table", ctypes.c_int, [ctypes.POINTER(Geometry), c_i32p, ctypes.POINTER(DelayInfo)]),
     ("amber_dedisperse", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(DelayInfo), ctypes.c_void_p,

@@ -60,7 +60,8 @@ const amber_tiles &default_tiles()
 // The default configuration, shrunk (channel_unroll first, then
 // dms_per_block, then the time tile) until its dedispersion tile is valid for
 // this delay table.
-amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out, int in_u16, const amber_tiles *start)
+amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out, int in_u16, const amber_tiles *start,
+                        int64_t n_out)
 {
     const amber_tiles &first = start ? *start : default_tiles();
     amber_tiles t = first;
@@ -71,8 +72,7 @@ amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out, int in_u
     for (;;) {
         if (plan_dedisperse(t, info, &p, in_u16) == AMBER_OK) {
             clear_error();
-            *out = t;
-            return AMBER_OK;
+            break;
         }
         if (t.channel_unroll > min_cu) t.channel_unroll /= 2;
         else if (t.dms_per_block > 1) { t.dms_per_block /= 2; t.channel_unroll = first.channel_unroll; }
@@ -87,6 +87,47 @@ amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out, int in_u
             return fail(AMBER_E_CONFIG, "no dedispersion tile fits this delay table (max_step=%d)", info.max_step);
         }
     }
+    if (n_out > 0 && !in_u16 && !start) fill_grid(info, n_out, &t);
+    *out = t;
+    return AMBER_OK;
+}
+
+int64_t dedisperse_blocks(const amber_tiles &t, int n_dm, int64_t n_out)
+{
+    const int64_t tile_t = (int64_t)t.threads_per_dm * t.samples_per_thread;
+    const int64_t dms = (int64_t)t.dms_per_block * (t.dms_per_thread > 1 ? t.dms_per_thread : 1);
+    return (n_out + tile_t - 1) / tile_t * ((n_dm + dms - 1) / dms);
+}
+
+void fill_grid(const amber_delay_info &info, int64_t n_out, amber_tiles *t)
+{
+    // A problem whose default tiles give fewer than 1.5 work-groups per CU
+    // leaves CUs idle or unevenly loaded (the kernel is bound per CU by its
+    // LDS reads).  Smaller tiles, in the order that measured best on short
+    // beams and on the 256-channel workload: 4 samples per work-item with
+    // channel groups of 32, then one DM per wavefront.  Fewer DMs per
+    // work-group measured slower in every case (the staging is then shared
+    // by fewer trials), so the walk stops there.
+    constexpr int64_t kFillBlocks = 384;  // 1.5 x the 256 CUs
+    DedispPlan p;
+    while (dedisperse_blocks(*t, info.n_dm, n_out) < kFillBlocks) {
+        amber_tiles n = *t;
+        if (n.samples_per_thread > 4) {
+            n.samples_per_thread /= 2;
+            n.channel_unroll = 32;
+        } else if (n.dms_per_thread > 1) {
+            n.dms_per_thread = 1;
+            n.channel_unroll = 32;
+        } else {
+            break;
+        }
+        if (plan_dedisperse(n, info, &p) != AMBER_OK) {
+            n.channel_unroll = t->channel_unroll;  // the wider channel group may not fit
+            if (plan_dedisperse(n, info, &p) != AMBER_OK) break;
+        }
+        *t = n;
+    }
+    clear_error();
 }
 
 amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info, DedispPlan *out, int in_u16)
@@ -228,11 +269,11 @@ amber_status amber_default_tiles(amber_tiles *tiles)
     return AMBER_OK;
 }
 
-amber_status amber_auto_tiles(const amber_delay_info *info, amber_tiles *tiles)
+amber_status amber_auto_tiles(const amber_delay_info *info, int64_t n_out, amber_tiles *tiles)
 {
     clear_error();
     if (!tiles || !info) return fail(AMBER_E_ARG, "tiles or info is NULL");
-    return auto_tiles(*info, tiles);
+    return auto_tiles(*info, tiles, 0, nullptr, n_out);
 }
 
 amber_status amber_validate_tiles(const amber_tiles *tiles, const amber_delay_info *info, int32_t n_widths)
@@ -313,7 +354,7 @@ amber_status dedisperse_common(const int32_t *d_delays, const amber_delay_info *
     if ((int64_t)info->n_chan * 255 >= ((int64_t)1 << 31))
         return fail(AMBER_E_ARG, "n_chan=%d can overflow int32 sums", info->n_chan);
     amber_tiles chosen;
-    amber_status s = tiles ? AMBER_OK : auto_tiles(*info, &chosen);
+    amber_status s = tiles ? AMBER_OK : auto_tiles(*info, &chosen, 0, nullptr, n_out);
     if (s != AMBER_OK) return s;
     DedispPlan plan;
     s = plan_dedisperse(tiles ? *tiles : chosen, *info, &plan);

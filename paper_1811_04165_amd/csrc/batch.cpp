@@ -73,7 +73,7 @@ amber_status amber_batch_create(const amber_beam *beams, int32_t n_beams, const 
     for (int k = 0; k < n_beams; ++k) {
         const amber_beam &bm = beams[k];
         amber_tiles t;
-        amber_status s = tiles ? AMBER_OK : auto_tiles(bm.info, &t);
+        amber_status s = tiles ? AMBER_OK : auto_tiles(bm.info, &t, 0, nullptr, bm.n_out);
         if (tiles) t = tiles[k];
         DedispPlan dp;
         BoxcarPlan bp;

@@ -53,9 +53,16 @@ inline int64_t mask_lds_bytes(const DedispPlan &p) { return (int64_t)kWave * (p.
 amber_tiles subband_step_tiles(int n_dm, int n_chan, int in_u16);
 
 // The first valid tiles of a shrinking sequence that starts at `start`
-// (default: the library's defaults).
+// (default: the library's defaults); with the defaults and n_out > 0 (uint8
+// input), then made smaller by fill_grid until the grid fills the chip.
 amber_status auto_tiles(const amber_delay_info &info, amber_tiles *out, int in_u16 = 0,
-                        const amber_tiles *start = nullptr);
+                        const amber_tiles *start = nullptr, int64_t n_out = 0);
+// Work-groups of a dedispersion launch with tiles t.
+int64_t dedisperse_blocks(const amber_tiles &t, int n_dm, int64_t n_out);
+// Shrinks valid tiles (uint8 input: samples_per_thread down to 4, then one DM
+// per wavefront) until the launch has at least 384 work-groups (1.5 per CU)
+// or neither step is left; keeps them valid.
+void fill_grid(const amber_delay_info &info, int64_t n_out, amber_tiles *t);
 
 // Boxcar / S/N geometry.
 struct BoxcarPlan {

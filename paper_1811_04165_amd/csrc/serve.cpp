@@ -574,7 +574,7 @@ amber_status amber_server_add_beam(amber_server *s, const amber_stream_beam *bm,
     clear_error();
     if (bm->tiles)
         b->tiles = *bm->tiles;
-    else if ((st = auto_tiles(b->info, &b->tiles)) != AMBER_OK)
+    else if ((st = auto_tiles(b->info, &b->tiles, 0, nullptr, bm->chunk)) != AMBER_OK)
         return st;
     if ((st = plan_dedisperse(b->tiles, b->info, &b->dp)) != AMBER_OK) return st;
     if ((st = plan_boxcar(b->tiles, widths, n_widths, bm->chunk, &b->bp)) != AMBER_OK) return st;

@@ -157,3 +157,46 @@ def test_gpu_test_tiles_are_valid():
         _, info = amber.delay_table(freqs, 81.92e-6, n_dm, 1.5, step)
         for kw in t.ODD_TILES:
             amber.validate_tiles(amber.make_tiles(**{"dms_per_thread": 1, **kw}) if kw else amber.auto_tiles(info), info, 1)
+
+
+def test_auto_tiles_fills_small_grids():
+    """With a series length, the automatic tiles shrink until the dedispersion
+    launch has at least 384 work-groups (1.5 per CU) or no step is left, and
+    stay valid; large problems keep the defaults, and n_out = 0 skips it."""
+    import paper_1811_04165_amd as amber
+
+    def blocks(t, n_dm, n_out):
+        tile_t = t.threads_per_dm * t.samples_per_thread
+        dms = t.dms_per_block * max(1, t.dms_per_thread)
+        return -(-n_out // tile_t) * -(-n_dm // dms)
+
+    d = amber.default_tiles().as_dict()
+    wl = workloads.small()
+    g = wl.geom
+    _, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+    t = amber.auto_tiles(info, wl.n_out)
+    # 64 work-groups by default; 4 samples per work-item (128), one DM per wavefront (256)
+    assert (t.samples_per_thread, t.channel_unroll, t.dms_per_thread, t.dms_per_block) == (4, 32, 1, d["dms_per_block"])
+    assert blocks(t, g.n_dm, wl.n_out) == 256
+    assert amber.auto_tiles(info, 0).as_dict() == d
+    for k, v in t.as_dict().items():
+        if k not in ("samples_per_thread", "channel_unroll", "dms_per_thread"):
+            assert v == d[k], k
+    wl = workloads.beam()
+    g = wl.geom
+    _, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+    assert amber.auto_tiles(info, wl.n_out).as_dict() == d
+    # shapes from tiny to large: valid, and filled unless no step is left
+    for n_chan, n_dm, n_out in ((64, 1, 100), (256, 64, 4096), (384, 512, 4096), (768, 512, 4472),
+                                (1536, 1024, 5456), (384, 512, 13400), (1536, 2048, 100000)):
+        freqs = 1250.0 + np.arange(n_chan) * (300.0 / n_chan)
+        _, info = amber.delay_table(freqs, 81.92e-6, n_dm, 0.0, 0.5)
+        t = amber.auto_tiles(info, n_out)
+        amber.validate_tiles(t, info, 1)
+        base = amber.auto_tiles(info, 0)
+        if blocks(base, n_dm, n_out) >= 384:
+            assert t.as_dict() == base.as_dict()
+        else:
+            assert blocks(t, n_dm, n_out) >= 384 or (t.samples_per_thread == 4 and t.dms_per_thread == 1)
+    from paper_1811_04165_amd._lib import load
+    assert load().amber_auto_tiles(None, 10, None) == -1  # AMBER_E_ARG
