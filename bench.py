@@ -167,7 +167,7 @@ def serve_summary(seconds: float = 5.0, warmup_s: float = 1.0):
             "chunks_per_s": r["chunks_per_s"], "value": r["value"], "latency_ms": r["latency_ms"]}
 
 
-def tune_report(seeds: int):
+def tune_report(seeds: int, log_path=None):
     """GA (several seeds) vs exhaustive vs random (same budget as each GA run)
     vs per-kernel brute force, on the 256-channel / 128-DM workload, with the
     finalists re-timed interleaved."""
@@ -178,12 +178,13 @@ def tune_report(seeds: int):
         "threads_per_dm": sp.gene_values(G.GENE_THREADS_PER_DM),
         "samples_per_thread": sp.gene_values(G.GENE_SAMPLES_PER_THREAD),
         "dms_per_block": sp.gene_values(G.GENE_DMS_PER_BLOCK), "channel_unroll": sp.gene_values(G.GENE_CHANNEL_UNROLL),
-        "dms_per_thread": sp.gene_values(G.GENE_DMS_PER_THREAD), "snr_threads": sp.gene_values(G.GENE_SNR_THREADS),
+        "dms_per_thread": sp.gene_values(G.GENE_DMS_PER_THREAD),
+        "direct_reads": sp.gene_values(G.GENE_DIRECT_READS), "snr_threads": sp.gene_values(G.GENE_SNR_THREADS),
         "boxcar_step": sp.gene_values(G.GENE_BOXCAR0)}}
 
     def run(kind, **kw):
         print("[bench] tune %s %s" % (kind, kw), file=sys.stderr, flush=True)
-        r = amber.tune(sp, search.delays, x, n_in, amber.tune_params(kind, **kw), buffers=bufs)
+        r = amber.tune(sp, search.delays, x, n_in, amber.tune_params(kind, **kw), log_path=log_path, buffers=bufs)
         return r
 
     ga = [run("ga", seed=s) for s in range(1, seeds + 1)]
@@ -455,8 +456,9 @@ def ga_study_report(seeds: int):
     sp = amber.default_space(search.info, wl.widths, wl.n_out)
     G = amber.genes
     # the study's table covers the dedispersion genes with one DM per wavefront
-    # and the boxcar steps at 256 work-items
+    # and LDS staging, and the boxcar steps at 256 work-items
     sp.set_gene_values(G.GENE_DMS_PER_THREAD, [1])
+    sp.set_gene_values(G.GENE_DIRECT_READS, [0])
     sp.set_gene_values(G.GENE_SNR_THREADS, [256])
     nw = len(wl.widths)
     gv = [sp.gene_values(i) for i in range(sp.n_genes)]
@@ -477,7 +479,7 @@ def ga_study_report(seeds: int):
     t_dd = {}
     for tpd, spt, dpb, cu in itertools.product(*gv[:4]):
         t = amber.make_tiles(threads_per_dm=tpd, samples_per_thread=spt, dms_per_block=dpb, channel_unroll=cu,
-                             snr_threads=256)
+                             dms_per_thread=1, direct_reads=0, snr_threads=256)
         try:
             amber.validate_tiles(t, search.info, nw)
         except amber.AmberError:
@@ -884,6 +886,8 @@ def main() -> int:
                     help="instead of the throughput step: compare the GA tile search with exhaustive, random and "
                          "per-kernel brute-force search on the 256-channel workload")
     ap.add_argument("--tune-seeds", type=int, default=10)
+    ap.add_argument("--tune-log", type=str, default="",
+                    help="JSONL log of the --tune searches (a line per generation, or per 1000 evaluations)")
     ap.add_argument("--ga-study", action="store_true",
                     help="instead of the throughput step: the paper's GA studies (mutation and crossover rates, "
                          "population size, crossover type, random search) replayed on a measured fitness table")
@@ -929,7 +933,7 @@ def main() -> int:
         print("bench.py: no GPU visible", file=sys.stderr)
         return 3
     if args.tune:
-        print(json.dumps(tune_report(args.tune_seeds)))
+        print(json.dumps(tune_report(args.tune_seeds, args.tune_log or None)))
         return 0
     if args.batched:
         print(json.dumps(batched_report(args.beams, args.steps, args.warmup)))

@@ -97,10 +97,18 @@ typedef struct {
  *                      with samples_per_thread <= 16); 0 reads as 1.  A
  *                      work-group covers dms_per_block * dms_per_thread DMs,
  *                      and every staged window serves all of them
+ *   direct_reads       how the dedispersion kernel reads its input (the
+ *                      paper's localMem gene): 0 (the default) stages each
+ *                      channel's window in LDS (localMem on); 1 reads it
+ *                      straight from global memory through the caches
+ *                      (localMem off), with dms_per_thread 1 and
+ *                      (samples_per_thread / 4 + 1) * channel_unroll <= 64
+ *                      (the dwords a work-item loads per channel group).
+ *                      uint8 input only: the subband steps take 0.
  * The LDS footprint of the dedispersion tile must fit in 160 KiB and its
  * staging must need at most 4 items of 16 samples per work-item (3 when
  * samples_per_thread is 16, 2 when it is 32 or when it is 16 with two DMs per
- * wavefront). */
+ * wavefront); direct reads use no LDS. */
 typedef struct {
     int32_t threads_per_dm;
     int32_t samples_per_thread;
@@ -109,6 +117,7 @@ typedef struct {
     int32_t snr_threads;
     int32_t boxcar_step[AMBER_MAX_WIDTHS];
     int32_t dms_per_thread;
+    int32_t direct_reads;
 } amber_tiles;
 
 /* Fill `tiles` with the library's default configuration. */
@@ -330,10 +339,10 @@ amber_status amber_downsample_snr(const int32_t *d_dd, int32_t n_dm, int64_t dd_
 /* ---- tile search (Section 3: genetic algorithm; Section 2: brute force) ---- */
 
 /* Genes: 0 threads_per_dm, 1 samples_per_thread, 2 dms_per_block,
- * 3 channel_unroll, 4 dms_per_thread (the dedispersion kernel's genes),
- * 5 snr_threads, 6 + k boxcar_step[k] for k < n_widths (the boxcar / S/N
- * kernel's genes). */
-#define AMBER_GENES_K1 5
+ * 3 channel_unroll, 4 dms_per_thread, 5 direct_reads (the dedispersion
+ * kernel's genes), 6 snr_threads, 7 + k boxcar_step[k] for k < n_widths (the
+ * boxcar / S/N kernel's genes). */
+#define AMBER_GENES_K1 6
 #define AMBER_MAX_GENES (AMBER_GENES_K1 + 1 + AMBER_MAX_WIDTHS)
 #define AMBER_MAX_GENE_VALUES 8
 

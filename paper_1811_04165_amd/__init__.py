@@ -57,12 +57,13 @@ def default_tiles() -> Tiles:
 
 
 def make_tiles(threads_per_dm=None, samples_per_thread=None, dms_per_block=None, channel_unroll=None,
-               snr_threads=None, boxcar_step=None, dms_per_thread=None) -> Tiles:
+               snr_threads=None, boxcar_step=None, dms_per_thread=None, direct_reads=None) -> Tiles:
     """Default tiles with the given fields replaced; boxcar_step is an int or a per-width list."""
     t = default_tiles()
     for name, v in (("threads_per_dm", threads_per_dm), ("samples_per_thread", samples_per_thread),
                     ("dms_per_block", dms_per_block), ("channel_unroll", channel_unroll),
-                    ("snr_threads", snr_threads), ("dms_per_thread", dms_per_thread)):
+                    ("snr_threads", snr_threads), ("dms_per_thread", dms_per_thread),
+                    ("direct_reads", direct_reads)):
         if v is not None:
             setattr(t, name, int(v))
     if boxcar_step is not None:

@@ -46,13 +46,13 @@ class Tiles(ctypes.Structure):
     _fields_ = [("threads_per_dm", ctypes.c_int32), ("samples_per_thread", ctypes.c_int32),
                 ("dms_per_block", ctypes.c_int32), ("channel_unroll", ctypes.c_int32),
                 ("snr_threads", ctypes.c_int32), ("boxcar_step", ctypes.c_int32 * AMBER_MAX_WIDTHS),
-                ("dms_per_thread", ctypes.c_int32)]
+                ("dms_per_thread", ctypes.c_int32), ("direct_reads", ctypes.c_int32)]
 
     def as_dict(self):
         return {"threads_per_dm": self.threads_per_dm, "samples_per_thread": self.samples_per_thread,
                 "dms_per_block": self.dms_per_block, "channel_unroll": self.channel_unroll,
                 "snr_threads": self.snr_threads, "boxcar_step": list(self.boxcar_step),
-                "dms_per_thread": self.dms_per_thread}
+                "dms_per_thread": self.dms_per_thread, "direct_reads": self.direct_reads}
 
     def __repr__(self):
         d = self.as_dict()
@@ -62,8 +62,9 @@ class Tiles(ctypes.Structure):
 
 # gene indices of a tune space (include/amber.h): the dedispersion kernel's
 # genes, then the boxcar / S/N kernel's
-GENE_THREADS_PER_DM, GENE_SAMPLES_PER_THREAD, GENE_DMS_PER_BLOCK, GENE_CHANNEL_UNROLL, GENE_DMS_PER_THREAD = range(5)
-AMBER_GENES_K1 = 5
+(GENE_THREADS_PER_DM, GENE_SAMPLES_PER_THREAD, GENE_DMS_PER_BLOCK, GENE_CHANNEL_UNROLL, GENE_DMS_PER_THREAD,
+ GENE_DIRECT_READS) = range(6)
+AMBER_GENES_K1 = 6
 GENE_SNR_THREADS = AMBER_GENES_K1
 GENE_BOXCAR0 = AMBER_GENES_K1 + 1
 AMBER_MAX_GENES = AMBER_GENES_K1 + 1 + AMBER_MAX_WIDTHS

@@ -160,6 +160,18 @@ amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info,
     p.in_u16 = in_u16 ? 1 : 0;
     p.threads = p.tpd * p.dpb;
     p.tile_t = p.tpd * p.spt;
+    if (t.direct_reads != 0 && t.direct_reads != 1)
+        return fail(AMBER_E_CONFIG, "direct_reads=%d must be 0 or 1", t.direct_reads);
+    if (t.direct_reads) {
+        if (in_u16) return fail(AMBER_E_CONFIG, "direct reads take uint8 input");
+        if (p.dpt != 1) return fail(AMBER_E_CONFIG, "direct reads take dms_per_thread=1");
+        if ((p.spt / 4 + 1) * p.cu > 64)
+            return fail(AMBER_E_CONFIG, "direct reads load (samples_per_thread/4 + 1) * channel_unroll = %d dwords "
+                        "per channel group (max 64)", (p.spt / 4 + 1) * p.cu);
+        p.direct = 1;
+        *out = p;
+        return AMBER_OK;
+    }
     // Offsets a DM of the tile reads at, relative to the first DM's window
     // start (which is rounded down to a dword: 4 uint8 or 2 uint16 samples):
     // [0, omax].
@@ -360,6 +372,13 @@ amber_status dedisperse_common(const int32_t *d_delays, const amber_delay_info *
     s = plan_dedisperse(tiles ? *tiles : chosen, *info, &plan);
     if (s != AMBER_OK) return s;
     if (n_out == 0) return AMBER_OK;
+    if (plan.direct) {
+        DedispJob j = make_dedisp_job(plan, d_delays, info->n_dm, info->n_chan, d_in, in_stride, d_dd, dd_stride,
+                                      n_out);
+        j.keep = d_keep;
+        return launch_dedisperse_direct_jobs(plan, &j, nullptr, 1, (int64_t)j.tiles_t * j.tiles_dm,
+                                             (hipStream_t)stream);
+    }
     return launch_dedisperse(plan, d_delays, info->n_dm, info->n_chan, d_in, in_stride, n_in, d_dd, dd_stride, n_out,
                              (hipStream_t)stream, d_keep);
 }

@@ -41,6 +41,8 @@ struct DedispPlan {
     int maxi;           // staging items per work-item (prefetched in registers)
     int omax;           // largest sample offset a DM may read at inside the window
     int in_u16;         // input samples are uint16 (subband step two)
+    int direct;         // reads the input from global memory, no LDS staging
+                        // (win, omax and maxi are then unused)
     int64_t lds_bytes;  // dynamic LDS per work-group
 };
 
@@ -159,6 +161,10 @@ private:
 };
 
 // Launchers (device translation units).
+// Direct-read dedispersion (plans with direct set): one job or a job table,
+// uint8 input, int32 sums, one problem per job (groups 1).
+amber_status launch_dedisperse_direct_jobs(const DedispPlan &p, const DedispJob *single, const DedispJob *d_jobs,
+                                           int n_jobs, int64_t n_blocks, hipStream_t stream);
 amber_status launch_dedisperse(const DedispPlan &p, const int32_t *d_delays, int n_dm, int n_chan,
                                const uint8_t *d_in, int64_t in_stride, int64_t n_in, int32_t *d_dd,
                                int64_t dd_stride, int64_t n_out, hipStream_t stream, const uint8_t *d_keep = nullptr);

@@ -10,7 +10,7 @@ void LaunchSet::add_dedisperse(const DedispPlan &p, DedispJob j)
 {
     auto it = std::find_if(d_.begin(), d_.end(), [&](const DGroup &g) {
         return g.plan.tpd == p.tpd && g.plan.spt == p.spt && g.plan.dpb == p.dpb && g.plan.cu == p.cu &&
-               g.plan.in_u16 == p.in_u16 && g.plan.dpt == p.dpt;
+               g.plan.in_u16 == p.in_u16 && g.plan.dpt == p.dpt && g.plan.direct == p.direct;
     });
     if (it == d_.end()) {
         d_.emplace_back();
@@ -73,8 +73,11 @@ amber_status LaunchSet::launch(const void *d_tables, hipStream_t stream) const
 {
     const char *p = static_cast<const char *>(d_tables);
     for (const auto &g : d_) {
-        amber_status s = launch_dedisperse_jobs(g.plan, nullptr, reinterpret_cast<const DedispJob *>(p),
-                                                (int)g.jobs.size(), g.n_blocks, g.lds, stream);
+        const DedispJob *tab = reinterpret_cast<const DedispJob *>(p);
+        amber_status s = g.plan.direct
+                             ? launch_dedisperse_direct_jobs(g.plan, nullptr, tab, (int)g.jobs.size(), g.n_blocks, stream)
+                             : launch_dedisperse_jobs(g.plan, nullptr, tab, (int)g.jobs.size(), g.n_blocks, g.lds,
+                                                      stream);
         if (s != AMBER_OK) return s;
         p += g.jobs.size() * sizeof(DedispJob);
     }

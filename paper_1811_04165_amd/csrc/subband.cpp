@@ -51,6 +51,7 @@ amber_status plan_step(const amber_tiles *given, const amber_delay_info &info, i
     amber_tiles t;
     if (given) {
         t = *given;
+        if (t.direct_reads) return fail(AMBER_E_CONFIG, "the subband steps stage their input in LDS (direct_reads 0)");
     } else {
         const amber_tiles start = subband_step_tiles(info.n_dm, info.n_chan, in_u16);
         amber_status s = auto_tiles(info, &t, in_u16, &start);

@@ -23,6 +23,7 @@ constexpr double kInf = std::numeric_limits<double>::infinity();
 // genes [0, kGroupSplit): dedispersion; [kGroupSplit, n): boxcar / S/N
 constexpr int kGroupSplit = AMBER_GENES_K1;
 constexpr int kGeneDpt = 4;                    // dms_per_thread
+constexpr int kGeneDirect = 5;                 // direct_reads
 constexpr int kGeneSnr = AMBER_GENES_K1;       // snr_threads
 constexpr int kGeneBox0 = AMBER_GENES_K1 + 1;  // boxcar_step[0]
 
@@ -70,6 +71,7 @@ amber_tiles to_tiles(const amber_tune_space &sp, const Genome &g)
     t.dms_per_block = sp.values[2][g[2]];
     t.channel_unroll = sp.values[3][g[3]];
     t.dms_per_thread = sp.values[kGeneDpt][g[kGeneDpt]];
+    t.direct_reads = sp.values[kGeneDirect][g[kGeneDirect]];
     t.snr_threads = sp.values[kGeneSnr][g[kGeneSnr]];
     for (int k = 0; k < sp.n_widths; ++k) t.boxcar_step[k] = sp.values[kGeneBox0 + k][g[kGeneBox0 + k]];
     return t;
@@ -97,9 +99,9 @@ std::string tiles_json(const amber_tiles &t, int n_widths)
     char buf[512];
     int n = snprintf(buf, sizeof buf,
                      "{\"threads_per_dm\":%d,\"samples_per_thread\":%d,\"dms_per_block\":%d,\"channel_unroll\":%d,"
-                     "\"dms_per_thread\":%d,\"snr_threads\":%d,\"boxcar_step\":[",
+                     "\"dms_per_thread\":%d,\"direct_reads\":%d,\"snr_threads\":%d,\"boxcar_step\":[",
                      t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll, t.dms_per_thread,
-                     t.snr_threads);
+                     t.direct_reads, t.snr_threads);
     for (int k = 0; k < n_widths; ++k) n += snprintf(buf + n, sizeof buf - n, "%s%d", k ? "," : "", t.boxcar_step[k]);
     snprintf(buf + n, sizeof buf - n, "]}");
     return buf;
@@ -461,7 +463,7 @@ public:
     {
         const amber_tiles &d = default_tiles();
         const int k1[] = {d.threads_per_dm, d.samples_per_thread, d.dms_per_block, d.channel_unroll,
-                          d.dms_per_thread, d.snr_threads};
+                          d.dms_per_thread, d.direct_reads, d.snr_threads};
         return i < kGeneBox0 ? k1[i] : d.boxcar_step[i - kGeneBox0];
     }
 
@@ -772,6 +774,7 @@ amber_status amber_default_space(const amber_delay_info *info, const int32_t *wi
         {1, 2, 4, 8, 16},           // dms_per_block
         {1, 2, 4, 8, 16, 32},       // channel_unroll
         {1, 2},                     // dms_per_thread
+        {0, 1},                     // direct_reads (localMem on, off)
         {64, 128, 256, 512, 1024},  // snr_threads
     };
     sp->n_genes = kGeneBox0 + n_widths;
@@ -803,6 +806,7 @@ amber_status amber_space_size(const amber_tune_space *sp, int64_t *count)
         t.dms_per_block = sp->values[2][g[2]];
         t.channel_unroll = sp->values[3][g[3]];
         t.dms_per_thread = sp->values[kGeneDpt][g[kGeneDpt]];
+        t.direct_reads = sp->values[kGeneDirect][g[kGeneDirect]];
         DedispPlan dp;
         if (plan_dedisperse(t, sp->info, &dp) == AMBER_OK) ++n1;
         int i = 0;

@@ -84,11 +84,20 @@ def test_tile_validation():
            dict(channel_unroll=3), dict(channel_unroll=64), dict(snr_threads=48), dict(boxcar_step=3),
            dict(threads_per_dm=1024, samples_per_thread=16, channel_unroll=16),
            dict(dms_per_thread=3), dict(dms_per_thread=2, samples_per_thread=32, dms_per_block=4),
-           dict(dms_per_thread=-1)]
+           dict(dms_per_thread=-1),
+           # direct reads: 0 or 1, one DM per wavefront, at most 64 dwords loaded per channel group
+           dict(direct_reads=2), dict(direct_reads=-1), dict(direct_reads=1, dms_per_thread=2),
+           dict(direct_reads=1, dms_per_thread=1, samples_per_thread=32, channel_unroll=8),
+           dict(direct_reads=1, dms_per_thread=1, samples_per_thread=8, channel_unroll=32)]
     for kw in bad:
         with pytest.raises(amber.AmberError) as e:
             amber.validate_tiles(amber.make_tiles(**kw), info, 7)
         assert e.value.status == -3, kw
+    # direct reads use no LDS: tiles whose staging would not fit are valid
+    for kw in (dict(samples_per_thread=4, channel_unroll=32), dict(samples_per_thread=8, channel_unroll=16),
+               dict(samples_per_thread=32, channel_unroll=4), dict(samples_per_thread=4, channel_unroll=32, dms_per_block=1),
+               dict(threads_per_dm=1024, samples_per_thread=16, channel_unroll=8, dms_per_block=1)):
+        amber.validate_tiles(amber.make_tiles(direct_reads=1, dms_per_thread=1, **kw), info, 7)
 
 
 def test_device_calls_validate_before_launch():

@@ -87,12 +87,19 @@ TILE_SWEEP = [
     dict(threads_per_dm=64, samples_per_thread=4, dms_per_block=3, channel_unroll=16, dms_per_thread=2),
     dict(threads_per_dm=128, samples_per_thread=16, dms_per_block=4, channel_unroll=4, dms_per_thread=2),
     dict(threads_per_dm=256, samples_per_thread=8, dms_per_block=1, channel_unroll=4, dms_per_thread=2),
+    # direct reads from global memory (no LDS staging); every samples_per_thread, partial last blocks
+    dict(threads_per_dm=64, samples_per_thread=4, dms_per_block=1, channel_unroll=32, direct_reads=1),
+    dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=3, channel_unroll=16, direct_reads=1),
+    dict(threads_per_dm=128, samples_per_thread=16, dms_per_block=5, channel_unroll=4, direct_reads=1),
+    dict(threads_per_dm=256, samples_per_thread=32, dms_per_block=2, channel_unroll=1, direct_reads=1),
+    dict(threads_per_dm=1024, samples_per_thread=8, dms_per_block=1, channel_unroll=8, direct_reads=1),
 ]
 
 
 def _tile_id(k):
     return ("tpd%(threads_per_dm)d-spt%(samples_per_thread)d-dpb%(dms_per_block)d-cu%(channel_unroll)d" % k +
-            ("-dpt%d" % k["dms_per_thread"] if k.get("dms_per_thread", 1) != 1 else ""))
+            ("-dpt%d" % k["dms_per_thread"] if k.get("dms_per_thread", 1) != 1 else "") +
+            ("-direct" if k.get("direct_reads") else ""))
 
 
 @pytest.mark.parametrize("kw", TILE_SWEEP, ids=_tile_id)
@@ -115,7 +122,9 @@ ODD = [
 
 ODD_TILES = [None, dict(threads_per_dm=64, samples_per_thread=4, dms_per_block=3, channel_unroll=16),
              dict(threads_per_dm=128, samples_per_thread=16, dms_per_block=4, channel_unroll=8),
-             dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=3, channel_unroll=8, dms_per_thread=2)]
+             dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=3, channel_unroll=8, dms_per_thread=2),
+             dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=3, channel_unroll=16, direct_reads=1),
+             dict(threads_per_dm=128, samples_per_thread=4, dms_per_block=2, channel_unroll=32, direct_reads=1)]
 
 
 def odd_freqs(n_chan, n_dm):
@@ -374,11 +383,13 @@ def test_batched_beams_match_single_beams(amber, torch):
                           dd=torch.full((g.n_dm, wl.n_out + 3), -1, dtype=torch.int32, device="cuda"),
                           n_out=wl.n_out, snr=torch.zeros((len(widths), g.n_dm), dtype=torch.float32, device="cuda"),
                           peak=torch.zeros((len(widths), g.n_dm), dtype=torch.int32, device="cuda")))
-    # two tile classes so the batch needs more than one launch per kernel
+    # three tile classes (one reading its input directly from global memory)
+    # so the batch needs more than one launch per kernel
     tiles = [amber.make_tiles(samples_per_thread=8 if k % 2 else 16, channel_unroll=16) for k in range(len(beams))]
+    tiles[0] = amber.make_tiles(samples_per_thread=8, channel_unroll=16, dms_per_thread=1, direct_reads=1)
     say("batch of %d uneven beams, eager" % len(beams))
     batch = amber.Batch(beams, widths, tiles=tiles)
-    assert batch.launches() == (2, 1)
+    assert batch.launches() == (3, 1)
     batch.run()
     torch.cuda.synchronize()
     for b, (ref_dd, ref_s, ref_p) in zip(beams, refs):

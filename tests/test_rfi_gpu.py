@@ -38,12 +38,16 @@ RFI_TILES = [None,
              dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=16, channel_unroll=32),
              dict(threads_per_dm=128, samples_per_thread=4, dms_per_block=4, channel_unroll=8),
              dict(threads_per_dm=64, samples_per_thread=16, dms_per_block=3, channel_unroll=1),
-             dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=5, channel_unroll=16, dms_per_thread=2)]
+             dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=5, channel_unroll=16, dms_per_thread=2),
+             # direct reads: zapped channels get the all-zero selector
+             dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=3, channel_unroll=16, direct_reads=1),
+             dict(threads_per_dm=128, samples_per_thread=4, dms_per_block=2, channel_unroll=32, direct_reads=1)]
 
 
 @pytest.mark.parametrize("kw", RFI_TILES, ids=lambda k: "auto" if k is None else
                          "tpd%(threads_per_dm)d-spt%(samples_per_thread)d-dpb%(dms_per_block)d-cu%(channel_unroll)d" % k
-                         + ("-dpt%d" % k["dms_per_thread"] if "dms_per_thread" in k else ""))
+                         + ("-dpt%d" % k["dms_per_thread"] if "dms_per_thread" in k else "")
+                         + ("-direct" if k.get("direct_reads") else ""))
 def test_masked_small(amber, torch, kw):
     wl = workloads.small()
     g = wl.geom

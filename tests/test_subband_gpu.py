@@ -108,6 +108,18 @@ def test_subband_step_one_rows(amber, torch):
         assert np.array_equal(w[s], ref), s
 
 
+def test_subband_refuses_direct_reads(amber, torch):
+    """The subband steps stage their input in LDS: tiles asking for direct
+    reads are refused on the host, before any launch."""
+    n_out = 500
+    d1, d2, info, o1, o2, x, n_in = _setup(amber, SMALL, SMALL_GRID, n_out, seed=64)
+    t = amber.make_tiles(dms_per_thread=1, direct_reads=1)
+    for kw in (dict(tiles1=t), dict(tiles2=t)):
+        with pytest.raises(amber.AmberError) as e:
+            _run(amber, torch, d1, d2, info, x, n_in, n_out, **kw)
+        assert e.value.status == -3
+
+
 def test_subband_one_subband_is_coarse_brute_force(amber, torch):
     n_out = 1500
     grid = (1, 6, 0.0, 16.0, 4, 0.0, 4.0)       # every fine trial of coarse DM j: brute force at 16 j

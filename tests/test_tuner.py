@@ -37,15 +37,16 @@ def _small_space(amber, reduced=True):
         sp.set_gene_values(2, [1, 4, 16])
         sp.set_gene_values(3, [2, 8, 32])
         sp.set_gene_values(4, [1, 2])
-        sp.set_gene_values(5, [64, 256])
-        sp.set_gene_values(6, [1, 8])
-        sp.set_gene_values(7, [2, 4])
+        sp.set_gene_values(5, [0, 1])
+        sp.set_gene_values(6, [64, 256])
+        sp.set_gene_values(7, [1, 8])
+        sp.set_gene_values(8, [2, 4])
     return sp, info, widths
 
 
 def _tiles_key(t, n_w):
     return (t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll, t.dms_per_thread,
-            t.snr_threads) + tuple(t.boxcar_step[k] for k in range(n_w))
+            t.direct_reads, t.snr_threads) + tuple(t.boxcar_step[k] for k in range(n_w))
 
 
 def _all_valid(amber, sp, widths):
@@ -53,8 +54,8 @@ def _all_valid(amber, sp, widths):
     genes = [sp.gene_values(i) for i in range(sp.n_genes)]
     for combo in itertools.product(*genes):
         t = amber.make_tiles(threads_per_dm=combo[0], samples_per_thread=combo[1], dms_per_block=combo[2],
-                             channel_unroll=combo[3], dms_per_thread=combo[4], snr_threads=combo[5],
-                             boxcar_step=list(combo[6:]))
+                             channel_unroll=combo[3], dms_per_thread=combo[4], direct_reads=combo[5],
+                             snr_threads=combo[6], boxcar_step=list(combo[7:]))
         try:
             amber.validate_tiles(t, sp.info, len(widths))
         except amber.AmberError:
@@ -65,10 +66,10 @@ def _all_valid(amber, sp, widths):
 
 def test_default_space_and_size(amber):
     sp, info, widths = _small_space(amber, reduced=False)
-    assert sp.n_genes == 6 + len(widths)
-    assert sp.gene_values(1) == [4, 8, 16, 32] and sp.gene_values(4) == [1, 2]
+    assert sp.n_genes == 7 + len(widths)
+    assert sp.gene_values(1) == [4, 8, 16, 32] and sp.gene_values(4) == [1, 2] and sp.gene_values(5) == [0, 1]
     n = amber.space_size(sp)
-    assert 0 < n <= 5 * 4 * 5 * 6 * 2 * 5 * 16
+    assert 0 < n <= 5 * 4 * 5 * 6 * 2 * 2 * 5 * 16
     spr, _, _ = _small_space(amber)
     assert amber.space_size(spr) == len(_all_valid(amber, spr, widths))
 
@@ -97,15 +98,16 @@ def test_exhaustive_returns_argmin(amber):
 
 def _smooth(target, n_w):
     def fit(t):
+        # direct_reads (0 or 1) enters as 1 + value so that its log is defined
         vals = [t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll, t.dms_per_thread,
-                t.snr_threads] + [t.boxcar_step[k] for k in range(n_w)]
+                1 + t.direct_reads, t.snr_threads] + [t.boxcar_step[k] for k in range(n_w)]
         return 1e-4 * (1.0 + sum((math.log2(v) - math.log2(g)) ** 2 for v, g in zip(vals, target)))
     return fit
 
 
 def test_ga_valid_offspring_deterministic_and_converging(amber, tmp_path):
     sp, info, widths = _small_space(amber, reduced=False)
-    target = (64, 8, 16, 16, 2, 256, 4, 2)
+    target = (64, 8, 16, 16, 2, 1, 256, 4, 2)
     smooth = _smooth(target, len(widths))
 
     def fit(t):
@@ -119,8 +121,8 @@ def test_ga_valid_offspring_deterministic_and_converging(amber, tmp_path):
     assert r1.n_evals <= 32 * 41
     # the smooth landscape's optimum (valid by construction) is found or nearly
     assert r1.best_time_s <= smooth(amber.make_tiles(threads_per_dm=64, samples_per_thread=8, dms_per_block=16,
-                                                     channel_unroll=16, dms_per_thread=2, snr_threads=256,
-                                                     boxcar_step=[4, 2])) * 3.0
+                                                     channel_unroll=16, dms_per_thread=2, direct_reads=0,
+                                                     snr_threads=256, boxcar_step=[4, 2])) * 3.0
     lines = [json.loads(l) for l in log.read_text().splitlines()]
     final = lines.pop()
     assert [l["generation"] for l in lines] == list(range(41))
@@ -128,8 +130,8 @@ def test_ga_valid_offspring_deterministic_and_converging(amber, tmp_path):
     assert len(final["final_population"]) == len(final["fitness"]) == 32
     for genes, f in zip(final["final_population"], final["fitness"]):
         t = amber.make_tiles(threads_per_dm=genes[0], samples_per_thread=genes[1], dms_per_block=genes[2],
-                             channel_unroll=genes[3], dms_per_thread=genes[4], snr_threads=genes[5],
-                             boxcar_step=genes[6:])
+                             channel_unroll=genes[3], dms_per_thread=genes[4], direct_reads=genes[5],
+                             snr_threads=genes[6], boxcar_step=genes[7:])
         amber.validate_tiles(t, sp.info, len(widths))
         assert f == pytest.approx(smooth(t), rel=1e-6)
     assert min(final["fitness"]) == pytest.approx(r1.best_time_s, rel=1e-6)
