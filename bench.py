@@ -526,6 +526,9 @@ def ga_study_replay(sp, wl, t_dd, t_box, seeds: int):
     bf, _ = run("per_kernel")
     t_bf, budget = bf.best_time_s, bf.n_evals
     checkpoints = [c for c in (50, 100, 200, 400, 800) if c < budget] + [budget]
+    G = amber.genes
+    cols = [G.GENE_THREADS_PER_DM, G.GENE_SAMPLES_PER_THREAD, G.GENE_DMS_PER_BLOCK, G.GENE_CHANNEL_UNROLL] + \
+        [G.GENE_BOXCAR0 + k for k in range(nw)]
     genes = ["threads_per_dm", "samples_per_thread", "dms_per_block", "channel_unroll"] + \
         ["boxcar_step_w%d" % w for w in wl.widths]
     base = dict(pop=20, p_cross=0.8, p_mut=0.1, crossover=0)
@@ -553,7 +556,8 @@ def ga_study_replay(sp, wl, t_dd, t_box, seeds: int):
                 gens = max(1, budget // p["pop"] - 1)
                 r, hist = run("ga", log=log, seed=seed, generations=gens, **p)
                 lines = [json.loads(l) for l in open(log)]
-                end = np.array(lines[-1]["final_population"], dtype=np.float64)
+                # the final population lists every gene's value: keep the studied ones, in the order of `genes`
+                end = np.array(lines[-1]["final_population"], dtype=np.float64)[:, cols]
             else:
                 r, hist = run("random", seed=1000 + seed, max_evals=budget)
                 top = sorted({c: v for v, c in hist}.items(), key=lambda kv: kv[1])[:p["pop"]]
@@ -920,7 +924,7 @@ def main() -> int:
                          "hardware byte counters read under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (the hot path is measured at N=1); "
+        print("bench.py: the library runs on exactly one GPU (the hot path is measured at N=1); "
               "got --gpus %d" % args.gpus, file=sys.stderr)
         return 2
 

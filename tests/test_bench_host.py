@@ -1,0 +1,66 @@
+"""Host-side parts of bench.py: the one-GPU guard and the GA-study replay
+against a synthetic fitness table (no GPU)."""
+import itertools
+import math
+import os
+import subprocess
+import sys
+
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_ga_study_replay_on_a_synthetic_table():
+    """Every setting runs, the per-kernel brute force finds the table optimum,
+    and the end-population statistics are finite and keyed by the studied
+    genes: genes the study holds fixed (one value) must not shift or pollute
+    the columns."""
+    import bench
+    import paper_1811_04165_amd as amber
+    wl = workloads.small()
+    g = wl.geom
+    _, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+    sp = amber.default_space(info, wl.widths, wl.n_out)
+    G = amber.genes
+    sp.set_gene_values(G.GENE_THREADS_PER_DM, [64, 256])
+    sp.set_gene_values(G.GENE_SAMPLES_PER_THREAD, [4, 8])
+    sp.set_gene_values(G.GENE_DMS_PER_BLOCK, [1, 4])
+    sp.set_gene_values(G.GENE_CHANNEL_UNROLL, [2, 8])
+    sp.set_gene_values(G.GENE_DMS_PER_THREAD, [1])
+    sp.set_gene_values(G.GENE_DIRECT_READS, [0])
+    sp.set_gene_values(G.GENE_SNR_THREADS, [256])
+    for k in range(len(wl.widths)):
+        sp.set_gene_values(G.GENE_BOXCAR0 + k, [1, 4])
+    # fitness: a smooth bowl in log2 of every studied gene, separable by kernel
+    t_dd = {}
+    for tpd, spt, dpb, cu in itertools.product([64, 256], [4, 8], [1, 4], [2, 8]):
+        t = amber.make_tiles(threads_per_dm=tpd, samples_per_thread=spt, dms_per_block=dpb, channel_unroll=cu,
+                             dms_per_thread=1, direct_reads=0, snr_threads=256)
+        try:
+            amber.validate_tiles(t, info, len(wl.widths))
+        except amber.AmberError:
+            continue
+        t_dd[(tpd, spt, dpb, cu)] = 1e-5 * (1 + math.log2(tpd / 64) + abs(math.log2(spt / 8)) + math.log2(dpb)
+                                            + abs(math.log2(cu / 8)))
+    t_box = {steps: 1e-5 * (1 + sum(math.log2(s) for s in steps))
+             for steps in itertools.product([1, 4], repeat=len(wl.widths))}
+    out = bench.ga_study_replay(sp, wl, t_dd, t_box, seeds=2)["ga_study"]
+    assert out["brute_force_per_kernel"]["over_optimum"] == pytest.approx(1.0)
+    names = ["threads_per_dm", "samples_per_thread", "dms_per_block", "channel_unroll"] + \
+        ["boxcar_step_w%d" % w for w in wl.widths]
+    assert len(out["settings"]) == 11
+    for st in out["settings"]:
+        assert list(st["cv_end_population"]) == names, st["name"]
+        assert all(math.isfinite(v) and v >= 0 for v in st["cv_end_population"].values()), st["name"]
+        assert st["best_over_bf"]["median"] >= 1.0 - 1e-9
+        assert set(st["best_gene_histograms"]) == set(names)
