@@ -166,7 +166,8 @@ amber_status amber_delay_table(const amber_geometry *g, int32_t *delays, amber_d
  * d_in:      device uint8 [n_chan][in_stride]; in_stride >= n_in and a
  *            multiple of 4; n_in >= n_out + info->max_delay.
  * d_dd:      device int32 [n_dm][dd_stride]; dd_stride >= n_out.  Columns
- *            >= n_out are not written.
+ *            >= n_out are not written.  n_out = 0 is valid: the arguments
+ *            are checked, nothing is launched, and d_dd may be NULL.
  * tiles:     NULL = amber_auto_tiles(info, n_out).
  * Reads stay inside the n_chan * in_stride input bytes and the LDS tile even
  * if the table does not match info; results are then meaningless but the call

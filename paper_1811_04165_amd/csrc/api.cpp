@@ -351,7 +351,7 @@ amber_status dedisperse_common(const int32_t *d_delays, const amber_delay_info *
                                int64_t in_stride, int64_t n_in, int32_t *d_dd, int64_t dd_stride, int64_t n_out,
                                const uint8_t *d_keep, const amber_tiles *tiles, void *stream)
 {
-    if (!d_delays || !info || !d_in || !d_dd) return fail(AMBER_E_ARG, "NULL pointer argument");
+    if (!d_delays || !info || !d_in || (!d_dd && n_out > 0)) return fail(AMBER_E_ARG, "NULL pointer argument");
     if (info->n_dm < 1 || info->n_chan < 1) return fail(AMBER_E_ARG, "info has n_dm=%d n_chan=%d", info->n_dm, info->n_chan);
     if (n_out < 0 || n_in < 0) return fail(AMBER_E_ARG, "n_out and n_in must be >= 0");
     if (n_out > (int64_t)1 << 30) return fail(AMBER_E_ARG, "n_out=%lld exceeds 2^30", (long long)n_out);

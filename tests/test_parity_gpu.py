@@ -152,6 +152,22 @@ def test_dedisperse_odd_shapes(amber, torch, case):
         assert np.array_equal(out.cpu().numpy(), ref), kw
 
 
+def test_empty_series(amber, torch, small_case):
+    """n_out = 0: dedispersion launches nothing and returns an empty table; a
+    boxcar or S/N of an empty series is refused (no width fits)."""
+    wl, d, mx, x, n_in, dd = small_case
+    say("empty series")
+    got, _, _ = _device_dedisperse(amber, torch, wl, x, n_in, 0)
+    assert got.shape == (wl.geom.n_dm, 0)
+    for tiles in (None, amber.make_tiles(dms_per_thread=1, direct_reads=1)):
+        got, _, _ = _device_dedisperse(amber, torch, wl, x, n_in, 0, tiles=tiles)
+        assert got.shape == (wl.geom.n_dm, 0)
+    ddd = torch.from_numpy(dd).cuda()
+    with pytest.raises(amber.AmberError) as e:
+        amber.integrate_snr(ddd, 0, (1, 2))
+    assert e.value.status == -1
+
+
 def test_dedisperse_saturated_many_channels(amber, torch):
     """All-255 input over 1536 channels: every sum is 391680, exercising the
     16-bit packed accumulators' flush at its limit."""
@@ -260,6 +276,7 @@ BOX_EDGE = [
     (9, 1000, (3, 7, 100, 1000)),
     (4, 20000, tuple(range(1, 17))),
     (70, 4099, (1, 2, 4, 8, 16, 32, 64)),
+    (4, 5000, (1, 512, 1024)),           # the largest sliding width, sums near the int32 limit
 ]
 
 
@@ -267,7 +284,10 @@ BOX_EDGE = [
 def test_integrate_snr_edge_shapes(amber, torch, case):
     n_dm, n_out, widths = case
     rng = np.random.default_rng(n_out)
-    dd = rng.integers(0, 391680, size=(n_dm, n_out)).astype(np.int32)
+    # values up to the largest 1536-channel sum, or (largest widths) up to
+    # 2e6, so that width-1024 sums reach 2.05e9 < 2^31
+    hi = 2_000_000 if max(widths) >= 512 else 391680
+    dd = rng.integers(0, hi, size=(n_dm, n_out)).astype(np.int32)
     dd[0] = 12345                        # constant row: sigma = 0 -> snr 0, peak 0
     if n_out > 10:
         dd[1, 3] = dd[1, 9] = 400000     # tie: the first maximum wins
