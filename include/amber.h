@@ -351,7 +351,7 @@ amber_status amber_downsample_snr(const int32_t *d_dd, int32_t n_dm, int64_t dd_
  * boundary conditions, as the paper's GA does before initialisation) and the
  * problem a configuration must be valid for. */
 typedef struct {
-    int32_t n_genes;                                   /* 6 + n_widths */
+    int32_t n_genes;                                   /* AMBER_GENES_K1 + 1 + n_widths */
     int32_t n_values[AMBER_MAX_GENES];
     int32_t values[AMBER_MAX_GENES][AMBER_MAX_GENE_VALUES];
     amber_delay_info info;                             /* validity of dedispersion tiles */
@@ -395,8 +395,11 @@ typedef struct {
  * return marks a failed evaluation (fitness +inf, never selected). */
 typedef int32_t (*amber_fitness_fn)(const amber_tiles *tiles, void *user, double *seconds);
 
-/* The default search space for a problem (gene arrays of powers of two within
- * the kernels' bounds). */
+/* The default search space for a problem: threads_per_dm {64 .. 1024},
+ * samples_per_thread {4 .. 32}, dms_per_block {1 .. 16}, channel_unroll
+ * {1 .. 32} (powers of two), dms_per_thread {1, 2}, direct_reads {0, 1},
+ * snr_threads {64 .. 1024}, boxcar_step {1, 2, 4, 8} per width.  Invalid
+ * combinations stay in the arrays; the searches skip them. */
 amber_status amber_default_space(const amber_delay_info *info, const int32_t *widths, int32_t n_widths,
                                  int64_t n_out, amber_tune_space *space);
 
