@@ -380,6 +380,10 @@ typedef struct {
     int32_t reps;         /* device evaluator: timed runs (median) */
     double eval_timeout_s;/* slower evaluations count as failures (fitness +inf) */
     int64_t max_evals;    /* random search budget; cap for exhaustive (0 = none) */
+    int32_t seed_default; /* GA: 1 = the first individual of the initial population
+                             is the library's default configuration (when all
+                             its values are in the gene arrays and it is valid),
+                             the others random; 0 (the paper's form) = all random */
 } amber_tune_params;
 
 typedef struct {

@@ -93,7 +93,8 @@ class TuneParams(ctypes.Structure):
     _fields_ = [("search", ctypes.c_int32), ("pop", ctypes.c_int32), ("generations", ctypes.c_int32),
                 ("crossover", ctypes.c_int32), ("p_cross", ctypes.c_double), ("p_mut", ctypes.c_double),
                 ("pool_frac", ctypes.c_double), ("seed", ctypes.c_uint64), ("warmup", ctypes.c_int32),
-                ("reps", ctypes.c_int32), ("eval_timeout_s", ctypes.c_double), ("max_evals", ctypes.c_int64)]
+                ("reps", ctypes.c_int32), ("eval_timeout_s", ctypes.c_double), ("max_evals", ctypes.c_int64),
+                ("seed_default", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):

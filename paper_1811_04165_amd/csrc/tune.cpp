@@ -232,6 +232,26 @@ private:
         return false;
     }
 
+    // The library's default configuration as a genome: each gene at its
+    // default value (the first value where the array lacks it).  True when
+    // every default value is in its gene's array.
+    bool default_genome(Genome &g) const
+    {
+        bool all = true;
+        for (int i = 0; i < n_genes(); ++i) {
+            const int want = pb_.default_value(i);
+            g[i] = 0;
+            bool found = false;
+            for (int v = 0; v < pb_.n_values(i); ++v)
+                if (pb_.value(i, v) == want) {
+                    g[i] = v;
+                    found = true;
+                }
+            all = all && found;
+        }
+        return all;
+    }
+
     // ---- genetic algorithm ------------------------------------------------
     int tournament(const std::vector<double> &fit)
     {
@@ -309,8 +329,15 @@ private:
         if (n < 2 || p_.generations < 0) return fail(AMBER_E_ARG, "GA needs pop >= 2 and generations >= 0");
         std::vector<Genome> pop(n);
         std::vector<double> fit(n);
+        // seed_default: the first individual is the default configuration
+        // (when it is in the space and valid), the others random
+        Genome d(n_genes());
+        const bool seeded = p_.seed_default && default_genome(d) && valid(d);
         for (int i = 0; i < n; ++i) {
-            if (!random_genome(pop[i])) return fail(AMBER_E_CONFIG, "no valid configuration found to initialise");
+            if (i == 0 && seeded)
+                pop[i] = d;
+            else if (!random_genome(pop[i]))
+                return fail(AMBER_E_CONFIG, "no valid configuration found to initialise");
             fit[i] = evaluate(pop[i]);
         }
         log_line(0);
@@ -406,11 +433,7 @@ private:
     amber_status per_kernel()
     {
         Genome base(n_genes(), 0);
-        for (int i = 0; i < n_genes(); ++i) {
-            const int want = pb_.default_value(i);
-            for (int v = 0; v < pb_.n_values(i); ++v)
-                if (pb_.value(i, v) == want) base[i] = v;
-        }
+        default_genome(base);
         for (int k = 0; k < n_kernels(); ++k) {
             Genome best_k;
             double fit_k = kInf;

@@ -188,3 +188,25 @@ def test_per_kernel_search_solves_separable_landscape(amber):
     best = min(valid, key=lambda c: a[c[:k1]] + b[c[k1:]])
     assert _tiles_key(res.best, len(widths)) == best
     assert res.n_evals < len(valid)
+
+
+def test_ga_seeded_with_the_default(amber):
+    """seed_default puts the library's default configuration into the initial
+    population (elitism then keeps it unless something beats it); without it,
+    or when a default value is missing from its gene array, the population is
+    random."""
+    sp, info, widths = _small_space(amber, reduced=False)
+    n_w = len(widths)
+    key_d = _tiles_key(amber.default_tiles(), n_w)
+
+    def fit(t):
+        return 1e-4 if _tiles_key(t, n_w) == key_d else 2e-4
+
+    r = amber.search_tiles(sp, amber.tune_params("ga", pop=2, generations=0, seed_default=1), fit)
+    assert _tiles_key(r.best, n_w) == key_d and r.best_time_s == pytest.approx(1e-4)
+    r0 = amber.search_tiles(sp, amber.tune_params("ga", pop=2, generations=0, seed=1), fit)
+    assert r0.best_time_s == pytest.approx(2e-4)
+    # the default's snr_threads (128) is not in the reduced space: random start, no error
+    spr, _, _ = _small_space(amber)
+    r1 = amber.search_tiles(spr, amber.tune_params("ga", pop=4, generations=1, seed_default=1), fit)
+    assert r1.n_evals > 0 and r1.best_time_s == pytest.approx(2e-4)
