@@ -302,7 +302,12 @@ amber_status amber_snr(const int32_t *d_box, int32_t n_dm, int64_t box_stride, i
 
 /* amber_integrate followed by amber_snr in one kernel: each dedispersed row is
  * read once and its boxcar series live only in LDS and registers.  Same
- * arguments and results as the pair, without d_box. */
+ * arguments and results as the pair, without d_box.  tiles == NULL: the
+ * defaults, with snr_threads 64 when n_dm >= 4096 (one row per work-group;
+ * with that many rows single-wave groups keep the CUs busier) and the default
+ * 128 below, raised while 16 * snr_threads < twice the largest width rounded
+ * up to 16.  A batch with automatic tiles applies the same rule to its total
+ * number of rows. */
 amber_status amber_integrate_snr(const int32_t *d_dd, int32_t n_dm, int64_t dd_stride, int64_t n_out,
                                  const int32_t *widths, int32_t n_widths,
                                  float *d_snr, int32_t *d_peak_t,

@@ -51,6 +51,19 @@ amber_status hip_fail(hipError_t err, const char *what)
     return fail(AMBER_E_DEVICE, "%s: %s", what, hipGetErrorString(err));
 }
 
+int auto_snr_threads(int64_t rows, const int32_t *widths, int n_widths)
+{
+    // measured on 12 208-sample rows, widths 1..64: 2048 rows 0.105 ms at 128
+    // vs 0.114 ms at 64; 8192 rows 0.325 vs 0.376 ms; 49 152 rows 1.72 vs
+    // 2.02 ms (64 vs 128)
+    int t = rows >= 4096 ? 64 : default_tiles().snr_threads;
+    int maxw = 1;
+    for (int k = 0; k < n_widths; ++k) maxw = widths[k] > maxw ? widths[k] : maxw;
+    const int halo = (maxw + 15) / 16 * 16;
+    while (t * 16 < 2 * halo && t < kMaxThreads) t *= 2;
+    return t;
+}
+
 const amber_tiles &default_tiles()
 {
     static const amber_tiles t = make_default_tiles();
@@ -449,7 +462,9 @@ amber_status amber_integrate_snr(const int32_t *d_dd, int32_t n_dm, int64_t dd_s
     amber_status s = check_rows(d_dd, n_dm, dd_stride, n_out, "d_dd");
     if (s != AMBER_OK) return s;
     if (!d_snr) return fail(AMBER_E_ARG, "d_snr is NULL");
-    const amber_tiles &t = tiles ? *tiles : default_tiles();
+    amber_tiles t = tiles ? *tiles : default_tiles();
+    if (!tiles && widths && n_widths >= 1 && n_widths <= AMBER_MAX_WIDTHS)
+        t.snr_threads = auto_snr_threads(n_dm, widths, n_widths);
     BoxcarPlan plan;
     if ((s = plan_boxcar(t, widths, n_widths, n_out, &plan)) != AMBER_OK) return s;
     return launch_integrate_snr(plan, t, d_dd, n_dm, dd_stride, n_out, widths, n_widths, d_snr, d_peak_t,

@@ -69,12 +69,20 @@ amber_status amber_batch_create(const amber_beam *beams, int32_t n_beams, const 
         if (s != AMBER_OK) return s;
     }
     auto b = new amber_batch();
+    // automatic tiles: the boxcar / S/N rows of every beam share launches, so
+    // their work-group size follows the batch's total row count
+    int64_t total_rows = 0;
+    for (int k = 0; k < n_beams; ++k) total_rows += beams[k].info.n_dm;
+    const int snr_threads = auto_snr_threads(total_rows, widths, n_widths);
     // group beams by identical launch shapes
     for (int k = 0; k < n_beams; ++k) {
         const amber_beam &bm = beams[k];
         amber_tiles t;
         amber_status s = tiles ? AMBER_OK : auto_tiles(bm.info, &t, 0, nullptr, bm.n_out);
-        if (tiles) t = tiles[k];
+        if (tiles)
+            t = tiles[k];
+        else
+            t.snr_threads = snr_threads;
         DedispPlan dp;
         BoxcarPlan bp;
         if (s == AMBER_OK) s = plan_dedisperse(t, bm.info, &dp);

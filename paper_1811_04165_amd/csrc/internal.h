@@ -79,6 +79,11 @@ amber_status plan_boxcar(const amber_tiles &t, const int32_t *widths, int32_t n_
                          BoxcarPlan *out, int max_width = 1024);
 
 const amber_tiles &default_tiles();
+// Work-group size of the fused boxcar / S/N kernel when the caller passes no
+// tiles: 64 from 4096 rows up (one row per work-group: enough rows keep the
+// CUs busy with single-wave groups), else the default 128; raised while a
+// chunk of 16 samples per work-item is shorter than twice the largest width.
+int auto_snr_threads(int64_t rows, const int32_t *widths, int n_widths);
 
 // One beam's dedispersion work: the arguments of a launch, or one entry of a
 // batched launch's job table (tiles of job j occupy work-groups

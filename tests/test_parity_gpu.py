@@ -152,6 +152,21 @@ def test_dedisperse_odd_shapes(amber, torch, case):
         assert np.array_equal(out.cpu().numpy(), ref), kw
 
 
+@pytest.mark.parametrize("widths", [(1, 2, 4, 8, 16, 32, 64), (1, 1024)], ids=["w1-64", "w1-1024"])
+def test_integrate_snr_automatic_tiles_many_rows(amber, torch, widths):
+    """tiles = None with 4096 rows or more: single-wave work-groups, or (width
+    1024) the larger group the chunk needs; sampled rows against the oracle."""
+    n_dm, n_out = 5000, 2100
+    rng = np.random.default_rng(5000 + len(widths))
+    dd = rng.integers(0, 391680, size=(n_dm, n_out)).astype(np.int32)
+    ddd = torch.from_numpy(dd).cuda()
+    say("integrate_snr automatic tiles", n_dm, widths)
+    s, p = amber.integrate_snr(ddd, n_out, widths)
+    rows = np.unique(np.concatenate([[0, 1, 4095, 4096, n_dm - 1], rng.integers(0, n_dm, 60)]))
+    _, ref_s, ref_p = _oracle_box_snr(dd[rows], widths)
+    _check_snr(s.cpu().numpy()[:, rows], p.cpu().numpy()[:, rows], ref_s, ref_p)
+
+
 def test_empty_series(amber, torch, small_case):
     """n_out = 0: dedispersion launches nothing and returns an empty table; a
     boxcar or S/N of an empty series is refused (no width fits)."""
