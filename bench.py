@@ -897,9 +897,13 @@ def tune_subband_report(seeds: int, grid_name: str = "table2-grid"):
     rnd = [run("random", seed=100 + s, max_evals=ga[s - 1].n_evals) for s in range(1, seeds + 1)]
     pk = run("per_kernel")
 
+    # the boxcar / S/N tiles the search held (explicit: with tiles=None the
+    # library would size its work-groups by the 49152 rows)
+    t_box = amber.make_tiles(snr_threads=d.snr_threads, boxcar_step=[d.boxcar_step[k] for k in range(len(wl.widths))])
+
     def path(t1, t2):
         amber.subband_dedisperse(d1d, d2d, info, x, n_in, n_out, tiles1=t1, tiles2=t2, out=dd, work=work)
-        amber.integrate_snr(dd, n_out, wl.widths, out=(snr, peak))
+        amber.integrate_snr(dd, n_out, wl.widths, t_box, out=(snr, peak))
 
     finalists = [(r.step1, r.step2) for r in ga + rnd + [pk]] + [(None, None)]
     print("[bench] interleaved re-timing of %d finalists" % len(finalists), file=sys.stderr, flush=True)
