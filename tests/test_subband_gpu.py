@@ -108,6 +108,29 @@ def test_subband_step_one_rows(amber, torch):
         assert np.array_equal(w[s], ref), s
 
 
+def test_subband_shift_split_is_exact(amber, torch):
+    """The library moves each coarse DM's smallest step-two shift into step
+    one; the oracle's tables keep every shift where the scheme defines it.
+    Both splits through the same entry point (the info describing each) give
+    the same trials, equal to the oracle's."""
+    n_out = 1777
+    f = SMALL.freqs()
+    d1, d2, info, o1, o2, x, n_in = _setup(amber, SMALL, SMALL_GRID, n_out, seed=65)
+    o1 = np.ascontiguousarray(o1, dtype=np.int32)
+    o2 = np.ascontiguousarray(o2, dtype=np.int32)
+    raw = amber.SubbandInfo(n_chan=info.n_chan, n_subbands=info.n_subbands, n_coarse=info.n_coarse,
+                            n_fine=info.n_fine, max_delay1=int(o1.max()), max_step1=int(np.diff(o1, axis=1).max()),
+                            max_delay2=int(o2.max()), max_step2=int(np.diff(o2, axis=1).max()),
+                            max_delay=int((o2 + o1.max(axis=2).T[:, None, :]).max()))
+    assert raw.max_delay == info.max_delay          # the composed shifts are the same
+    assert raw.max_delay2 > info.max_delay2 and raw.max_step1 <= info.max_step1
+    say("subband shift split", info, raw)
+    moved = _run(amber, torch, d1, d2, info, x, n_in, n_out).cpu().numpy()
+    kept = _run(amber, torch, o1, o2, raw, x, n_in, n_out).cpu().numpy()
+    assert np.array_equal(moved, kept)
+    assert np.array_equal(moved, oracle.subband_dedisperse(o1, o2, x, n_in, n_out))
+
+
 def test_subband_refuses_direct_reads(amber, torch):
     """The subband steps stage their input in LDS: tiles asking for direct
     reads are refused on the host, before any launch."""
