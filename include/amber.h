@@ -520,9 +520,12 @@ typedef struct amber_batch amber_batch;  /* opaque */
 /* Plans a batch: beams whose dedispersion tiles coincide share one launch
  * (each work-group finds its beam in a job table), and beams whose boxcar /
  * S/N tiles coincide share one launch; all beams use the same widths.
- * tiles: per-beam array (e.g. a tuned configuration per shape class) or NULL
- * for amber_auto_tiles(info, n_out) of each beam.  The job tables live in device memory
- * owned by the batch (allocated here, freed by amber_batch_destroy).
+ * tiles: per-beam array (a tuned configuration per shape class, or one
+ * configuration repeated for every beam: fewer distinct tiles mean fewer
+ * launches) or NULL for amber_auto_tiles(info, n_out) of each beam, with the
+ * boxcar / S/N work-group size chosen from the batch's total rows (as
+ * amber_integrate_snr chooses it from n_dm).  The job tables live in device
+ * memory owned by the batch (allocated here, freed by amber_batch_destroy).
  * Arguments are validated as the single-beam calls validate them. */
 amber_status amber_batch_create(const amber_beam *beams, int32_t n_beams, const int32_t *widths, int32_t n_widths,
                                 const amber_tiles *tiles, amber_batch **batch);
