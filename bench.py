@@ -188,19 +188,24 @@ def tune_report(seeds: int, log_path=None):
         return r
 
     ga = [run("ga", seed=s) for s in range(1, seeds + 1)]
+    gas = [run("ga", seed=s, seed_default=1) for s in range(1, seeds + 1)]   # initial population holds the defaults
     rnd = [run("random", seed=100 + s, max_evals=ga[s - 1].n_evals) for s in range(1, seeds + 1)]
     pk = run("per_kernel")
     ex = run("exhaustive", reps=1, warmup=1)
-    finalists = [r.best for r in ga] + [r.best for r in rnd] + [pk.best, ex.best]
+    finalists = [r.best for r in ga] + [r.best for r in rnd] + [pk.best, ex.best] + [r.best for r in gas]
     print("[bench] interleaved re-timing of %d finalists" % len(finalists), file=sys.stderr, flush=True)
     t = time_configs(search, x, finalists, reps=100)
     n = seeds
     t_ga, t_rnd, t_pk, t_ex = t[:n], t[n:2 * n], t[2 * n], t[2 * n + 1]
+    t_gas = t[2 * n + 2:]
     nw = len(wl.widths)
     out.update({
-        "retimed_s": {"ga": t_ga, "random": t_rnd, "per_kernel": t_pk, "exhaustive": t_ex},
+        "retimed_s": {"ga": t_ga, "random": t_rnd, "per_kernel": t_pk, "exhaustive": t_ex, "ga_seeded": t_gas},
         "ga_median_over_exhaustive": statistics.median(t_ga) / t_ex,
         "ga_worst_over_exhaustive": max(t_ga) / t_ex,
+        "ga_seeded_median_over_exhaustive": statistics.median(t_gas) / t_ex,
+        "ga_seeded_worst_over_exhaustive": max(t_gas) / t_ex,
+        "ga_seeded_evals_median": statistics.median([r.n_evals for r in gas]),
         "random_median_over_exhaustive": statistics.median(t_rnd) / t_ex,
         "per_kernel_over_exhaustive": t_pk / t_ex,
         "cost": {"ga_evals_median": statistics.median([r.n_evals for r in ga]),
