@@ -19,7 +19,7 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-N_CASES = 24
+N_CASES = 40
 SNR_RTOL = 1e-5
 
 
@@ -122,7 +122,7 @@ def test_random_case(amber, torch, case):
         pytest.fail("no valid S/N tile drawn")
 
 
-N_SUBBAND_CASES = 12
+N_SUBBAND_CASES = 16
 
 
 def _draw_step_tiles(rng, step):
@@ -182,7 +182,7 @@ def test_random_subband_case(amber, torch, case):
         pytest.fail("no subband tiles accepted")
 
 
-N_DECIMATION_CASES = 12
+N_DECIMATION_CASES = 16
 
 
 @pytest.mark.parametrize("case", range(N_DECIMATION_CASES))
