@@ -259,10 +259,8 @@ constexpr int kMaxFactor = 4096;  // largest decimation factor (the paper's larg
 // (16 samples per work-item) holds twice the largest factor and one decimated
 // bin per work-item and step (measured fastest on the 1536-channel beam: the
 // decimated series are short, so larger steps leave work-items idle).
-amber_status downsample_tiles(const amber_tiles *tiles, const int32_t *factors, int32_t n_factors, int64_t n_out,
-                              amber_tiles *out)
+amber_status downsample_tiles(const amber_tiles *tiles, const int32_t *factors, int32_t n_factors, amber_tiles *out)
 {
-    (void)n_out;
     if (!factors || n_factors < 1 || n_factors > AMBER_MAX_WIDTHS)
         return fail(AMBER_E_ARG, "n_factors=%d must be in [1, %d]", n_factors, AMBER_MAX_WIDTHS);
     if (tiles) {
@@ -479,7 +477,7 @@ amber_status amber_downsample(const int32_t *d_dd, int32_t n_dm, int64_t dd_stri
     amber_status s = check_rows(d_dd, n_dm, dd_stride, n_out, "d_dd");
     if (s != AMBER_OK) return s;
     amber_tiles t;
-    if ((s = downsample_tiles(tiles, factors, n_factors, n_out, &t)) != AMBER_OK) return s;
+    if ((s = downsample_tiles(tiles, factors, n_factors, &t)) != AMBER_OK) return s;
     for (int k = 0; k < n_factors; ++k)
         if (y_stride < n_out / factors[k])
             return fail(AMBER_E_SHAPE, "y_stride=%lld < n_out / factors[%d]", (long long)y_stride, k);
@@ -499,7 +497,7 @@ amber_status amber_downsample_snr(const int32_t *d_dd, int32_t n_dm, int64_t dd_
     if (s != AMBER_OK) return s;
     if (!d_snr) return fail(AMBER_E_ARG, "d_snr is NULL");
     amber_tiles t;
-    if ((s = downsample_tiles(tiles, factors, n_factors, n_out, &t)) != AMBER_OK) return s;
+    if ((s = downsample_tiles(tiles, factors, n_factors, &t)) != AMBER_OK) return s;
     BoxcarPlan plan;
     if ((s = plan_boxcar(t, factors, n_factors, n_out, &plan, kMaxFactor)) != AMBER_OK) return s;
     return launch_integrate_snr(plan, t, d_dd, n_dm, dd_stride, n_out, factors, n_factors, d_snr, d_peak,
