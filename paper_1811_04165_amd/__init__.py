@@ -120,6 +120,27 @@ def _check_dev(t, dtype, name: str, ndim: int):
         raise ValueError("%s must be %d-D with unit stride along its last dimension" % (name, ndim))
 
 
+def _check_table(t, dtype, name: str, n_w: int, n_dm: int, device):
+    """An output table [n_w, n_dm]: contiguous, on `device`."""
+    _check_dev(t, dtype, name, 2)
+    if tuple(t.shape) != (n_w, n_dm) or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous [%d, %d] tensor" % (name, n_w, n_dm))
+    if t.device != device:
+        raise ValueError("%s must be on %s" % (name, device))
+
+
+def _table_out(out, n_w: int, n_dm: int, device):
+    """(snr float32, peak int32) output tables, allocated or checked."""
+    torch = _torch()
+    if out is None:
+        return (torch.empty((n_w, n_dm), dtype=torch.float32, device=device),
+                torch.empty((n_w, n_dm), dtype=torch.int32, device=device))
+    s, p = out
+    _check_table(s, torch.float32, "snr out", n_w, n_dm, device)
+    _check_table(p, torch.int32, "peak out", n_w, n_dm, device)
+    return s, p
+
+
 def _tiles_ref(tiles: Optional[Tiles]):
     return ctypes.byref(tiles) if tiles is not None else None
 
@@ -140,6 +161,8 @@ def dedisperse(delays, info: DelayInfo, x, n_in: int, n_out: int, tiles: Optiona
     _check_dev(out, torch.int32, "out", 2)
     if out.shape[0] != info.n_dm or out.shape[1] < n_out:
         raise ValueError("out must be [n_dm, >= n_out]")
+    if delays.device != x.device or out.device != x.device:
+        raise ValueError("delays, x and out must be on one device")
     if keep is not None:
         _check_dev(keep, torch.uint8, "keep", 1)
         if keep.shape[0] != info.n_chan or not keep.is_contiguous():
@@ -226,13 +249,16 @@ def integrate(dd, n_out: int, widths: Sequence[int], tiles: Optional[Tiles] = No
     """dd: int32 CUDA [n_dm, >= n_out].  Returns int32 [n_w, n_dm, n_out] (row k valid up to n_out - w_k + 1)."""
     torch = _torch()
     _check_dev(dd, torch.int32, "dd", 2)
+    if dd.shape[1] < int(n_out) or int(n_out) < 1:
+        raise ValueError("dd must be [n_dm, >= n_out] with n_out >= 1")
     w, wp = _widths_arr(widths)
     n_dm = dd.shape[0]
     if out is None:
         out = torch.empty((len(w), n_dm, n_out), dtype=torch.int32, device=dd.device)
     _check_dev(out, torch.int32, "out", 3)
-    if out.shape[0] != len(w) or out.shape[1] != n_dm or out.stride(1) < n_out or out.stride(0) != n_dm * out.stride(1):
-        raise ValueError("out must be [n_w, n_dm, stride] with packed rows")
+    if out.device != dd.device or out.shape[0] != len(w) or out.shape[1] != n_dm or out.shape[2] < n_out \
+            or out.stride(0) != n_dm * out.stride(1):
+        raise ValueError("out must be int32 [n_w, n_dm, >= n_out] with packed rows on %s" % dd.device)
     check(load().amber_integrate(dd.data_ptr(), n_dm, dd.stride(0), int(n_out), wp, len(w), out.data_ptr(),
                                  out.stride(1), _tiles_ref(tiles), _stream_handle(stream)))
     return out
@@ -257,13 +283,11 @@ def integrate_snr(dd, n_out: int, widths: Sequence[int], tiles: Optional[Tiles] 
     """Fused boxcar + S/N.  dd: int32 CUDA [n_dm, >= n_out].  Returns (snr float32, peak int32), [n_w, n_dm] each."""
     torch = _torch()
     _check_dev(dd, torch.int32, "dd", 2)
+    if dd.shape[1] < int(n_out) or int(n_out) < 1:
+        raise ValueError("dd must be [n_dm, >= n_out] with n_out >= 1")
     w, wp = _widths_arr(widths)
     n_dm = dd.shape[0]
-    if out is None:
-        s = torch.empty((len(w), n_dm), dtype=torch.float32, device=dd.device)
-        p = torch.empty((len(w), n_dm), dtype=torch.int32, device=dd.device)
-    else:
-        s, p = out
+    s, p = _table_out(out, len(w), n_dm, dd.device)
     check(load().amber_integrate_snr(dd.data_ptr(), n_dm, dd.stride(0), int(n_out), wp, len(w), s.data_ptr(),
                                      p.data_ptr(), _tiles_ref(tiles), _stream_handle(stream)))
     return s, p
@@ -273,10 +297,19 @@ def downsample(dd, n_out: int, factors: Sequence[int], tiles: Optional[Tiles] = 
     """Decimation: int32 [n_f, n_dm, max_j] with row k valid up to n_out // factors[k]."""
     torch = _torch()
     _check_dev(dd, torch.int32, "dd", 2)
+    if dd.shape[1] < int(n_out) or int(n_out) < 1:
+        raise ValueError("dd must be [n_dm, >= n_out] with n_out >= 1")
     f, fp = _widths_arr(factors)
     n_dm = dd.shape[0]
+    if len(f) == 0 or int(f.min()) < 1:
+        raise ValueError("factors must be >= 1")
+    n_y = int(n_out) // int(f.min())
     if out is None:
-        out = torch.empty((len(f), n_dm, int(n_out) // int(f.min())), dtype=torch.int32, device=dd.device)
+        out = torch.empty((len(f), n_dm, n_y), dtype=torch.int32, device=dd.device)
+    _check_dev(out, torch.int32, "out", 3)
+    if out.device != dd.device or out.shape[0] != len(f) or out.shape[1] != n_dm or out.shape[2] < n_y \
+            or out.stride(0) != n_dm * out.stride(1):
+        raise ValueError("out must be int32 [n_f, n_dm, >= n_out // min f] with packed rows on %s" % dd.device)
     check(load().amber_downsample(dd.data_ptr(), n_dm, dd.stride(0), int(n_out), fp, len(f), out.data_ptr(),
                                   out.stride(1), _tiles_ref(tiles), _stream_handle(stream)))
     return out
@@ -286,13 +319,11 @@ def downsample_snr(dd, n_out: int, factors: Sequence[int], tiles: Optional[Tiles
     """Decimation + S/N fused.  Returns (snr float32, peak int32), [n_f, n_dm] each; peaks in decimated samples."""
     torch = _torch()
     _check_dev(dd, torch.int32, "dd", 2)
+    if dd.shape[1] < int(n_out) or int(n_out) < 1:
+        raise ValueError("dd must be [n_dm, >= n_out] with n_out >= 1")
     f, fp = _widths_arr(factors)
     n_dm = dd.shape[0]
-    if out is None:
-        s = torch.empty((len(f), n_dm), dtype=torch.float32, device=dd.device)
-        p = torch.empty((len(f), n_dm), dtype=torch.int32, device=dd.device)
-    else:
-        s, p = out
+    s, p = _table_out(out, len(f), n_dm, dd.device)
     check(load().amber_downsample_snr(dd.data_ptr(), n_dm, dd.stride(0), int(n_out), fp, len(f), s.data_ptr(),
                                       p.data_ptr(), _tiles_ref(tiles), _stream_handle(stream)))
     return s, p

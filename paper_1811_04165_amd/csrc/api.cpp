@@ -478,12 +478,14 @@ amber_status amber_downsample(const int32_t *d_dd, int32_t n_dm, int64_t dd_stri
     if (s != AMBER_OK) return s;
     amber_tiles t;
     if ((s = downsample_tiles(tiles, factors, n_factors, &t)) != AMBER_OK) return s;
+    if (!d_y || ((uintptr_t)d_y & 3) != 0) return fail(AMBER_E_ARG, "d_y is NULL or misaligned");
+    // the plan checks every factor against [1, min(n_out, 4096)] before the
+    // output stride is sized from them
+    BoxcarPlan plan;
+    if ((s = plan_boxcar(t, factors, n_factors, n_out, &plan, kMaxFactor)) != AMBER_OK) return s;
     for (int k = 0; k < n_factors; ++k)
         if (y_stride < n_out / factors[k])
             return fail(AMBER_E_SHAPE, "y_stride=%lld < n_out / factors[%d]", (long long)y_stride, k);
-    if (!d_y || ((uintptr_t)d_y & 3) != 0) return fail(AMBER_E_ARG, "d_y is NULL or misaligned");
-    BoxcarPlan plan;
-    if ((s = plan_boxcar(t, factors, n_factors, n_out, &plan, kMaxFactor)) != AMBER_OK) return s;
     return launch_integrate(plan, t, d_dd, n_dm, dd_stride, n_out, factors, n_factors, d_y, y_stride,
                             (hipStream_t)stream, 1);
 }

@@ -142,6 +142,63 @@ def test_device_calls_validate_before_launch():
     f10 = (ctypes.c_int32 * 1)(10)
     rc = lib.amber_downsample(fake, 4, 100, 100, f10, 1, fake, 9, None, None)
     assert rc == -2 and b"y_stride" in lib.amber_last_error()
+    # a zero or negative factor is refused before any division by it
+    for bad in (0, -3):
+        fb = (ctypes.c_int32 * 2)(10, bad)
+        rc = lib.amber_downsample(fake, 4, 100, 100, fb, 2, fake, 100, None, None)
+        assert rc == -1 and b"widths[1]" in lib.amber_last_error()
+        rc = lib.amber_downsample_snr(fake, 4, 100, 100, fb, 2, fake, fake, None, None)
+        assert rc == -1
+    rc = lib.amber_downsample(fake, 4, 100, 100, f10, 1, None, 100, None, None)
+    assert rc == -1 and b"d_y" in lib.amber_last_error()
+
+
+def test_binding_rejects_host_and_misshaped_outputs():
+    """The Python wrappers refuse host tensors and output tables of the wrong
+    dtype or shape before calling the library (a short output would be
+    written past its end on the device)."""
+    import torch
+    import paper_1811_04165_amd as amber
+    dd = torch.zeros((4, 100), dtype=torch.int32)
+    with pytest.raises(TypeError):
+        amber.integrate_snr(dd, 100, [1, 2])
+    with pytest.raises(TypeError):
+        amber.downsample(dd, 100, [10])
+    with pytest.raises(TypeError):
+        amber.downsample_snr(dd, 100, [10], out=(torch.zeros((1, 4)), torch.zeros((1, 4), dtype=torch.int32)))
+    from paper_1811_04165_amd import _table_out, _check_table
+
+    class _Fake:
+        """A stand-in exposing what the checks read of a device tensor."""
+        def __init__(self, dtype, shape, device="cuda:0", contiguous=True):
+            self.dtype, self.shape, self.device, self._c = dtype, shape, device, contiguous
+            self.is_cuda = True
+
+        def dim(self):
+            return len(self.shape)
+
+        def stride(self, k):
+            return 1
+
+        def is_contiguous(self):
+            return self._c
+
+    import paper_1811_04165_amd as pkg
+    real = torch.Tensor
+    try:
+        torch.Tensor = _Fake  # isinstance checks in the binding see the stand-in as a tensor
+        ok = _Fake(torch.float32, (2, 4))
+        _check_table(ok, torch.float32, "snr out", 2, 4, "cuda:0")
+        for bad, exc in ((_Fake(torch.float64, (2, 4)), TypeError), (_Fake(torch.float32, (1, 4)), ValueError),
+                         (_Fake(torch.float32, (2, 4), contiguous=False), ValueError),
+                         (_Fake(torch.float32, (2, 4), device="cuda:1"), ValueError)):
+            with pytest.raises(exc):
+                _check_table(bad, torch.float32, "snr out", 2, 4, "cuda:0")
+        with pytest.raises(TypeError):
+            _table_out((_Fake(torch.float32, (2, 4)), _Fake(torch.float32, (2, 4))), 2, 4, "cuda:0")
+    finally:
+        torch.Tensor = real
+    assert pkg is amber
 
 
 def test_gpu_test_tiles_are_valid():

@@ -391,3 +391,54 @@ def test_injected_pulse_recovered_small():
         assert pulse.t0 - w < p[kk, pulse.dm_index] < pulse.t0 + pulse.width
     # off the pulse's DM the detection is weaker
     assert s[:, pulse.dm_index].max() > s[:, pulse.dm_index + 2].max() + 5
+
+
+# --- best candidate and the workloads' delay constants -------------------------------
+
+def test_best_candidate_tie_rule():
+    """Equal S/N values: the smallest DM index wins, then the smallest width
+    index (the candidate rule of the search); a transposed loop order or a
+    non-strict comparison picks a different entry in one of these tables."""
+    s = np.zeros((4, 9))
+    s[2, 3] = s[0, 5] = 7.5            # same value at (DM 3, width 2) and (DM 5, width 0)
+    assert oracle.best_candidate(s)[:2] == (3, 2)
+    s[1, 3] = 7.5                      # and at (DM 3, width 1): same DM, smaller width
+    assert oracle.best_candidate(s)[:2] == (3, 1)
+    s[3, 8] = 7.5000001                # a strictly larger value anywhere wins
+    assert oracle.best_candidate(s)[:2] == (8, 3)
+    assert oracle.best_candidate(np.full((3, 4), -1.0))[:2] == (0, 0)
+
+
+def _exact_delay(f_c, f_top, dm, t_samp):
+    """The cold-plasma delay in exact rational arithmetic (decimal inputs taken
+    as written), rounded half away from zero: no floating point at all."""
+    from fractions import Fraction as Fr
+    f_c, f_top, dm, t_samp = (Fr(v if isinstance(v, str) else repr(float(v))) for v in (f_c, f_top, dm, t_samp))
+    x = Fr("4148.808") * dm * (1 / f_c ** 2 - 1 / f_top ** 2) / t_samp
+    n = math.floor(x)
+    return n + 1 if x - n >= Fr(1, 2) else n
+
+
+def test_workload_delay_constants():
+    """The workloads' largest delays and one entry, evaluated independently
+    (exact rationals) and as stated for the two workloads: the 256-channel one
+    has max delay 1435 and delay 565 at DM 50, channel 0; the 1536-channel beam
+    has max delay 11593."""
+    small, beam = workloads.small(), workloads.beam()
+    g = small.geom
+    d, mx = oracle.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+    f = g.freqs()
+    assert mx == 1435 and d[50, 0] == 565 and d[-1, 0] == mx
+    assert _exact_delay(f[0], f.max(), "50", g.t_samp_s) == 565
+    assert _exact_delay(f[0], f.max(), "127", g.t_samp_s) == 1435
+    g = beam.geom
+    d, mx = oracle.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+    f = g.freqs()
+    assert mx == 11593 and d[-1, 0] == mx
+    assert _exact_delay(f[0], f.max(), g.dm_first + (g.n_dm - 1) * g.dm_step,
+                        g.t_samp_s) == 11593
+    # a few more entries of the beam table, exactly
+    rng = np.random.default_rng(17)
+    for i, c in zip(rng.integers(0, g.n_dm, 12), rng.integers(0, g.n_chan, 12)):
+        dm = g.dm_first + int(i) * g.dm_step
+        assert d[i, c] == _exact_delay(f[c], f.max(), dm, g.t_samp_s), (i, c)
