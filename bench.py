@@ -942,6 +942,44 @@ def tune_subband_report(seeds: int, grid_name: str = "table2-grid"):
             "higher_is_better": False, "tune_subband": out}
 
 
+def peaks_report():
+    """Issue rates and bandwidths the roofline peaks rest on, measured with the
+    microbenchmarks of paper_1811_04165_amd/peaks/peaks.hip (one launch of
+    2048 work-groups of 256 work-items, i.e. 32 wavefronts per CU, each timed
+    with HIP events after a warm-up launch)."""
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1811_04165_amd", "libamber_peaks.so"))
+    out = torch.zeros(2048 * 256, dtype=torch.int32, device="cuda")
+    cus, clk = 256, 2.4e9
+    blocks = 2048
+    res = {"blocks": blocks, "threads": 256, "clock_hz_assumed": clk, "cus": cus, "valu": {}, "lds": {}}
+    names = ["v_add_u32", "v_add3_u32", "v_pk_add_u16", "v_lshl_or_b32", "v_fma_f64", "v_cvt_f64_i32",
+             "v_max3_i32"]
+    for kind, name in enumerate(names):
+        r = ctypes.c_double()
+        if lib.peaks_valu(kind, blocks, 20000, ctypes.c_void_p(out.data_ptr()), ctypes.byref(r)) != 0:
+            raise RuntimeError("peaks_valu %s failed" % name)
+        res["valu"][name] = {"wave_instr_per_s": r.value, "lane_ops_per_s": 64 * r.value,
+                             "lanes_per_clk_per_cu": 64 * r.value / (cus * clk)}
+    for form, name in enumerate(["ds_read_b32", "ds_read2st64_b32", "ds_read_b64", "ds_read2st64_b64",
+                                 "ds_read_b128"]):
+        r = ctypes.c_double()
+        if lib.peaks_lds(form, blocks, 4000, ctypes.c_void_p(out.data_ptr()), ctypes.byref(r)) != 0:
+            raise RuntimeError("peaks_lds %s failed" % name)
+        res["lds"][name] = {"bytes_per_s": r.value, "bytes_per_clk_per_cu": r.value / (cus * clk)}
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    bw, sec = ctypes.c_double(), ctypes.c_double()
+    if lib.peaks_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), ctypes.c_size_t(n),
+                      cus * 16, ctypes.byref(bw), ctypes.byref(sec)) != 0:
+        raise RuntimeError("peaks_copy failed")
+    res["hbm_copy"] = {"bytes": n, "seconds": sec.value, "read_plus_write_bytes_per_s": bw.value,
+                       "frac_of_8TBs": bw.value / 8e12}
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -980,6 +1018,9 @@ def main() -> int:
     ap.add_argument("--downsample", action="store_true",
                     help="instead of the single-beam step: decimating downsampling + S/N over the factor ladder "
                          "on the dedispersed beam")
+    ap.add_argument("--peaks", action="store_true",
+                    help="instead of the throughput step: the VALU, LDS and copy microbenchmarks behind the "
+                         "roofline peaks")
     ap.add_argument("--extras", type=int, default=1,
                     help="1: also run one GA tile search (tune time) and 5 s of serving (p99 chunk latency)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -999,6 +1040,9 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 3
+    if args.peaks:
+        print(json.dumps(peaks_report()))
+        return 0
     if args.tune:
         print(json.dumps(tune_report(args.tune_seeds, args.tune_log or None)))
         return 0

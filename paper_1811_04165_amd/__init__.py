@@ -249,8 +249,8 @@ def integrate(dd, n_out: int, widths: Sequence[int], tiles: Optional[Tiles] = No
     """dd: int32 CUDA [n_dm, >= n_out].  Returns int32 [n_w, n_dm, n_out] (row k valid up to n_out - w_k + 1)."""
     torch = _torch()
     _check_dev(dd, torch.int32, "dd", 2)
-    if dd.shape[1] < int(n_out) or int(n_out) < 1:
-        raise ValueError("dd must be [n_dm, >= n_out] with n_out >= 1")
+    if dd.shape[1] < int(n_out):
+        raise ValueError("dd must be [n_dm, >= n_out]")
     w, wp = _widths_arr(widths)
     n_dm = dd.shape[0]
     if out is None:
@@ -283,8 +283,8 @@ def integrate_snr(dd, n_out: int, widths: Sequence[int], tiles: Optional[Tiles] 
     """Fused boxcar + S/N.  dd: int32 CUDA [n_dm, >= n_out].  Returns (snr float32, peak int32), [n_w, n_dm] each."""
     torch = _torch()
     _check_dev(dd, torch.int32, "dd", 2)
-    if dd.shape[1] < int(n_out) or int(n_out) < 1:
-        raise ValueError("dd must be [n_dm, >= n_out] with n_out >= 1")
+    if dd.shape[1] < int(n_out):
+        raise ValueError("dd must be [n_dm, >= n_out]")
     w, wp = _widths_arr(widths)
     n_dm = dd.shape[0]
     s, p = _table_out(out, len(w), n_dm, dd.device)
@@ -297,8 +297,8 @@ def downsample(dd, n_out: int, factors: Sequence[int], tiles: Optional[Tiles] = 
     """Decimation: int32 [n_f, n_dm, max_j] with row k valid up to n_out // factors[k]."""
     torch = _torch()
     _check_dev(dd, torch.int32, "dd", 2)
-    if dd.shape[1] < int(n_out) or int(n_out) < 1:
-        raise ValueError("dd must be [n_dm, >= n_out] with n_out >= 1")
+    if dd.shape[1] < int(n_out):
+        raise ValueError("dd must be [n_dm, >= n_out]")
     f, fp = _widths_arr(factors)
     n_dm = dd.shape[0]
     if len(f) == 0 or int(f.min()) < 1:
@@ -319,8 +319,8 @@ def downsample_snr(dd, n_out: int, factors: Sequence[int], tiles: Optional[Tiles
     """Decimation + S/N fused.  Returns (snr float32, peak int32), [n_f, n_dm] each; peaks in decimated samples."""
     torch = _torch()
     _check_dev(dd, torch.int32, "dd", 2)
-    if dd.shape[1] < int(n_out) or int(n_out) < 1:
-        raise ValueError("dd must be [n_dm, >= n_out] with n_out >= 1")
+    if dd.shape[1] < int(n_out):
+        raise ValueError("dd must be [n_dm, >= n_out]")
     f, fp = _widths_arr(factors)
     n_dm = dd.shape[0]
     s, p = _table_out(out, len(f), n_dm, dd.device)

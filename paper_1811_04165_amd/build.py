@@ -40,6 +40,24 @@ def _compile(src: str) -> str:
     return obj
 
 
+PEAKS_SRC = os.path.join(PKG, "peaks", "peaks.hip")
+PEAKS_LIB = os.path.join(PKG, "libamber_peaks.so")
+
+
+def build_peaks(verbose: bool = False) -> str:
+    """The microbenchmarks behind the roofline peaks (a library of their own,
+    loaded only by the benchmark's peak measurement)."""
+    tmp = PEAKS_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "-x", "hip"] + COMMON + ["-shared", "-o", tmp, PEAKS_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (PEAKS_SRC, r.stdout, r.stderr))
+    os.replace(tmp, PEAKS_LIB)
+    if verbose:
+        print("built", PEAKS_LIB)
+    return PEAKS_LIB
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
@@ -54,6 +72,7 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)
+    build_peaks(verbose)
     return LIB
 
 
