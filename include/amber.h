@@ -271,6 +271,29 @@ amber_status amber_subband_dedisperse(const int32_t *d_delay1, const int32_t *d_
                                       int64_t dd_stride, int64_t n_out, const uint8_t *d_keep,
                                       const amber_tiles *tiles1, const amber_tiles *tiles2, void *stream);
 
+/* amber_subband_dedisperse for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops or harnesses that forbid
+ * allocation): no d_work argument and no allocation of any kind.  Step one's
+ * sums go to a device array that is part of the library
+ * (amber_subband_static_bytes(), 32 MiB; each GPU the library runs on holds
+ * its own copy until the process ends), with rows of n_out + max_delay2
+ * samples rounded up to 64.  The coarse DMs run in slices of as many as that
+ * array holds (two launches per slice); dd is the same as
+ * amber_subband_dedisperse's with the same tiles.
+ * Every call on one GPU shares that GPU's array: calls that overlap on the
+ * same GPU (other streams, other threads) race and give undefined results.
+ * Nothing in the array needs to start at zero.
+ * Errors: those of amber_subband_dedisperse, and AMBER_E_SHAPE when one coarse
+ * DM's step-one rows (n_subbands * row bytes) exceed the array. */
+amber_status amber_subband_dedisperse_noalloc(const int32_t *d_delay1, const int32_t *d_delay2,
+                                              const amber_subband_info *info, const uint8_t *d_in,
+                                              int64_t in_stride, int64_t n_in, int32_t *d_dd, int64_t dd_stride,
+                                              int64_t n_out, const uint8_t *d_keep, const amber_tiles *tiles1,
+                                              const amber_tiles *tiles2, void *stream);
+
+/* Bytes of the device array amber_subband_dedisperse_noalloc uses. */
+int64_t amber_subband_static_bytes(void);
+
 /* Sliding boxcar integration ("smoothing" of each dedispersed series):
  *     box[k][i][t] = sum over j < widths[k] of dd[i][t + j],
  *     t < n_out - widths[k] + 1

@@ -33,7 +33,7 @@ __all__ = ["AmberError", "DelayInfo", "Tiles", "TuneSpace", "TuneParams", "TuneR
            "space_size", "tune_params", "search_tiles", "tune", "Batch", "default_tiles", "make_tiles", "delay_table", "dedisperse",
            "integrate", "snr", "integrate_snr", "downsample", "downsample_snr", "validate_tiles", "auto_tiles", "version", "Search", "Server",
            "chunk_span", "admit", "server_config", "server_clock", "SubbandInfo", "subband_delay_tables",
-           "subband_dedisperse", "genes", "default_subband_space",
+           "subband_dedisperse", "subband_dedisperse_noalloc", "subband_static_bytes", "genes", "default_subband_space",
            "subband_space_size", "search_subband_tiles", "tune_subband"]
 
 load()  # fail loudly at import if the native library is missing
@@ -238,6 +238,49 @@ def subband_dedisperse(delay1, delay2, info: SubbandInfo, x, n_in: int, n_out: i
                                           out.stride(0), int(n_out), kp, _tiles_ref(tiles1), _tiles_ref(tiles2),
                                           _stream_handle(stream)))
     return out
+
+
+def subband_dedisperse_noalloc(delay1, delay2, info: SubbandInfo, x, n_in: int, n_out: int,
+                               tiles1: Optional[Tiles] = None, tiles2: Optional[Tiles] = None, out=None, keep=None,
+                               stream=None):
+    """subband_dedisperse without a work buffer: step one's sums go to the library's own device array
+    (subband_static_bytes(); no allocation by the library).  `out` may be given to keep the call free of any
+    allocation on the Python side too.  Returns int32 [n_coarse * n_fine, n_out]."""
+    torch = _torch()
+    _check_dev(delay1, torch.int32, "delay1", 3)
+    _check_dev(delay2, torch.int32, "delay2", 3)
+    _check_dev(x, torch.uint8, "x", 2)
+    n_sub, nc, nf = info.n_subbands, info.n_coarse, info.n_fine
+    if n_sub < 1 or info.n_chan % n_sub:
+        raise ValueError("info has an invalid subband count")
+    m = info.n_chan // n_sub
+    if not delay1.is_contiguous() or tuple(delay1.shape) != (n_sub, nc, m):
+        raise ValueError("delay1 must be contiguous [n_sub, n_coarse, n_chan / n_sub]")
+    if not delay2.is_contiguous() or tuple(delay2.shape) != (nc, nf, n_sub):
+        raise ValueError("delay2 must be contiguous [n_coarse, n_fine, n_sub]")
+    if x.shape[0] != info.n_chan or x.shape[1] < n_in:
+        raise ValueError("x must be [n_chan, >= n_in]")
+    if out is None:
+        out = torch.empty((nc * nf, n_out), dtype=torch.int32, device=x.device)
+    _check_dev(out, torch.int32, "out", 2)
+    if out.shape[0] != nc * nf or out.shape[1] < n_out:
+        raise ValueError("out must be [n_coarse * n_fine, >= n_out]")
+    kp = None
+    if keep is not None:
+        _check_dev(keep, torch.uint8, "keep", 1)
+        if keep.shape[0] != info.n_chan or not keep.is_contiguous():
+            raise ValueError("keep must be a contiguous uint8 [n_chan] tensor")
+        kp = keep.data_ptr()
+    check(load().amber_subband_dedisperse_noalloc(delay1.data_ptr(), delay2.data_ptr(), ctypes.byref(info),
+                                                  x.data_ptr(), x.stride(0), int(n_in), out.data_ptr(),
+                                                  out.stride(0), int(n_out), kp, _tiles_ref(tiles1),
+                                                  _tiles_ref(tiles2), _stream_handle(stream)))
+    return out
+
+
+def subband_static_bytes() -> int:
+    """Bytes of the device array subband_dedisperse_noalloc uses (one per GPU)."""
+    return int(load().amber_subband_static_bytes())
 
 
 def _widths_arr(widths: Sequence[int]):

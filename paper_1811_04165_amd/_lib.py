@@ -207,6 +207,12 @@ SIGNATURES = [
                                                 ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                                 ctypes.c_void_p, ctypes.POINTER(Tiles), ctypes.POINTER(Tiles),
                                                 ctypes.c_void_p]),
+    ("amber_subband_dedisperse_noalloc", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                        ctypes.POINTER(SubbandInfo), ctypes.c_void_p, ctypes.c_int64,
+                                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                                        ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(Tiles),
+                                                        ctypes.POINTER(Tiles), ctypes.c_void_p]),
+    ("amber_subband_static_bytes", ctypes.c_int64, []),
     ("amber_integrate", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                        c_i32p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                        ctypes.POINTER(Tiles), ctypes.c_void_p]),

@@ -165,6 +165,18 @@ private:
     std::vector<BGroup> b_;
 };
 
+// Two-step subband dedispersion with step one's sums in d_work
+// ([n_subbands][slice][work_stride] uint16): the arguments of
+// amber_subband_dedisperse, validated here.  work_elems < 0: the buffer holds
+// every coarse DM (one pair of launches); otherwise the coarse DMs run in
+// slices of work_elems / (n_subbands * work_stride), two launches per slice,
+// and a slice of one coarse DM that does not fit is AMBER_E_SHAPE.
+amber_status subband_run(const int32_t *d_delay1, const int32_t *d_delay2, const amber_subband_info *info,
+                         const uint8_t *d_in, int64_t in_stride, int64_t n_in, uint16_t *d_work,
+                         int64_t work_stride, int64_t work_elems, int32_t *d_dd, int64_t dd_stride, int64_t n_out,
+                         const uint8_t *d_keep, const amber_tiles *tiles1, const amber_tiles *tiles2,
+                         hipStream_t stream);
+
 // Launchers (device translation units).
 // Direct-read dedispersion (plans with direct set): one job or a job table,
 // uint8 input, int32 sums, one problem per job (groups 1).

@@ -153,13 +153,16 @@ amber_status amber_subband_delay_tables(const amber_subband_geometry *g, int32_t
     return AMBER_OK;
 }
 
-amber_status amber_subband_dedisperse(const int32_t *d_delay1, const int32_t *d_delay2,
-                                      const amber_subband_info *info, const uint8_t *d_in, int64_t in_stride,
-                                      int64_t n_in, uint16_t *d_work, int64_t work_stride, int32_t *d_dd,
-                                      int64_t dd_stride, int64_t n_out, const uint8_t *d_keep,
-                                      const amber_tiles *tiles1, const amber_tiles *tiles2, void *stream)
+}  // extern "C"
+
+namespace amber {
+
+amber_status subband_run(const int32_t *d_delay1, const int32_t *d_delay2, const amber_subband_info *info,
+                         const uint8_t *d_in, int64_t in_stride, int64_t n_in, uint16_t *d_work,
+                         int64_t work_stride, int64_t work_elems, int32_t *d_dd, int64_t dd_stride, int64_t n_out,
+                         const uint8_t *d_keep, const amber_tiles *tiles1, const amber_tiles *tiles2,
+                         hipStream_t stream)
 {
-    clear_error();
     if (!d_delay1 || !d_delay2 || !info || !d_in || !d_work || !d_dd) return fail(AMBER_E_ARG, "NULL pointer argument");
     const int n_chan = info->n_chan, n_sub = info->n_subbands, nc = info->n_coarse, nf = info->n_fine;
     if (n_chan < 1 || n_sub < 1 || nc < 1 || nf < 1 || n_chan % n_sub != 0)
@@ -184,6 +187,15 @@ amber_status amber_subband_dedisperse(const int32_t *d_delay1, const int32_t *d_
                     (long long)work_stride, (long long)n1);
     if (((uintptr_t)d_work & 3) != 0) return fail(AMBER_E_ARG, "d_work must be 4-byte aligned");
     if (dd_stride < n_out) return fail(AMBER_E_SHAPE, "dd_stride=%lld < n_out=%lld", (long long)dd_stride, (long long)n_out);
+    // coarse DMs whose step-one rows the work buffer holds at once
+    int64_t slice = nc;
+    if (work_elems >= 0) {
+        slice = work_elems / ((int64_t)n_sub * work_stride);
+        if (slice < 1)
+            return fail(AMBER_E_SHAPE, "step one's rows of one coarse DM need %lld bytes; the work buffer holds %lld",
+                        (long long)((int64_t)n_sub * work_stride * 2), (long long)(work_elems * 2));
+        if (slice > nc) slice = nc;
+    }
 
     const amber_delay_info info1{nc, m, info->max_delay1, info->max_step1};
     const amber_delay_info info2{nf, n_sub, info->max_delay2, info->max_step2};
@@ -191,42 +203,65 @@ amber_status amber_subband_dedisperse(const int32_t *d_delay1, const int32_t *d_
     amber_status s = plan_step(tiles1, info1, 0, &p1);
     if (s != AMBER_OK) return s;
     if ((s = plan_step(tiles2, info2, 1, &p2)) != AMBER_OK) return s;
-    if (n_out == 0) return AMBER_OK;
-
-    // step one: one group per subband
-    DedispJob j1 = make_dedisp_job(p1, d_delay1, nc, m, d_in, in_stride, reinterpret_cast<int32_t *>(d_work),
-                                   work_stride, n1);
-    j1.in_bytes = (int64_t)n_chan * in_stride;
-    j1.out_u16 = 1;
-    j1.store_vec = 1;  // even stride, 4-byte aligned rows: pairs go out as dwords
-    j1.keep = d_keep;
-    j1.groups = n_sub;
-    j1.group_blocks = j1.tiles_t * j1.tiles_dm;
-    j1.group_delays = (int64_t)nc * m;
-    j1.group_in = (int64_t)m * in_stride;
-    j1.group_out = (int64_t)nc * work_stride * 2;
-    j1.group_keep = m;
-    // step two: one group per coarse DM over the subband rows
-    const int64_t sub_bytes = (int64_t)nc * work_stride * 2;  // one subband's rows
-    DedispJob j2 = make_dedisp_job(p2, d_delay2, nf, n_sub, reinterpret_cast<const uint8_t *>(d_work), sub_bytes,
-                                   d_dd, dd_stride, n_out);
-    j2.in_u16 = 1;
-    j2.in_bytes = (int64_t)n_sub * sub_bytes;
-    j2.flush_every = 65535 / (255 * m);
-    j2.groups = nc;
-    j2.group_blocks = j2.tiles_t * j2.tiles_dm;
-    j2.group_delays = (int64_t)nf * n_sub;
-    j2.group_in = work_stride * 2;
-    j2.group_out = (int64_t)nf * dd_stride * 4;
-    const int64_t b1 = (int64_t)j1.group_blocks * n_sub, b2 = (int64_t)j2.group_blocks * nc;
-    if (b1 > 0x7fffffff || b2 > 0x7fffffff) return fail(AMBER_E_SHAPE, "subband grid too large");
     const int64_t lds1 = p1.lds_bytes + (d_keep ? mask_lds_bytes(p1) : 0);
     if (lds1 > kMaxLdsBytes)
         return fail(AMBER_E_CONFIG, "masked step-one tile needs %lld B of LDS (limit %lld)", (long long)lds1,
                     (long long)kMaxLdsBytes);
-    if ((s = launch_dedisperse_jobs(p1, &j1, nullptr, 1, b1, lds1, (hipStream_t)stream)) != AMBER_OK)
-        return s;
-    return launch_dedisperse_jobs(p2, &j2, nullptr, 1, b2, p2.lds_bytes, (hipStream_t)stream);
+    if (n_out == 0) return AMBER_OK;
+
+    // Both steps over the coarse DMs [j0, j0 + jn): step one's sums of those
+    // coarse DMs fill the work buffer as [n_sub][jn][work_stride]; step two
+    // reads them back.  Each slice is computed exactly as the whole grid
+    // would be (the steps of different coarse DMs never meet).
+    for (int64_t j0 = 0; j0 < nc; j0 += slice) {
+        const int jn = (int)(nc - j0 < slice ? nc - j0 : slice);
+        // step one: one group per subband
+        DedispJob j1 = make_dedisp_job(p1, d_delay1 + j0 * m, jn, m, d_in, in_stride,
+                                       reinterpret_cast<int32_t *>(d_work), work_stride, n1);
+        j1.in_bytes = (int64_t)n_chan * in_stride;
+        j1.out_u16 = 1;
+        j1.store_vec = 1;  // even stride, 4-byte aligned rows: pairs go out as dwords
+        j1.keep = d_keep;
+        j1.groups = n_sub;
+        j1.group_blocks = j1.tiles_t * j1.tiles_dm;
+        j1.group_delays = (int64_t)nc * m;
+        j1.group_in = (int64_t)m * in_stride;
+        j1.group_out = (int64_t)jn * work_stride * 2;
+        j1.group_keep = m;
+        // step two: one group per coarse DM over the subband rows
+        const int64_t sub_bytes = (int64_t)jn * work_stride * 2;  // one subband's rows
+        DedispJob j2 = make_dedisp_job(p2, d_delay2 + j0 * nf * n_sub, nf, n_sub,
+                                       reinterpret_cast<const uint8_t *>(d_work), sub_bytes,
+                                       d_dd + j0 * nf * dd_stride, dd_stride, n_out);
+        j2.in_u16 = 1;
+        j2.in_bytes = (int64_t)n_sub * sub_bytes;
+        j2.flush_every = 65535 / (255 * m);
+        j2.groups = jn;
+        j2.group_blocks = j2.tiles_t * j2.tiles_dm;
+        j2.group_delays = (int64_t)nf * n_sub;
+        j2.group_in = work_stride * 2;
+        j2.group_out = (int64_t)nf * dd_stride * 4;
+        const int64_t b1 = (int64_t)j1.group_blocks * n_sub, b2 = (int64_t)j2.group_blocks * jn;
+        if (b1 > 0x7fffffff || b2 > 0x7fffffff) return fail(AMBER_E_SHAPE, "subband grid too large");
+        if ((s = launch_dedisperse_jobs(p1, &j1, nullptr, 1, b1, lds1, stream)) != AMBER_OK) return s;
+        if ((s = launch_dedisperse_jobs(p2, &j2, nullptr, 1, b2, p2.lds_bytes, stream)) != AMBER_OK) return s;
+    }
+    return AMBER_OK;
+}
+
+}  // namespace amber
+
+extern "C" {
+
+amber_status amber_subband_dedisperse(const int32_t *d_delay1, const int32_t *d_delay2,
+                                      const amber_subband_info *info, const uint8_t *d_in, int64_t in_stride,
+                                      int64_t n_in, uint16_t *d_work, int64_t work_stride, int32_t *d_dd,
+                                      int64_t dd_stride, int64_t n_out, const uint8_t *d_keep,
+                                      const amber_tiles *tiles1, const amber_tiles *tiles2, void *stream)
+{
+    clear_error();
+    return subband_run(d_delay1, d_delay2, info, d_in, in_stride, n_in, d_work, work_stride, -1, d_dd, dd_stride,
+                       n_out, d_keep, tiles1, tiles2, (hipStream_t)stream);
 }
 
 }  // extern "C"
