@@ -30,16 +30,19 @@ if ROOT not in sys.path:
 
 # MI355X published / derived peaks
 HBM_PEAK_GBS = 8000.0
-# 32-bit VALU: 256 CUs x 128 lane-ops/clk x 2.4 GHz = 78.6 T lane-ops/s (the
-# published FP32 vector rate, 157.3 TFLOP/s, counts an FMA as two); the
+# 32-bit VALU issue: 256 CUs x 4 SIMDs x 16 lanes = 64 lane-ops per clock per
+# CU at 2.4 GHz = 39.3 T lane-ops/s (the published FP32 vector rate,
+# 157.3 TFLOP/s, is this times two for packed FP32 and two for an FMA).  The
 # dedispersion sums live in 16-bit halves, two per 32-bit add
-# -> 157.3 T sample-additions/s.
-ALU_PEAK_TOPS = 256 * 128 * 2.4e9 * 2 / 1e12
+# -> 78.6 T sample-additions/s.  Measured (bench.py --peaks): v_add_u32
+# 1.11 x this issue rate, three-operand and packed forms 0.85-0.90 x.
+VALU_LANES_PER_CLK = 64
+ALU_PEAK_TOPS = 256 * VALU_LANES_PER_CLK * 2.4e9 * 2 / 1e12
 
-# LDS: 128 B/clk/CU for the 32-bit read forms the dedispersion kernel issues
-# (ds_read_b32, ds_read2st64_b32; microbenchmarked at 110-125 B/clk/CU;
-# 64- and 128-bit reads reach about twice that but need aligned data)
-LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
+# LDS reads: 256 B/clk/CU (CDNA4 doubled CDNA3's 128) = 157.3 TB/s; measured
+# ds_read_b128 209 B/clk/CU, ds_read_b64 194, and the 32-bit forms the
+# dedispersion kernel issues (ds_read_b32, ds_read2st64_b32) 113-120
+LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12
 
 METRIC = "DM-trial·samples/s per GPU + % HBM roofline; GA tune time; p99 chunk latency"
 UNIT = "DM-trial·samples/s"
@@ -107,7 +110,7 @@ def cpu_baseline(x, n_in, wl, budget_rows: int):
             "sample": "first %d of %d DM trials of the 1536-ch beam (all %d samples, widths %s), median of 5 "
                       "passes (%.1f s each); single core: first %d trials, one pass (%.1f s)" % (
                           budget_rows, g.n_dm, wl.n_out, list(wl.widths), med["total_s"], rows1, one["total_s"]),
-            "cpu_model": _cpu_model(), "stages_s": med,
+            "cpu_model": _cpu_model(), "compiler": "gcc " + " ".join(oracle.BUILD_FLAGS), "stages_s": med,
             "single_core": {"value": rows1 * wl.n_out / one["total_s"], "cores": 1, "stages_s": one}}
 
 
@@ -955,7 +958,8 @@ def peaks_report():
     blocks = 2048
     res = {"blocks": blocks, "threads": 256, "clock_hz_assumed": clk, "cus": cus, "valu": {}, "lds": {}}
     names = ["v_add_u32", "v_add3_u32", "v_pk_add_u16", "v_lshl_or_b32", "v_fma_f64", "v_cvt_f64_i32",
-             "v_max3_i32"]
+             "v_max3_i32", "v_mad_u64_u32", "v_add_f64", "v_max_f64", "v_cvt_f32_i32", "v_mul_lo_u32",
+             "v_cvt_f64_u32", "v_sub_u32"]
     for kind, name in enumerate(names):
         r = ctypes.c_double()
         if lib.peaks_valu(kind, blocks, 20000, ctypes.c_void_p(out.data_ptr()), ctypes.byref(r)) != 0:

@@ -38,11 +38,15 @@ _lock = threading.Lock()
 _lib = None
 
 
+# No -march: the library may be built on one host and run on another.
+BUILD_FLAGS = ["-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared"]
+
+
 def build(force: bool = False) -> str:
-    """Compile amber_oracle.c into liboracle.so (gcc, -O2, OpenMP)."""
+    """Compile amber_oracle.c into liboracle.so (gcc with BUILD_FLAGS)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        cmd = ["gcc"] + BUILD_FLAGS + ["-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB

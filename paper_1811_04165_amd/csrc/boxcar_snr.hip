@@ -27,6 +27,7 @@
 
 #include <cfloat>
 #include <climits>
+#include <type_traits>
 
 namespace amber {
 namespace {
@@ -359,6 +360,521 @@ __global__ __launch_bounds__(MAXT) void integrate_snr_kernel(BoxJob single, cons
     }
 }
 
+// ---- fused boxcar + S/N over wavefront spans (sliding widths <= 64) --------
+//
+// One work-group per dedispersed row and W = blockDim / 64 wavefronts.  The
+// row's outputs are cut into blocks of 256 (64 lanes x 4); wavefront v sweeps
+// the blocks [v nb / W, (v + 1) nb / W) in order, on its own (no barrier
+// until the end).  Per step j:
+//  - block j + 1's samples (loaded two steps earlier, 16 B per lane,
+//    coalesced) are centred on c = dd[row][0], prefix-summed across the
+//    wavefront with DPP and written to a two-block LDS ring (slot (j + 1) & 1);
+//    the first entries of slot 0 are repeated after slot 1, so that no read
+//    wraps;
+//  - lane l reads the prefix at its 4 outputs u = 256 j + 4 l .. + 3 and, per
+//    width w, at u + w: box' = Q[u + w] - Q[u] is the width-w boxcar minus
+//    w c, exact in uint32 arithmetic because its true value fits int32;
+//  - per width it keeps the running maximum (3-input maxima of its 4 values),
+//    the block where that maximum last rose, and the sum of squares in int64
+//    (one 32 x 32 + 64-bit multiply-add per value).
+// The int64 sums are exact while (max width x max |centred sample|)^2 times
+// the values per lane stays below 2^62, and the wavefront's block totals
+// (which give the row's sum) while max |centred sample| < 2^23; each
+// wavefront tracks its largest centred sample, and a row that breaks either
+// bound has its sum and sums of squares recomputed after the sweep (no
+// dedispersed uint8 data of fewer than 32 896 channels comes near it).  The sum of box' over the row needs no per-output work: it is w T
+// minus head and tail terms, with T the centred row's sum.  After the sweep:
+// wavefront reductions, one barrier, then per width one wavefront finds the
+// first index of the maximum (its 4 candidate outputs in the earliest block
+// that reaches it, recomputed from dd), forms the mean from the closed form,
+// the variance and the S/N.
+
+constexpr int kSpanBlk = 256;
+constexpr int kSpanMaxW = 64;
+#ifndef SPAN_NB
+#define SPAN_NB 4
+#endif
+// reads of an odd block reach 256 + 4 * 63 + kSpanMaxW + 7 = 579 < 2 * 256 + kSpanDup
+constexpr int kSpanDup = 80;
+constexpr int kSpanRing = 2 * kSpanBlk + kSpanDup;  // dwords per wavefront
+
+struct SpanRes {
+    long long key;
+    double s2;
+};
+
+// Inclusive prefix sum across the wavefront (rows of 16 lanes with row_shr,
+// then row_bcast15 / row_bcast31 between rows).
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false); // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false); // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Raw samples of one lane in one block (block b: samples 256 b + 4 lane ..
+// + 3).  VEC (16-byte aligned rows of >= 4 samples): one 16-byte load from an
+// in-bounds address; a lane whose 4 samples are not all inside [0, n_out)
+// loads the row's first 16 bytes instead and re-reads its samples one by one
+// when the block is consumed.  Otherwise four dword loads from clamped
+// addresses.  Loads go through global-address-space pointers: flat loads
+// would also count against the LDS counter, and the compiler would then
+// drain every load in flight at each LDS wait.  Indices are 32-bit: the
+// launcher takes rows of fewer than 2^30 samples.
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) int32_t g_i32;
+typedef const __attribute__((address_space(1))) i32x4 g_i4;
+
+template <bool VEC>
+__device__ __forceinline__ i32x4 span_load(const int32_t *__restrict__ row, int blk, int n_out, int lane)
+{
+    const int t = blk * kSpanBlk + 4 * lane;
+    g_i32 *grow = (g_i32 *)row;
+    i32x4 v;
+    if (VEC) {
+        v = *(g_i4 *)(grow + (t + 4 <= n_out ? t : 0));
+    } else {
+        v.x = grow[t < n_out ? t : 0];
+        v.y = grow[t + 1 < n_out ? t + 1 : 0];
+        v.z = grow[t + 2 < n_out ? t + 2 : 0];
+        v.w = grow[t + 3 < n_out ? t + 3 : 0];
+    }
+    return v;
+}
+
+__device__ __forceinline__ int32_t max3i(int32_t a, int32_t b, int32_t c)
+{
+    int32_t r;
+    asm("v_max3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ int32_t min3i(int32_t a, int32_t b, int32_t c)
+{
+    int32_t r;
+    asm("v_min3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// Centres block `blk` on c, writes its prefix (starting at `base`) to ring
+// slot blk & 1, widens [xlo, xhi] to its centred samples and returns the
+// block's total (uint32, true value fits int32).
+template <bool VEC>
+__device__ __forceinline__ uint32_t span_put(uint32_t *ring, int blk, const i32x4 &r, const int32_t *__restrict__ row,
+                                             int n_out, int32_t c, uint32_t base, int lane, int32_t &xlo,
+                                             int32_t &xhi)
+{
+    const int t = blk * kSpanBlk + 4 * lane;
+    int32_t x[4];
+    if (VEC && (blk + 1) * kSpanBlk <= n_out) {  // the whole block lies in the row
+        x[0] = r.x - c; x[1] = r.y - c; x[2] = r.z - c; x[3] = r.w - c;
+    } else if (VEC) {
+        if (t + 4 <= n_out) {
+            x[0] = r.x - c; x[1] = r.y - c; x[2] = r.z - c; x[3] = r.w - c;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) x[e] = (t + e < n_out) ? ((g_i32 *)row)[t + e] - c : 0;
+        }
+    } else {
+        const int32_t v[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[e] = (t + e < n_out) ? v[e] - c : 0;
+    }
+    xlo = min3i(min3i(xlo, x[0], x[1]), x[2], x[3]);
+    xhi = max3i(max3i(xhi, x[0], x[1]), x[2], x[3]);
+    const uint32_t l0 = (uint32_t)x[0], l1 = l0 + (uint32_t)x[1], l2 = l1 + (uint32_t)x[2],
+                   l3 = l2 + (uint32_t)x[3];
+    const uint32_t incl = wave_scan_incl(l3);
+    const uint32_t ex = incl - l3 + base;
+    const u32x4 q = u32x4{ex, ex + l0, ex + l1, ex + l2};
+    const int slot = blk & 1;
+    *reinterpret_cast<u32x4 *>(ring + slot * kSpanBlk + 4 * lane) = q;
+    if (slot == 0 && lane < kSpanDup / 4) *reinterpret_cast<u32x4 *>(ring + 2 * kSpanBlk + 4 * lane) = q;
+    return (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+}
+
+// box'[e] = Q[b + e + w] - Q[b + e] for the lane's 4 outputs (A = Q[b .. b + 3]).
+template <int R>
+__device__ __forceinline__ void span_box(const uint32_t *ring, int b, int w, const u32x4 &A, int32_t (&x)[4])
+{
+    const int q = w - R;
+    const u32x4 g0 = *reinterpret_cast<const u32x4 *>(ring + b + q);
+    if (R == 0) {
+        x[0] = (int32_t)(g0.x - A.x); x[1] = (int32_t)(g0.y - A.y);
+        x[2] = (int32_t)(g0.z - A.z); x[3] = (int32_t)(g0.w - A.w);
+    } else {
+        const u32x4 g1 = *reinterpret_cast<const u32x4 *>(ring + b + q + 4);
+        const uint32_t g[8] = {g0.x, g0.y, g0.z, g0.w, g1.x, g1.y, g1.z, g1.w};
+        x[0] = (int32_t)(g[R] - A.x); x[1] = (int32_t)(g[R + 1] - A.y);
+        x[2] = (int32_t)(g[R + 2] - A.z); x[3] = (int32_t)(g[R + 3] - A.w);
+    }
+}
+
+template <bool POW2>
+__device__ __forceinline__ int span_width(const WidthSet &ws, int k)
+{
+    return POW2 ? (1 << k) : ws.w[k];
+}
+
+// One block of one width: the lane's 4 boxcar values x, all valid (TAIL
+// false) or valid below n_valid (TAIL true).
+template <bool TAIL>
+__device__ __forceinline__ void span_acc(const int32_t (&x)[4], int t0, int n_valid, int32_t &vmax, int32_t &jmax,
+                                         long long &s2, int32_t j)
+{
+    int32_t m;
+    if (!TAIL) {
+        m = max3i(max3i(vmax, x[0], x[1]), x[2], x[3]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s2 += (long long)x[e] * (long long)x[e];
+    } else {
+        m = vmax;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const bool ok = t0 + e < n_valid;
+            m = ok ? max(m, x[e]) : m;
+            const int32_t v = ok ? x[e] : 0;
+            s2 += (long long)v * (long long)v;
+        }
+    }
+    jmax = m != vmax ? j : jmax;
+    vmax = m;
+}
+
+// The statistics of block j for every width (its prefix and the next
+// block's are in the ring).
+template <int NW, bool POW2, bool TAIL>
+__device__ __forceinline__ void span_block(const uint32_t *ring, int j, int lane, const WidthSet &ws, int n_out,
+                                           int32_t (&vmax)[NW], int32_t (&jmax)[NW], long long (&s2)[NW])
+{
+    const int b = (j & 1) * kSpanBlk + 4 * lane;
+    const int t0 = j * kSpanBlk + 4 * lane;
+    if (POW2) {
+        // widths 1, 2, 4, ..: every window end lies in one of the groups of
+        // four at offsets 0, 4, 8, 16, ..; all of them are read before any is
+        // used, so that a step waits for LDS once (read one by one, each read
+        // would wait a full LDS latency)
+        constexpr int NG = NW < 3 ? 2 : NW - 1;
+        u32x4 G[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) G[g] = *reinterpret_cast<const u32x4 *>(ring + b + (g == 0 ? 0 : 2 << g));
+        __builtin_amdgcn_sched_barrier(0);
+        const u32x4 A = G[0];
+        const uint32_t lo[8] = {G[0].x, G[0].y, G[0].z, G[0].w, G[1].x, G[1].y, G[1].z, G[1].w};
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            int32_t x[4];
+            if (k < 2) {  // w = 1, 2: ends inside groups 0 and 1
+                const int w = 1 << k;
+                x[0] = (int32_t)(lo[w] - A.x); x[1] = (int32_t)(lo[w + 1] - A.y);
+                x[2] = (int32_t)(lo[w + 2] - A.z); x[3] = (int32_t)(lo[w + 3] - A.w);
+            } else {      // w = 4 << (k - 2): group k - 1
+                const u32x4 E = G[k - 1];
+                x[0] = (int32_t)(E.x - A.x); x[1] = (int32_t)(E.y - A.y);
+                x[2] = (int32_t)(E.z - A.z); x[3] = (int32_t)(E.w - A.w);
+            }
+            span_acc<TAIL>(x, t0, n_out - (1 << k) + 1, vmax[k], jmax[k], s2[k], j);
+        }
+        return;
+    }
+    const u32x4 A = *reinterpret_cast<const u32x4 *>(ring + b);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const int w = span_width<POW2>(ws, k);
+        int32_t x[4];
+        switch (w & 3) {
+        case 0: span_box<0>(ring, b, w, A, x); break;
+        case 1: span_box<1>(ring, b, w, A, x); break;
+        case 2: span_box<2>(ring, b, w, A, x); break;
+        default: span_box<3>(ring, b, w, A, x); break;
+        }
+        span_acc<TAIL>(x, t0, n_out - w + 1, vmax[k], jmax[k], s2[k], j);
+    }
+}
+
+// Whole-wavefront reductions with DPP (quad permutes, row mirrors, then
+// row_bcast15 / row_bcast31 into the last row); the result is read from lane
+// 63 and is the same in every lane.  64-bit values move as two halves.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v, uint64_t identity)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)identity, (int)(uint32_t)v, CTRL, ROWS,
+                                                               0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(identity >> 32), (int)(uint32_t)(v >> 32),
+                                                               CTRL, ROWS, 0xf, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t lane63(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ long long wave_max_ll(long long v)
+{
+    const uint64_t id = (uint64_t)LLONG_MIN;
+    auto mx = [](long long a, uint64_t b) { return a > (long long)b ? a : (long long)b; };
+    v = mx(v, dpp64<0xb1, 0xf>((uint64_t)v, id));   // quad_perm [1,0,3,2]
+    v = mx(v, dpp64<0x4e, 0xf>((uint64_t)v, id));   // quad_perm [2,3,0,1]
+    v = mx(v, dpp64<0x141, 0xf>((uint64_t)v, id));  // row_half_mirror
+    v = mx(v, dpp64<0x140, 0xf>((uint64_t)v, id));  // row_mirror
+    v = mx(v, dpp64<0x142, 0xa>((uint64_t)v, id));  // row_bcast:15
+    v = mx(v, dpp64<0x143, 0xc>((uint64_t)v, id));  // row_bcast:31
+    return (long long)lane63((uint64_t)v);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+    auto add = [](double a, uint64_t b) { return a + __longlong_as_double((long long)b); };
+    auto bits = [](double a) { return (uint64_t)__double_as_longlong(a); };
+    v = add(v, dpp64<0xb1, 0xf>(bits(v), 0));
+    v = add(v, dpp64<0x4e, 0xf>(bits(v), 0));
+    v = add(v, dpp64<0x141, 0xf>(bits(v), 0));
+    v = add(v, dpp64<0x140, 0xf>(bits(v), 0));
+    v = add(v, dpp64<0x142, 0xa>(bits(v), 0));
+    v = add(v, dpp64<0x143, 0xc>(bits(v), 0));
+    return __longlong_as_double((long long)lane63(bits(v)));
+}
+
+__device__ __forceinline__ long long wave_sum_ll(long long v)
+{
+    v += (long long)dpp64<0xb1, 0xf>((uint64_t)v, 0);
+    v += (long long)dpp64<0x4e, 0xf>((uint64_t)v, 0);
+    v += (long long)dpp64<0x141, 0xf>((uint64_t)v, 0);
+    v += (long long)dpp64<0x140, 0xf>((uint64_t)v, 0);
+    v += (long long)dpp64<0x142, 0xa>((uint64_t)v, 0);
+    v += (long long)dpp64<0x143, 0xc>((uint64_t)v, 0);
+    return (long long)lane63((uint64_t)v);
+}
+
+// NW: the exact number of widths; POW2: widths are 1, 2, 4, ... 2^(NW-1).
+constexpr int NB = SPAN_NB;
+template <int NW, bool POW2, bool VEC>
+__global__ __launch_bounds__(1024) void span_snr_kernel(BoxJob single, const BoxJob *__restrict__ jobs, int n_jobs,
+                                                        WidthSet ws)
+{
+    extern __shared__ uint4 lds4[];
+    // the wavefront index is uniform: keep it (and the span bounds, the block
+    // counter and every branch on them) in scalar registers
+    const int W = blockDim.x >> 6, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    uint32_t *ring = reinterpret_cast<uint32_t *>(lds4) + wave * kSpanRing;
+    SpanRes *res = reinterpret_cast<SpanRes *>(reinterpret_cast<uint32_t *>(lds4) + W * kSpanRing);
+    long long *tres = reinterpret_cast<long long *>(res + W * NW);
+    int *flags = reinterpret_cast<int *>(tres + W);  // per wavefront: its sums of squares may have overflowed
+
+    int i = blockIdx.x;
+    BoxJob job = single;
+    if (jobs) {
+        int j = 0;
+        while (j + 1 < n_jobs && jobs[j + 1].row_start <= i) ++j;
+        job = jobs[j];
+        i -= job.row_start;
+    }
+    const int n_out = (int)job.n_out;
+    const int32_t *__restrict__ row = job.dd + (size_t)i * job.dd_stride;
+    const int32_t c = *(g_i32 *)row;
+    // the row's first and last 64 samples (for the boxcar sums' head and tail
+    // terms), loaded now and used after the sweep
+    const int32_t head = lane < n_out ? ((g_i32 *)row)[lane] : 0;
+    const int32_t tail = n_out - 1 - lane >= 0 ? ((g_i32 *)row)[n_out - 1 - lane] : 0;
+    int maxw = 1;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) maxw = max(maxw, span_width<POW2>(ws, k));
+    const int n_min = n_out - maxw + 1;  // outputs below it are valid for every width
+
+    int32_t vmax[NW], jmax[NW];
+    long long s2[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        vmax[k] = INT32_MIN;
+        jmax[k] = -1;
+        s2[k] = 0;
+    }
+    long long tsum = 0;
+    int32_t xlo = 0, xhi = 0;
+    bool overflow = false;
+
+    const int nb = (n_out + kSpanBlk - 1) / kSpanBlk;
+    const int jb = (int)((uint32_t)nb * (uint32_t)wave / (uint32_t)W),
+              je = (int)((uint32_t)nb * (uint32_t)(wave + 1) / (uint32_t)W);
+    if (jb < je) {
+        // blocks before j_tail have every output valid for every width; the
+        // others (at most two, at the row's end) take the masked statistics
+        const int j_tail = min(max(n_min / kSpanBlk, jb), je);
+        uint32_t base = 0;
+        // Main part, blocks [jb, j_tail): NB block buffers.  While block j
+        // is summed, blocks j + 1 (its windows' lookahead, put into the ring
+        // first) .. j + NB - 1 are loaded and j + NB is being loaded.  The
+        // loop is unrolled NB times so that buffers are never copied (a copy
+        // would wait for the load in flight); it starts NB - 1 steps early at
+        // most (dummy steps: loads and prefix writes of earlier blocks, no
+        // statistics), so that its length is a multiple of NB.
+        if (jb < j_tail) {
+            const int r = (NB - (j_tail - jb) % NB) % NB;
+            int j = jb - r;
+            i32x4 buf[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) buf[u] = span_load<VEC>(row, max(j + u, 0), n_out, lane);
+            base = span_put<VEC>(ring, j, buf[0], row, n_out, c, 0u, lane, xlo, xhi);
+            if (j >= jb) tsum += (int32_t)base;
+            for (; j < j_tail; j += NB) {
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    const int jj = j + u;
+                    const int jl = jj + NB <= je ? jj + NB : jj + 1;  // past the lookahead: a harmless reload
+                    buf[u] = span_load<VEC>(row, max(jl, 0), n_out, lane);
+                    const uint32_t tot =
+                        span_put<VEC>(ring, jj + 1, buf[(u + 1) % NB], row, n_out, c, base, lane, xlo, xhi);
+                    base += tot;
+                    if (jj + 1 >= jb && jj + 1 < je) tsum += (int32_t)tot;
+                    wave_sync_lds();
+                    if (jj >= jb) span_block<NW, POW2, false>(ring, jj, lane, ws, n_out, vmax, jmax, s2);
+                    wave_sync_lds();
+                }
+            }
+        } else {
+            base = span_put<VEC>(ring, jb, span_load<VEC>(row, jb, n_out, lane), row, n_out, c, 0u, lane, xlo,
+                                 xhi);
+            tsum += (int32_t)base;
+        }
+        // tail blocks: block j + 1 loaded and put, then block j's masked statistics
+        for (int j = j_tail; j < je; ++j) {
+            const uint32_t tot = span_put<VEC>(ring, j + 1, span_load<VEC>(row, j + 1, n_out, lane), row, n_out, c,
+                                               base, lane, xlo, xhi);
+            base += tot;
+            if (j + 1 < je) tsum += (int32_t)tot;
+            wave_sync_lds();
+            span_block<NW, POW2, true>(ring, j, lane, ws, n_out, vmax, jmax, s2);
+            wave_sync_lds();
+        }
+        // exactness: a block's total (256 centred samples) fits int32 while
+        // max |x'| < 2^23; the int64 sums of squares while (maxw max |x'|)^2
+        // times the 4 (je - jb) values per lane and width stays below 2^62
+        const int32_t xm = (int32_t)wave_max_ll((long long)max(max(xhi, -xlo), 0));
+        const double bound = (double)maxw * (double)xm;
+        overflow = xm >= (1 << 23) || bound * bound * (4.0 * (double)(je - jb)) >= 4.6e18;
+    }
+
+    // wavefront totals: per width (max, earliest 4-output group) and sum of squares
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const int u0 = jmax[k] >= 0 ? jmax[k] * kSpanBlk + 4 * lane : 0;
+        const long long key = wave_max_ll(pack_key(vmax[k], u0));
+        const double s = wave_sum_d((double)s2[k]);
+        if (lane == 0) res[wave * NW + k] = SpanRes{key, s};
+    }
+    if (lane == 0) {
+        tres[wave] = tsum;
+        flags[wave] = overflow ? 1 : 0;
+    }
+    __syncthreads();
+    bool redo = false;
+    long long T = 0;
+    for (int v = 0; v < W; ++v) {
+        redo = redo || flags[v] != 0;
+        T += tres[v];
+    }
+    if (redo) {
+        // the centred row's sum again, in int64
+        long long a = 0;
+        for (int t = lane; t < n_out; t += 64) a += (long long)row[t] - c;
+        T = wave_sum_ll(a);
+    }
+    // this wavefront's widths k = wave, wave + W, ..: totals over the
+    // wavefronts (in a fixed order), then the loads that find the first index
+    // of each maximum, all issued before any is used
+    long long key[NW];
+    double s2t[NW];
+    int32_t v1[NW], v2[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        if (k % W != wave) continue;
+        key[k] = LLONG_MIN;
+        s2t[k] = 0.0;
+        for (int v = 0; v < W; ++v) {
+            const SpanRes r = res[v * NW + k];
+            key[k] = r.key > key[k] ? r.key : key[k];
+            s2t[k] += r.s2;
+        }
+        const int u0 = (int)(0xffffffffu - (uint32_t)(key[k] & 0xffffffffll));
+        v1[k] = (u0 + lane < n_out) ? row[u0 + lane] : 0;
+        v2[k] = (lane < 3 && u0 + 64 + lane < n_out) ? row[u0 + 64 + lane] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        if (k % W != wave) continue;
+        const int w = span_width<POW2>(ws, k);
+        const int N = n_out - w + 1;
+        double s = s2t[k];
+        if (redo) {
+            // sums of squares again in FP64: lane l takes a contiguous run
+            // of outputs and slides its window along it
+            const int C = (N + 63) / 64, t0 = lane * C, t1 = min(N, t0 + C);
+            double acc = 0.0;
+            if (t0 < t1) {
+                long long bx = 0;
+                for (int m = 0; m < w; ++m) bx += (long long)row[t0 + m] - c;
+                acc = (double)bx * (double)bx;
+                for (int t = t0 + 1; t < t1; ++t) {
+                    bx += (long long)row[t + w - 1] - (long long)row[t - 1];
+                    acc += (double)bx * (double)bx;
+                }
+            }
+            s = wave_sum_d(acc);
+        }
+        const int32_t vm = (int32_t)(key[k] >> 32);
+        const int u0 = (int)(0xffffffffu - (uint32_t)(key[k] & 0xffffffffll));
+        // head and tail outputs of the boxcar sum's weights below w
+        double corr = 0.0;
+        if (lane <= w - 2) {
+            const int th = lane, tt = n_out - 1 - lane;
+            if (th < n_out) {
+                const int cnt = min(th, N - 1) - max(0, th - w + 1) + 1;
+                corr += (double)(w - cnt) * (double)(head - c);
+            }
+            if (tt >= w - 1) {
+                const int cnt = min(tt, N - 1) - max(0, tt - w + 1) + 1;
+                corr += (double)(w - cnt) * (double)(tail - c);
+            }
+        }
+        corr = wave_sum_d(corr);
+        const double s1 = (double)w * (double)T - corr;
+        // first index of the maximum among outputs u0 .. u0 + 3
+        const uint32_t p1 = wave_scan_incl((uint32_t)v1[k]), p2 = wave_scan_incl((uint32_t)v2[k]);
+        const uint32_t p64 = (uint32_t)__builtin_amdgcn_readlane((int)p1, 63);
+        auto S = [&](int m) -> uint32_t {
+            if (m == 0) return 0u;
+            if (m <= 64) return (uint32_t)__builtin_amdgcn_readlane((int)p1, m - 1);
+            return p64 + (uint32_t)__builtin_amdgcn_readlane((int)p2, m - 65);
+        };
+        const uint32_t want = (uint32_t)vm + (uint32_t)w * (uint32_t)c;
+        int tstar = u0;
+        for (int e = 3; e >= 0; --e)
+            if (u0 + e < N && S(e + w) - S(e) == want) tstar = u0 + e;
+        if (lane == 0) {
+            const double m1 = s1 / (double)N;
+            double var = s / (double)N - m1 * m1;
+            var = var > 0.0 ? var : 0.0;
+            const double sigma = sqrt(var);
+            job.snr[(size_t)k * job.n_dm + i] = sigma > 0.0 ? (float)(((double)vm - m1) / sigma) : 0.0f;
+            if (job.peak) job.peak[(size_t)k * job.n_dm + i] = tstar;
+        }
+    }
+}
+
 // ---- materialised boxcar: one work-group per (chunk, row) ------------------
 __global__ __launch_bounds__(1024) void integrate_kernel(const int32_t *__restrict__ dd, int n_dm, int64_t dd_stride,
                                                          int64_t n_out, WidthSet ws, int chunk, int halo, int vec_ok,
@@ -463,18 +979,80 @@ BoxJob make_box_job(const int32_t *d_dd, int n_dm, int64_t dd_stride, int64_t n_
     j.snr = d_snr;
     j.peak = d_peak;
     j.n_dm = n_dm;
-    j.vec_ok = (dd_stride % 4 == 0) && (((uintptr_t)d_dd & 15) == 0);
+    // 16-byte row loads: aligned rows, and at least 4 samples (the span kernel
+    // reads a row's first 16 bytes in place of a load past its end)
+    j.vec_ok = (dd_stride % 4 == 0) && (((uintptr_t)d_dd & 15) == 0) && n_out >= 4;
     j.row_start = 0;
     return j;
 }
 
+namespace {
+
+// The span kernel: sliding widths up to kSpanMaxW, at most 8 per launch.
+template <int NW>
+void launch_span_nw(bool pow2, bool vec, dim3 grid, dim3 block, size_t lds, hipStream_t stream, const BoxJob &one,
+                    const BoxJob *d_jobs, int n_jobs, const WidthSet &ws)
+{
+    if (pow2) {
+        if (vec) hipLaunchKernelGGL((span_snr_kernel<NW, true, true>), grid, block, lds, stream, one, d_jobs, n_jobs, ws);
+        else hipLaunchKernelGGL((span_snr_kernel<NW, true, false>), grid, block, lds, stream, one, d_jobs, n_jobs, ws);
+    } else {
+        if (vec) hipLaunchKernelGGL((span_snr_kernel<NW, false, true>), grid, block, lds, stream, one, d_jobs, n_jobs, ws);
+        else hipLaunchKernelGGL((span_snr_kernel<NW, false, false>), grid, block, lds, stream, one, d_jobs, n_jobs, ws);
+    }
+}
+
+amber_status launch_span_snr(const BoxcarPlan &p, const BoxJob *single, const BoxJob *d_jobs, int n_jobs,
+                             int64_t n_rows, const int32_t *widths, int n_widths, bool vec, hipStream_t stream)
+{
+    WidthSet ws{};
+    bool pow2 = true;
+    for (int k = 0; k < n_widths; ++k) {
+        ws.w[k] = widths[k];
+        pow2 = pow2 && widths[k] == (1 << k);
+    }
+    ws.n = n_widths;
+    const int W = p.threads / kWave;
+    const size_t lds = (size_t)W * kSpanRing * 4 + (size_t)W * n_widths * sizeof(SpanRes) +
+                       (size_t)W * sizeof(long long) + (size_t)W * sizeof(int);
+    const BoxJob one = single ? *single : BoxJob{};
+    const dim3 grid((unsigned)n_rows), block(p.threads);
+    switch (n_widths) {
+    case 1: launch_span_nw<1>(pow2, vec, grid, block, lds, stream, one, d_jobs, n_jobs, ws); break;
+    case 2: launch_span_nw<2>(pow2, vec, grid, block, lds, stream, one, d_jobs, n_jobs, ws); break;
+    case 3: launch_span_nw<3>(pow2, vec, grid, block, lds, stream, one, d_jobs, n_jobs, ws); break;
+    case 4: launch_span_nw<4>(pow2, vec, grid, block, lds, stream, one, d_jobs, n_jobs, ws); break;
+    case 5: launch_span_nw<5>(pow2, vec, grid, block, lds, stream, one, d_jobs, n_jobs, ws); break;
+    case 6: launch_span_nw<6>(pow2, vec, grid, block, lds, stream, one, d_jobs, n_jobs, ws); break;
+    case 7: launch_span_nw<7>(pow2, vec, grid, block, lds, stream, one, d_jobs, n_jobs, ws); break;
+    case 8: launch_span_nw<8>(pow2, vec, grid, block, lds, stream, one, d_jobs, n_jobs, ws); break;
+    default: return fail(AMBER_E_CONFIG, "span kernel takes 1 to 8 widths, got %d", n_widths);
+    }
+    AMBER_HIP(hipGetLastError(), "integrate_snr (span) launch");
+    return AMBER_OK;
+}
+
+}  // namespace
+
+bool span_snr_applies(const int32_t *widths, int n_widths, int decimate)
+{
+    if (decimate || n_widths < 1 || n_widths > 8) return false;
+    for (int k = 0; k < n_widths; ++k)
+        if (widths[k] > kSpanMaxW) return false;
+    return true;
+}
+
 amber_status launch_integrate_snr_jobs(const BoxcarPlan &p, const amber_tiles &t, const BoxJob *single,
                                        const BoxJob *d_jobs, int n_jobs, int64_t n_rows, const int32_t *widths,
-                                       int n_widths, hipStream_t stream, int decimate)
+                                       int n_widths, hipStream_t stream, int decimate, int all_vec)
 {
     amber_status s = check_chunk(p);
     if (s != AMBER_OK) return s;
     if (n_rows > 0x7fffffff) return fail(AMBER_E_SHAPE, "too many rows (%lld)", (long long)n_rows);
+    if (span_snr_applies(widths, n_widths, decimate)) {
+        const bool vec = single ? single->vec_ok != 0 : all_vec > 0;
+        return launch_span_snr(p, single, d_jobs, n_jobs, n_rows, widths, n_widths, vec, stream);
+    }
     // One beam with more than 8 series: passes of at most 8 series through
     // the 8-series kernel (each pass re-reads the rows, but the statistics of
     // 16 series per work-item need registers enough to halve the resident
@@ -487,7 +1065,7 @@ amber_status launch_integrate_snr_jobs(const BoxcarPlan &p, const amber_tiles &t
             amber_tiles tk = t;
             const int nk = n_widths - k0 < 8 ? n_widths - k0 : 8;
             for (int k = 0; k < nk; ++k) tk.boxcar_step[k] = t.boxcar_step[k0 + k];
-            if ((s = launch_integrate_snr_jobs(p, tk, &j, nullptr, 1, n_rows, widths + k0, nk, stream, decimate)) !=
+            if ((s = launch_integrate_snr_jobs(p, tk, &j, nullptr, 1, n_rows, widths + k0, nk, stream, decimate, -1)) !=
                 AMBER_OK)
                 return s;
         }

@@ -82,9 +82,11 @@ amber_status LaunchSet::launch(const void *d_tables, hipStream_t stream) const
         p += g.jobs.size() * sizeof(DedispJob);
     }
     for (const auto &g : b_) {
+        int all_vec = 1;
+        for (const auto &j : g.jobs) all_vec &= j.vec_ok ? 1 : 0;
         amber_status s = launch_integrate_snr_jobs(g.plan, g.tiles, nullptr, reinterpret_cast<const BoxJob *>(p),
                                                    (int)g.jobs.size(), g.n_rows, g.widths.data(),
-                                                   (int)g.widths.size(), stream);
+                                                   (int)g.widths.size(), stream, 0, all_vec);
         if (s != AMBER_OK) return s;
         p += g.jobs.size() * sizeof(BoxJob);
     }

@@ -22,11 +22,15 @@ __global__ __launch_bounds__(256) void valu_kernel(uint32_t *out, uint32_t seed,
 {
     uint32_t a[CHAINS];
     double f[CHAINS];
+    uint64_t u[CHAINS];
+    float g[CHAINS];
     const uint32_t b = seed ^ blockIdx.x, c = seed * 3u + threadIdx.x;
 #pragma unroll
     for (int j = 0; j < CHAINS; ++j) {
         a[j] = threadIdx.x * 7u + j * seed;
         f[j] = (double)a[j];
+        u[j] = a[j];
+        g[j] = 0.f;
     }
     const double fb = (double)b * 1e-9;
     for (int i = 0; i < iters; ++i) {
@@ -39,11 +43,18 @@ __global__ __launch_bounds__(256) void valu_kernel(uint32_t *out, uint32_t seed,
             if (KIND == 4) asm volatile("v_fma_f64 %0, %0, %1, %1" : "+v"(f[j]) : "v"(fb));
             if (KIND == 5) asm volatile("v_cvt_f64_i32 %0, %1" : "=v"(f[j]) : "v"(a[j] + (uint32_t)i));
             if (KIND == 6) asm volatile("v_max3_i32 %0, %0, %1, %2" : "+v"(a[j]) : "v"(b), "v"(c));
+            if (KIND == 7) asm volatile("v_mad_u64_u32 %0, vcc, %1, %2, %0" : "+v"(u[j]) : "v"(a[j]), "v"(b) : "vcc");
+            if (KIND == 8) asm volatile("v_add_f64 %0, %0, %1" : "+v"(f[j]) : "v"(fb));
+            if (KIND == 9) asm volatile("v_max_f64 %0, %0, %1" : "+v"(f[j]) : "v"(fb));
+            if (KIND == 10) asm volatile("v_cvt_f32_i32 %0, %1" : "=v"(g[j]) : "v"(a[j] + (uint32_t)i));
+            if (KIND == 11) asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(a[j]) : "v"(b));
+            if (KIND == 12) asm volatile("v_cvt_f64_u32 %0, %1" : "=v"(f[j]) : "v"(a[j] + (uint32_t)i));
+            if (KIND == 13) asm volatile("v_sub_u32 %0, %1, %0" : "+v"(a[j]) : "v"(b));
         }
     }
     uint32_t s = 0;
 #pragma unroll
-    for (int j = 0; j < CHAINS; ++j) s ^= a[j] ^ (uint32_t)f[j];
+    for (int j = 0; j < CHAINS; ++j) s ^= a[j] ^ (uint32_t)f[j] ^ (uint32_t)u[j] ^ (uint32_t)g[j];
     if (s == 0x9e3779b9u) out[blockIdx.x] = s;
 }
 
@@ -134,7 +145,9 @@ int timed(F launch, float *ms)
 extern "C" {
 
 // Kinds: 0 v_add_u32, 1 v_add3_u32, 2 v_pk_add_u16, 3 v_lshl_or_b32,
-// 4 v_fma_f64, 5 v_cvt_f64_i32, 6 v_max3_i32.  Writes the launch's
+// 4 v_fma_f64, 5 v_cvt_f64_i32, 6 v_max3_i32, 7 v_mad_u64_u32, 8 v_add_f64,
+// 9 v_max_f64, 10 v_cvt_f32_i32, 11 v_mul_lo_u32, 12 v_cvt_f64_u32,
+// 13 v_sub_u32.  Writes the launch's
 // wave-instructions per second of the timed form.  `out` is a device buffer
 // of >= blocks uint32.
 int peaks_valu(int kind, int blocks, int iters, uint32_t *out, double *winst_per_s)
@@ -152,6 +165,13 @@ int peaks_valu(int kind, int blocks, int iters, uint32_t *out, double *winst_per
     case 4: go(valu_kernel<4>); break;
     case 5: go(valu_kernel<5>); break;
     case 6: go(valu_kernel<6>); break;
+    case 7: go(valu_kernel<7>); break;
+    case 8: go(valu_kernel<8>); break;
+    case 9: go(valu_kernel<9>); break;
+    case 10: go(valu_kernel<10>); break;
+    case 11: go(valu_kernel<11>); break;
+    case 12: go(valu_kernel<12>); break;
+    case 13: go(valu_kernel<13>); break;
     default: return -1;
     }
     if (rc) return rc;
