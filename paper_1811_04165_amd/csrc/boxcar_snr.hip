@@ -436,20 +436,26 @@ typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) int32_t g_i32;
 typedef const __attribute__((address_space(1))) i32x4 g_i4;
 
-template <bool VEC>
-__device__ __forceinline__ i32x4 span_load(const int32_t *__restrict__ row, int blk, int n_out, int lane)
+// Buffer loads: a row is a buffer of n_out dwords whose reads past its end
+// return zero (the hardware's range check), so no load needs its address
+// clamped and the offsets are a fixed per-lane part plus a scalar block part.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const int32_t *row, int n_out)
 {
-    const int t = blk * kSpanBlk + 4 * lane;
-    g_i32 *grow = (g_i32 *)row;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t *>(row), (short)0, n_out * 4, 0x00020000);
+}
+
+template <bool VEC>
+__device__ __forceinline__ i32x4 span_load(__amdgpu_buffer_rsrc_t rs, int blk, int lane)
+{
+    // the whole byte offset in the vector operand, which the range check
+    // covers (blk >= 0; rows of fewer than 2^29 samples)
+    const int off = blk * (kSpanBlk * 4) + 16 * lane;
+    if (VEC) return __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
     i32x4 v;
-    if (VEC) {
-        v = *(g_i4 *)(grow + (t + 4 <= n_out ? t : 0));
-    } else {
-        v.x = grow[t < n_out ? t : 0];
-        v.y = grow[t + 1 < n_out ? t + 1 : 0];
-        v.z = grow[t + 2 < n_out ? t + 2 : 0];
-        v.w = grow[t + 3 < n_out ? t + 3 : 0];
-    }
+    v.x = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+    v.y = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4, 0, 0);
+    v.z = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 8, 0, 0);
+    v.w = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 12, 0, 0);
     return v;
 }
 
@@ -686,6 +692,7 @@ __global__ __launch_bounds__(1024) void span_snr_kernel(BoxJob single, const Box
     const int n_out = (int)job.n_out;
     const int32_t *__restrict__ row = job.dd + (size_t)i * job.dd_stride;
     const int32_t c = *(g_i32 *)row;
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc(row, n_out);
     // the row's first and last 64 samples (for the boxcar sums' head and tail
     // terms), loaded now and used after the sweep
     const int32_t head = lane < n_out ? ((g_i32 *)row)[lane] : 0;
@@ -727,15 +734,16 @@ __global__ __launch_bounds__(1024) void span_snr_kernel(BoxJob single, const Box
             int j = jb - r;
             i32x4 buf[NB];
 #pragma unroll
-            for (int u = 0; u < NB; ++u) buf[u] = span_load<VEC>(row, max(j + u, 0), n_out, lane);
+            for (int u = 0; u < NB; ++u) buf[u] = span_load<VEC>(rs, max(j + u, 0), lane);
             base = span_put<VEC>(ring, j, buf[0], row, n_out, c, 0u, lane, xlo, xhi);
             if (j >= jb) tsum += (int32_t)base;
             for (; j < j_tail; j += NB) {
 #pragma unroll
                 for (int u = 0; u < NB; ++u) {
                     const int jj = j + u;
-                    const int jl = jj + NB <= je ? jj + NB : jj + 1;  // past the lookahead: a harmless reload
-                    buf[u] = span_load<VEC>(row, max(jl, 0), n_out, lane);
+                    // blocks past the lookahead are loaded and never used
+                    // (past the row's end the loads return zeros)
+                    buf[u] = span_load<VEC>(rs, max(jj + NB, 0), lane);
                     const uint32_t tot =
                         span_put<VEC>(ring, jj + 1, buf[(u + 1) % NB], row, n_out, c, base, lane, xlo, xhi);
                     base += tot;
@@ -746,13 +754,13 @@ __global__ __launch_bounds__(1024) void span_snr_kernel(BoxJob single, const Box
                 }
             }
         } else {
-            base = span_put<VEC>(ring, jb, span_load<VEC>(row, jb, n_out, lane), row, n_out, c, 0u, lane, xlo,
+            base = span_put<VEC>(ring, jb, span_load<VEC>(rs, jb, lane), row, n_out, c, 0u, lane, xlo,
                                  xhi);
             tsum += (int32_t)base;
         }
         // tail blocks: block j + 1 loaded and put, then block j's masked statistics
         for (int j = j_tail; j < je; ++j) {
-            const uint32_t tot = span_put<VEC>(ring, j + 1, span_load<VEC>(row, j + 1, n_out, lane), row, n_out, c,
+            const uint32_t tot = span_put<VEC>(ring, j + 1, span_load<VEC>(rs, j + 1, lane), row, n_out, c,
                                                base, lane, xlo, xhi);
             base += tot;
             if (j + 1 < je) tsum += (int32_t)tot;
@@ -1034,9 +1042,9 @@ amber_status launch_span_snr(const BoxcarPlan &p, const BoxJob *single, const Bo
 
 }  // namespace
 
-bool span_snr_applies(const int32_t *widths, int n_widths, int decimate)
+bool span_snr_applies(const int32_t *widths, int n_widths, int decimate, int64_t max_n_out)
 {
-    if (decimate || n_widths < 1 || n_widths > 8) return false;
+    if (decimate || n_widths < 1 || n_widths > 8 || max_n_out >= ((int64_t)1 << 29)) return false;
     for (int k = 0; k < n_widths; ++k)
         if (widths[k] > kSpanMaxW) return false;
     return true;
@@ -1044,12 +1052,13 @@ bool span_snr_applies(const int32_t *widths, int n_widths, int decimate)
 
 amber_status launch_integrate_snr_jobs(const BoxcarPlan &p, const amber_tiles &t, const BoxJob *single,
                                        const BoxJob *d_jobs, int n_jobs, int64_t n_rows, const int32_t *widths,
-                                       int n_widths, hipStream_t stream, int decimate, int all_vec)
+                                       int n_widths, hipStream_t stream, int decimate, int all_vec,
+                                       int64_t max_n_out)
 {
     amber_status s = check_chunk(p);
     if (s != AMBER_OK) return s;
     if (n_rows > 0x7fffffff) return fail(AMBER_E_SHAPE, "too many rows (%lld)", (long long)n_rows);
-    if (span_snr_applies(widths, n_widths, decimate)) {
+    if (span_snr_applies(widths, n_widths, decimate, single ? single->n_out : max_n_out)) {
         const bool vec = single ? single->vec_ok != 0 : all_vec > 0;
         return launch_span_snr(p, single, d_jobs, n_jobs, n_rows, widths, n_widths, vec, stream);
     }
@@ -1065,7 +1074,7 @@ amber_status launch_integrate_snr_jobs(const BoxcarPlan &p, const amber_tiles &t
             amber_tiles tk = t;
             const int nk = n_widths - k0 < 8 ? n_widths - k0 : 8;
             for (int k = 0; k < nk; ++k) tk.boxcar_step[k] = t.boxcar_step[k0 + k];
-            if ((s = launch_integrate_snr_jobs(p, tk, &j, nullptr, 1, n_rows, widths + k0, nk, stream, decimate, -1)) !=
+            if ((s = launch_integrate_snr_jobs(p, tk, &j, nullptr, 1, n_rows, widths + k0, nk, stream, decimate, -1, j.n_out)) !=
                 AMBER_OK)
                 return s;
         }

@@ -126,13 +126,15 @@ amber_status launch_dedisperse_jobs(const DedispPlan &p, const DedispJob *single
 BoxJob make_box_job(const int32_t *d_dd, int n_dm, int64_t dd_stride, int64_t n_out, float *d_snr, int32_t *d_peak);
 // decimate != 0: the widths are decimation factors (see amber_downsample_snr).
 // all_vec: with a job table, 1 when every job's rows allow 16-byte loads
-// (BoxJob::vec_ok), else 0; ignored with a single job.
+// (BoxJob::vec_ok), else 0; max_n_out: with a job table, the longest row.
+// Both are ignored with a single job.
 amber_status launch_integrate_snr_jobs(const BoxcarPlan &p, const amber_tiles &t, const BoxJob *single,
                                        const BoxJob *d_jobs, int n_jobs, int64_t n_rows, const int32_t *widths,
-                                       int n_widths, hipStream_t stream, int decimate = 0, int all_vec = 0);
-// Sliding widths that the span kernel serves (at most 8, each <= 64): it
-// needs no chunk length, so snr_threads is free of the halo constraint.
-bool span_snr_applies(const int32_t *widths, int n_widths, int decimate);
+                                       int n_widths, hipStream_t stream, int decimate = 0, int all_vec = 0,
+                                       int64_t max_n_out = 0);
+// Sliding widths and rows that the span kernel serves (at most 8 widths,
+// each <= 64; rows of fewer than 2^29 samples).
+bool span_snr_applies(const int32_t *widths, int n_widths, int decimate, int64_t max_n_out);
 
 // Jobs of several beams grouped into as few launches as their launch shapes
 // allow.  Dedispersion jobs with the same tile genes share a launch (the

@@ -83,10 +83,14 @@ amber_status LaunchSet::launch(const void *d_tables, hipStream_t stream) const
     }
     for (const auto &g : b_) {
         int all_vec = 1;
-        for (const auto &j : g.jobs) all_vec &= j.vec_ok ? 1 : 0;
+        int64_t max_n_out = 0;
+        for (const auto &j : g.jobs) {
+            all_vec &= j.vec_ok ? 1 : 0;
+            max_n_out = j.n_out > max_n_out ? j.n_out : max_n_out;
+        }
         amber_status s = launch_integrate_snr_jobs(g.plan, g.tiles, nullptr, reinterpret_cast<const BoxJob *>(p),
                                                    (int)g.jobs.size(), g.n_rows, g.widths.data(),
-                                                   (int)g.widths.size(), stream, 0, all_vec);
+                                                   (int)g.widths.size(), stream, 0, all_vec, max_n_out);
         if (s != AMBER_OK) return s;
         p += g.jobs.size() * sizeof(BoxJob);
     }
