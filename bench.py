@@ -114,28 +114,44 @@ def cpu_baseline(x, n_in, wl, budget_rows: int):
             "single_core": {"value": rows1 * wl.n_out / one["total_s"], "cores": 1, "stages_s": one}}
 
 
-def time_configs(search, x, configs, reps: int):
-    """Median GPU time (HIP events) of dedisperse + fused boxcar/S/N for each
-    configuration, timed interleaved (round robin) so drifts hit all alike."""
-    import torch
+def _point_space(search, tiles):
+    """A search space holding the one configuration `tiles`."""
     import paper_1811_04165_amd as amber
+    G = amber.genes
+    sp = amber.default_space(search.info, search.widths, search.n_out)
+    vals = [tiles.threads_per_dm, tiles.samples_per_thread, tiles.dms_per_block, tiles.channel_unroll,
+            tiles.dms_per_thread, tiles.direct_reads, tiles.snr_threads]
+    for gene, v in zip([G.GENE_THREADS_PER_DM, G.GENE_SAMPLES_PER_THREAD, G.GENE_DMS_PER_BLOCK,
+                        G.GENE_CHANNEL_UNROLL, G.GENE_DMS_PER_THREAD, G.GENE_DIRECT_READS, G.GENE_SNR_THREADS], vals):
+        sp.set_gene_values(gene, [v])
+    for k in range(len(search.widths)):
+        sp.set_gene_values(G.GENE_BOXCAR0 + k, [tiles.boxcar_step[k]])
+    return sp
+
+
+def time_configs(search, x, configs, reps: int):
+    """Median GPU time of dedisperse + fused boxcar/S/N for each configuration,
+    measured as the searches measure fitness (the library's timer: HIP events
+    around the two launches made from native code, after one untimed run),
+    one run per configuration per round, round robin, so drifts hit all alike.
+    (Events around launches made from Python would add the interpreter's
+    per-call time, which is larger than these kernels.)"""
+    import paper_1811_04165_amd as amber
+    spaces = [_point_space(search, t) for t in configs]
+    params = amber.tune_params("exhaustive", warmup=1, reps=1)
+    bufs = (search.dd, search.snr, search.peak)
     times = [[] for _ in configs]
     gc.collect()
     for _ in range(reps):
-        for k, t in enumerate(configs):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            amber.dedisperse(search.delays, search.info, x, search.n_in, search.n_out, t, out=search.dd)
-            amber.integrate_snr(search.dd, search.n_out, search.widths, t, out=(search.snr, search.peak))
-            b.record()
-            b.synchronize()
-            times[k].append(a.elapsed_time(b) / 1e3)
+        for k, sp in enumerate(spaces):
+            times[k].append(amber.tune(sp, search.delays, x, search.n_in, params, buffers=bufs).best_time_s)
     return [statistics.median(v) for v in times]
 
 
 def _small_tune_setup():
     """The tile-search workload (256 channels, 128 DM trials) on the device and
-    its search space (the boxcar kernel's thread count held, its steps tuned)."""
+    its default search space (the boxcar / S/N kernel's gene is its thread
+    count: for these widths it has no per-width step)."""
     import torch
     import paper_1811_04165_amd as amber
     import workloads
@@ -145,7 +161,6 @@ def _small_tune_setup():
     x_host, n_in = workloads.make_input(wl, search.delays_host, search.info.max_delay)
     x = torch.from_numpy(x_host).cuda()
     sp = amber.default_space(search.info, wl.widths, wl.n_out)
-    sp.set_gene_values(amber.genes.GENE_SNR_THREADS, [256])
     return wl, search, x, n_in, sp, (search.dd, search.snr, search.peak)
 
 
@@ -162,12 +177,22 @@ def ga_tune_summary():
             "best": r.as_dict(len(wl.widths))["best"]}
 
 
-def serve_summary(seconds: float = 5.0, warmup_s: float = 1.0):
-    """The streaming service with continuous batching at the workload's rate
-    (400 chunks/s from 40 beams), briefly."""
-    r = serve_report(40, seconds, warmup_s, [400.0], modes=("served",))["serve"]["by_rate"]["400.0"]["served"]
+def serve_summary(seconds: float = 5.0, warmup_s: float = 1.0, over_rate: float = 1600.0):
+    """The streaming service at the workload's rate (400 chunks/s from 40
+    beams) with continuous batching and, beside it, the plain per-chunk path
+    (one chunk at a time: no fusion, no overlap), briefly; then both at
+    `over_rate` chunks/s for 3 s, past the plain path's capacity."""
+    by = serve_report(40, seconds, warmup_s, [400.0, over_rate])["serve"]["by_rate"]
+
+    def pick(r):
+        return {"chunks_per_s": r["chunks_per_s"], "value": r["value"], "latency_ms": r["latency_ms"]}
     return {"offered_chunks_per_s": 400.0, "seconds": seconds, "warmup_s": warmup_s,
-            "chunks_per_s": r["chunks_per_s"], "value": r["value"], "latency_ms": r["latency_ms"]}
+            "chunks_per_s": by["400.0"]["served"]["chunks_per_s"], "value": by["400.0"]["served"]["value"],
+            "latency_ms": by["400.0"]["served"]["latency_ms"],
+            "plain": pick(by["400.0"]["one_at_a_time"]),
+            "over_capacity": {"offered_chunks_per_s": over_rate, "seconds": min(seconds, 3.0),
+                              "served": pick(by[str(over_rate)]["served"]),
+                              "plain": pick(by[str(over_rate)]["one_at_a_time"])}}
 
 
 def tune_report(seeds: int, log_path=None):
@@ -192,23 +217,31 @@ def tune_report(seeds: int, log_path=None):
 
     ga = [run("ga", seed=s) for s in range(1, seeds + 1)]
     gas = [run("ga", seed=s, seed_default=1) for s in range(1, seeds + 1)]   # initial population holds the defaults
+    gar = [run("ga", seed=s, restart_after=GA_RESTART_AFTER) for s in range(1, seeds + 1)]
     rnd = [run("random", seed=100 + s, max_evals=ga[s - 1].n_evals) for s in range(1, seeds + 1)]
     pk = run("per_kernel")
     ex = run("exhaustive", reps=1, warmup=1)
-    finalists = [r.best for r in ga] + [r.best for r in rnd] + [pk.best, ex.best] + [r.best for r in gas]
+    finalists = [r.best for r in ga] + [r.best for r in rnd] + [pk.best, ex.best] + [r.best for r in gas] + \
+        [r.best for r in gar]
     print("[bench] interleaved re-timing of %d finalists" % len(finalists), file=sys.stderr, flush=True)
     t = time_configs(search, x, finalists, reps=100)
     n = seeds
     t_ga, t_rnd, t_pk, t_ex = t[:n], t[n:2 * n], t[2 * n], t[2 * n + 1]
-    t_gas = t[2 * n + 2:]
+    t_gas, t_gar = t[2 * n + 2:3 * n + 2], t[3 * n + 2:]
     nw = len(wl.widths)
     out.update({
-        "retimed_s": {"ga": t_ga, "random": t_rnd, "per_kernel": t_pk, "exhaustive": t_ex, "ga_seeded": t_gas},
+        "retimed_s": {"ga": t_ga, "random": t_rnd, "per_kernel": t_pk, "exhaustive": t_ex, "ga_seeded": t_gas,
+                      "ga_restart": t_gar},
         "ga_median_over_exhaustive": statistics.median(t_ga) / t_ex,
         "ga_worst_over_exhaustive": max(t_ga) / t_ex,
         "ga_seeded_median_over_exhaustive": statistics.median(t_gas) / t_ex,
         "ga_seeded_worst_over_exhaustive": max(t_gas) / t_ex,
         "ga_seeded_evals_median": statistics.median([r.n_evals for r in gas]),
+        "ga_restart": {"restart_after": GA_RESTART_AFTER,
+                       "median_over_exhaustive": statistics.median(t_gar) / t_ex,
+                       "worst_over_exhaustive": max(t_gar) / t_ex,
+                       "evals_median": statistics.median([r.n_evals for r in gar]),
+                       "wall_s_median": statistics.median([r.wall_s for r in gar])},
         "random_median_over_exhaustive": statistics.median(t_rnd) / t_ex,
         "per_kernel_over_exhaustive": t_pk / t_ex,
         "cost": {"ga_evals_median": statistics.median([r.n_evals for r in ga]),
@@ -493,48 +526,161 @@ def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitter
                       "seconds": seconds, "warmup_s": warmup_s, "submit_threads": submitters, "by_rate": out}}
 
 
-def ga_study_report(seeds: int):
-    """The paper's GA studies (Figs 3-5, App. A) on MI355X, replayed against a
-    measured fitness table of the 256-channel / 128-DM workload.
+GA_RESTART_AFTER = 5   # generations without a better best before the GA re-draws its population
+GA_STUDY_BASE = dict(pop=20, p_cross=0.8, p_mut=0.1, crossover=0)
 
-    Each kernel's GPU time is measured for every value of its own genes
-    (median of 7 runs); the two kernels run back to back, so a
-    configuration's fitness is the sum.  The library's search engine then
-    runs on the host against that table: every search gets the evaluation
-    budget of the per-kernel brute force (the paper's T_run = T_BF), and the
-    same seeds for every setting."""
-    import itertools
+
+def _ga_study_settings():
+    """The settings of the paper's studies (Section 4): mutation and crossover
+    rates, population size, crossover type, random search; plus the restart
+    on stagnation this library adds."""
+    settings = [("base (N_pop 20, p_cross 0.8, p_mut 0.1, uniform)", "ga", {})]
+    settings += [("p_mut %g" % v, "ga", {"p_mut": v}) for v in (0.01, 0.3, 1.0)]
+    settings += [("p_cross %g" % v, "ga", {"p_cross": v}) for v in (0.2, 0.5, 1.0)]
+    settings += [("N_pop %d" % v, "ga", {"pop": v}) for v in (30, 50)]
+    settings += [("one-point crossover", "ga", {"crossover": 1}), ("random search", "random", {})]
+    settings += [("restart after %d stale generations" % GA_RESTART_AFTER, "ga",
+                  {"restart_after": GA_RESTART_AFTER})]
+    return settings
+
+
+def ga_study_report(seeds: int):
+    """The paper's GA studies (Figs 3-5, App. A) on MI355X: with joint
+    on-device fitness (the headline), and replayed on a measured table of
+    per-kernel times (a noise-free control in which the kernels cannot
+    interact)."""
+    dev = ga_study_device(seeds)
+    table = ga_study_table(seeds)
+    return {"metric": "GA studies (on-device fitness)", "unit": "ratio",
+            "value": dev["settings"][0]["retimed_over_bf"]["median"], "higher_is_better": False,
+            "ga_study": {"device": dev, "table_replay": table}}
+
+
+def ga_study_device(seeds: int):
+    """The GA studies with joint on-device fitness on the 256-channel / 128-DM
+    workload: every evaluation times dedispersion + boxcar/S/N together on the
+    GPU (median of 3 runs after a warm-up), over the whole genome (the five
+    dedispersion genes and the boxcar / S/N thread count).  T_BF is the
+    on-device per-kernel brute force (each kernel's genes searched in turn,
+    the paper's Section 2 tuning); every search gets its evaluation budget,
+    and the same seeds for every setting.  Each run's best configuration and
+    the brute force's are re-timed interleaved, so that the ratios compare
+    like with like (a search's own best time is the luckiest of its noisy
+    measurements)."""
+    import json
     import os
     import tempfile
     import numpy as np
-    import torch
     import paper_1811_04165_amd as amber
-    import workloads
-    wl = workloads.small()
-    g = wl.geom
-    search = amber.Search(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step, wl.n_out, wl.widths)
-    x_host, n_in = workloads.make_input(wl, search.delays_host, search.info.max_delay)
-    x = torch.from_numpy(x_host).cuda()
-    sp = amber.default_space(search.info, wl.widths, wl.n_out)
+    wl, search, x, n_in, sp, bufs = _small_tune_setup()
     G = amber.genes
-    # the study's table covers the dedispersion genes with one DM per wavefront
-    # and LDS staging, and the boxcar steps at 256 work-items
+    cols = [G.GENE_THREADS_PER_DM, G.GENE_SAMPLES_PER_THREAD, G.GENE_DMS_PER_BLOCK, G.GENE_CHANNEL_UNROLL,
+            G.GENE_DMS_PER_THREAD, G.GENE_DIRECT_READS, G.GENE_SNR_THREADS]
+    names = ["threads_per_dm", "samples_per_thread", "dms_per_block", "channel_unroll", "dms_per_thread",
+             "direct_reads", "snr_threads"]
+
+    def key(t):
+        return (t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll, t.dms_per_thread,
+                t.direct_reads, t.snr_threads)
+
+    print("[bench] device study: per-kernel brute force", file=sys.stderr, flush=True)
+    bf = amber.tune(sp, search.delays, x, n_in, amber.tune_params("per_kernel"), buffers=bufs)
+    budget = bf.n_evals
+    checkpoints = [c for c in (50, 100, 200, 400, 800) if c < budget] + [budget]
+    tmp = tempfile.mkdtemp()
+    finalists = {key(bf.best): bf.best}
+    runs = []
+    for name, kind, kw in _ga_study_settings():
+        print("[bench] device study: %s" % name, file=sys.stderr, flush=True)
+        p = dict(GA_STUDY_BASE)
+        p.update(kw)
+        for seed in range(1, seeds + 1):
+            log = os.path.join(tmp, "s.jsonl")
+            if os.path.exists(log):
+                os.remove(log)
+            if kind == "ga":
+                gens = max(1, budget // p["pop"] - 1)
+                r = amber.tune(sp, search.delays, x, n_in, amber.tune_params("ga", seed=seed, generations=gens, **p),
+                               log_path=log, buffers=bufs)
+            else:
+                r = amber.tune(sp, search.delays, x, n_in, amber.tune_params("random", seed=1000 + seed,
+                                                                             max_evals=budget),
+                               log_path=log, buffers=bufs)
+            lines = [json.loads(l) for l in open(log)]
+            gen_lines = [l for l in lines if "generation" in l]
+            cv = None
+            if kind == "ga" and "final_population" in lines[-1]:
+                end = np.array(lines[-1]["final_population"], dtype=np.float64)[:, cols]
+                mean = end.mean(axis=0)     # direct_reads takes 0 and 1: a population of zeros has c_v 0
+                cv = np.where(mean > 0, end.std(axis=0) / np.where(mean > 0, mean, 1.0), 0.0).tolist()
+            curve = []
+            for c in checkpoints:  # best so far after c evaluations (GA: at generation boundaries)
+                seen = [l["best_time_s"] for l in gen_lines if l["evals"] <= c and l["best_time_s"] > 0]
+                curve.append(min(seen) / bf.best_time_s if seen else None)
+            finalists[key(r.best)] = r.best
+            runs.append(dict(setting=name, kind=kind, seed=seed, best=key(r.best), best_s=r.best_time_s,
+                             evals=r.n_evals, wall_s=r.wall_s, cv=cv, curve=curve,
+                             restarts=gen_lines[-1].get("restarts", 0) if gen_lines else 0))
+    keys = list(finalists)
+    print("[bench] device study: interleaved re-timing of %d finalists" % len(keys), file=sys.stderr, flush=True)
+    times = dict(zip(keys, time_configs(search, x, [finalists[k] for k in keys], reps=15)))
+    t_bf = times[key(bf.best)]
+    out = {"workload": wl.name, "space_size": amber.space_size(sp), "genes": names,
+           "brute_force_per_kernel": {"best": dict(zip(names, key(bf.best))), "evals": budget,
+                                      "best_s_own": bf.best_time_s, "best_s_retimed": t_bf},
+           "budget_evals": budget, "seeds": seeds, "checkpoints": checkpoints,
+           "best_retimed_s": min(times.values()), "settings": []}
+    for name, kind, kw in _ga_study_settings():
+        rs = [r for r in runs if r["setting"] == name]
+        own = np.array([r["best_s"] for r in rs]) / bf.best_time_s
+        ret = np.array([times[r["best"]] for r in rs]) / t_bf
+        cvs = [r["cv"] for r in rs if r["cv"] is not None]
+        curves = np.array([[v if v is not None else np.nan for v in r["curve"]] for r in rs], dtype=np.float64)
+        best_genes = np.array([r["best"] for r in rs])
+        out["settings"].append({
+            "name": name, "kind": kind, "params": dict(GA_STUDY_BASE, **kw),
+            "evals_median": float(np.median([r["evals"] for r in rs])),
+            "wall_s_median": float(np.median([r["wall_s"] for r in rs])),
+            "restarts_median": float(np.median([r["restarts"] for r in rs])),
+            "own_best_over_bf": {"median": float(np.median(own)), "p10": float(np.percentile(own, 10)),
+                                 "p90": float(np.percentile(own, 90))},
+            "retimed_over_bf": {"median": float(np.median(ret)), "p10": float(np.percentile(ret, 10)),
+                                "p90": float(np.percentile(ret, 90)), "worst": float(ret.max())},
+            "runs_within_5pct_of_bf": int(np.sum(ret <= 1.05)),
+            "runs_better_than_bf": int(np.sum(ret < 1.0)),
+            "curve_own_best_over_bf_median": dict(zip(map(str, checkpoints),
+                                                      [None if np.all(np.isnan(c)) else float(np.nanmedian(c))
+                                                       for c in curves.T])),
+            "cv_end_population": dict(zip(names, np.mean(cvs, axis=0).tolist())) if cvs else None,
+            "retimed_over_bf_all": ret.tolist(),
+            "best_gene_histograms": {n: dict(zip(*[list(map(int, a)) for a in np.unique(best_genes[:, k],
+                                                                                        return_counts=True)]))
+                                     for k, n in enumerate(names)}})
+    return out
+
+
+def ga_study_table(seeds: int):
+    """The GA studies replayed on a measured fitness table of the 256-channel /
+    128-DM workload (a noise-free control in which the two kernels cannot
+    interact): each dedispersion configuration is timed once with the boxcar /
+    S/N kernel at 256 threads, each S/N thread count once with the default
+    dedispersion tiles (the library's timer, median of 7 runs), and a
+    configuration's fitness is the sum of its dedispersion entry and its
+    thread count's difference from 256 threads, so per-kernel brute force is
+    exact on it by construction.  The table holds dms_per_thread 1 and LDS
+    staging."""
+    import itertools
+    import paper_1811_04165_amd as amber
+    wl, search, x, n_in, sp, bufs = _small_tune_setup()
+    G = amber.genes
     sp.set_gene_values(G.GENE_DMS_PER_THREAD, [1])
     sp.set_gene_values(G.GENE_DIRECT_READS, [0])
-    sp.set_gene_values(G.GENE_SNR_THREADS, [256])
     nw = len(wl.widths)
     gv = [sp.gene_values(i) for i in range(sp.n_genes)]
+    params = amber.tune_params("exhaustive", warmup=1, reps=7)
 
-    def med_time(fn, reps=7):
-        ts = []
-        for _ in range(reps):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            fn()
-            b.record()
-            b.synchronize()
-            ts.append(a.elapsed_time(b) / 1e3)
-        return statistics.median(ts)
+    def timed(t):
+        return amber.tune(_point_space(search, t), search.delays, x, n_in, params, buffers=bufs).best_time_s
 
     print("[bench] measuring the fitness table", file=sys.stderr, flush=True)
     gc.collect()
@@ -546,17 +692,10 @@ def ga_study_report(seeds: int):
             amber.validate_tiles(t, search.info, nw)
         except amber.AmberError:
             continue
-        amber.dedisperse(search.delays, search.info, x, n_in, wl.n_out, t, out=search.dd)
-        t_dd[(tpd, spt, dpb, cu)] = med_time(
-            lambda: amber.dedisperse(search.delays, search.info, x, n_in, wl.n_out, t, out=search.dd))
-    t_box = {}
-    for steps in itertools.product(*gv[G.GENE_BOXCAR0:]):
-        t = amber.make_tiles(snr_threads=256, boxcar_step=list(steps))
-        amber.integrate_snr(search.dd, wl.n_out, wl.widths, t, out=(search.snr, search.peak))
-        t_box[steps] = med_time(
-            lambda: amber.integrate_snr(search.dd, wl.n_out, wl.widths, t, out=(search.snr, search.peak)))
-
-    return ga_study_replay(sp, wl, t_dd, t_box, seeds)
+        t_dd[(tpd, spt, dpb, cu)] = timed(t)
+    ref = timed(amber.make_tiles(snr_threads=256))
+    t_box = {thr: timed(amber.make_tiles(snr_threads=thr)) - ref for thr in gv[G.GENE_SNR_THREADS]}
+    return ga_study_replay(sp, wl, t_dd, t_box, seeds)["ga_study"]
 
 
 def ga_study_replay(sp, wl, t_dd, t_box, seeds: int):
@@ -566,11 +705,10 @@ def ga_study_replay(sp, wl, t_dd, t_box, seeds: int):
     import tempfile
     import numpy as np
     import paper_1811_04165_amd as amber
-    nw = len(wl.widths)
 
     def fitness_of(t):
         return t_dd[(t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll)] + \
-            t_box[tuple(t.boxcar_step[k] for k in range(nw))]
+            t_box[t.snr_threads]
 
     opt = min(t_dd.values()) + min(t_box.values())
 
@@ -579,8 +717,8 @@ def ga_study_replay(sp, wl, t_dd, t_box, seeds: int):
 
         def fit(t):
             v = fitness_of(t)
-            hist.append((v, (t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll) +
-                         tuple(t.boxcar_step[k] for k in range(nw))))
+            hist.append((v, (t.threads_per_dm, t.samples_per_thread, t.dms_per_block, t.channel_unroll,
+                             t.snr_threads)))
             return v
         r = amber.search_tiles(sp, amber.tune_params(kind, **kw), fit, log_path=log)
         return r, hist
@@ -589,16 +727,11 @@ def ga_study_replay(sp, wl, t_dd, t_box, seeds: int):
     t_bf, budget = bf.best_time_s, bf.n_evals
     checkpoints = [c for c in (50, 100, 200, 400, 800) if c < budget] + [budget]
     G = amber.genes
-    cols = [G.GENE_THREADS_PER_DM, G.GENE_SAMPLES_PER_THREAD, G.GENE_DMS_PER_BLOCK, G.GENE_CHANNEL_UNROLL] + \
-        [G.GENE_BOXCAR0 + k for k in range(nw)]
-    genes = ["threads_per_dm", "samples_per_thread", "dms_per_block", "channel_unroll"] + \
-        ["boxcar_step_w%d" % w for w in wl.widths]
-    base = dict(pop=20, p_cross=0.8, p_mut=0.1, crossover=0)
-    settings = [("base (N_pop 20, p_cross 0.8, p_mut 0.1, uniform)", "ga", {})]
-    settings += [("p_mut %g" % v, "ga", {"p_mut": v}) for v in (0.01, 0.3, 1.0)]
-    settings += [("p_cross %g" % v, "ga", {"p_cross": v}) for v in (0.2, 0.5, 1.0)]
-    settings += [("N_pop %d" % v, "ga", {"pop": v}) for v in (30, 50)]
-    settings += [("one-point crossover", "ga", {"crossover": 1}), ("random search", "random", {})]
+    cols = [G.GENE_THREADS_PER_DM, G.GENE_SAMPLES_PER_THREAD, G.GENE_DMS_PER_BLOCK, G.GENE_CHANNEL_UNROLL,
+            G.GENE_SNR_THREADS]
+    genes = ["threads_per_dm", "samples_per_thread", "dms_per_block", "channel_unroll", "snr_threads"]
+    base = GA_STUDY_BASE
+    settings = _ga_study_settings()
     out = {"workload": wl.name, "space_size": amber.space_size(sp), "table": {
         "dedisperse_configs": len(t_dd), "boxcar_configs": len(t_box), "optimum_s": opt,
         "dedisperse_best_s": min(t_dd.values()), "boxcar_best_s": min(t_box.values())},
@@ -631,8 +764,8 @@ def ga_study_replay(sp, wl, t_dd, t_box, seeds: int):
             evals.append(r.n_evals)
             cvs.append(end.std(axis=0) / end.mean(axis=0))
             b = r.best
-            best_genes.append([b.threads_per_dm, b.samples_per_thread, b.dms_per_block, b.channel_unroll] +
-                              [b.boxcar_step[k] for k in range(nw)])
+            best_genes.append([b.threads_per_dm, b.samples_per_thread, b.dms_per_block, b.channel_unroll,
+                               b.snr_threads])
         f = np.array(finals)
         cv = np.mean(cvs, axis=0)
         hist_genes = {gname: dict(zip(*[list(map(int, a)) for a in np.unique(np.array(best_genes)[:, k],
@@ -996,7 +1129,7 @@ def main() -> int:
                          "per-kernel brute-force search on the 256-channel workload")
     ap.add_argument("--tune-seeds", type=int, default=10)
     ap.add_argument("--tune-log", type=str, default="",
-                    help="JSONL log of the --tune searches (a line per generation, or per 1000 evaluations)")
+                    help="JSONL log of the --tune searches (a line per generation, or per 50 evaluations)")
     ap.add_argument("--ga-study", action="store_true",
                     help="instead of the throughput step: the paper's GA studies (mutation and crossover rates, "
                          "population size, crossover type, random search) replayed on a measured fitness table")

@@ -89,10 +89,18 @@ typedef struct {
  *   channel_unroll     channels staged in LDS per step (unroll); 1..32, power
  *                      of two
  *   snr_threads        work-items per work-group of the boxcar / S/N kernels
- *                      (nrThreadsD0); 64..1024, power of two
+ *                      (nrThreadsD0); 64..1024, power of two.  In the fused
+ *                      kernel for up to 8 sliding widths of at most 64
+ *                      samples: snr_threads / 64 wavefronts share a row
  *   boxcar_step[k]     consecutive outputs per work-item for width k of the
  *                      boxcar / S/N kernels (nrItemsD0, one per width as the
- *                      paper has one per downsampling factor); 1, 2, 4 or 8
+ *                      paper has one per downsampling factor); 1, 2, 4 or 8.
+ *                      Used by decimation, by the materialised boxcar / S/N
+ *                      and by the fused kernel for more or wider widths; the
+ *                      fused kernel for up to 8 sliding widths of at most 64
+ *                      samples reads every width from one prefix per 4
+ *                      outputs and has no such gene (the value must still be
+ *                      valid)
  *   dms_per_thread     DM trials per wavefront (nrDMsPerThread): 1 or 2 (2
  *                      with samples_per_thread <= 16); 0 reads as 1.  A
  *                      work-group covers dms_per_block * dms_per_thread DMs,
@@ -323,11 +331,21 @@ amber_status amber_snr(const int32_t *d_box, int32_t n_dm, int64_t box_stride, i
                        float *d_snr, int32_t *d_peak_t,
                        const amber_tiles *tiles, void *stream);
 
-/* amber_integrate followed by amber_snr in one kernel: each dedispersed row is
- * read once and its boxcar series live only in LDS and registers.  Same
- * arguments and results as the pair, without d_box.  tiles == NULL: the
- * defaults, with snr_threads 64 when n_dm >= 4096 (one row per work-group;
- * with that many rows single-wave groups keep the CUs busier) and the default
+/* amber_integrate followed by amber_snr in one kernel (Section 2: the
+ * smoothing and S/N kernels after dedispersion): each dedispersed row is read
+ * once and its boxcar series live only in LDS and registers.  Same arguments
+ * and results as the pair, without d_box.
+ * Up to 8 sliding widths of at most 64 samples (rows below 2^29 samples) take
+ * a kernel in which the work-group's wavefronts sweep consecutive spans of
+ * the row: per 256 outputs a prefix in LDS, per width the maximum, the block
+ * where it first rises and an exact int64 sum of squares; the mean follows
+ * from the row's sum in closed form.  Its results are exact (up to the FP64
+ * finish) for dd >= 0 with dd * max(widths) < 2^31 (any dedispersed uint8
+ * data), and for signed dd with |dd| * max(widths) < 2^30; a row whose values
+ * could overflow the int64 sums has them recomputed in FP64.  More or wider
+ * widths take the chunked kernel of amber_integrate.
+ * tiles == NULL: the defaults, with snr_threads 64 when n_dm >= 4096 (with
+ * that many rows one wavefront per row keeps the CUs busiest) and the default
  * 128 below, raised while 16 * snr_threads < twice the largest width rounded
  * up to 16.  A batch with automatic tiles applies the same rule to its total
  * number of rows. */
@@ -412,6 +430,10 @@ typedef struct {
                              is the library's default configuration (when all
                              its values are in the gene arrays and it is valid),
                              the others random; 0 (the paper's form) = all random */
+    int32_t restart_after; /* GA: 0 (the paper's form) = off; n > 0 = when the best
+                              fitness has not improved for n generations, every
+                              individual but the best is replaced by a fresh random
+                              valid one (an addition for robustness across seeds) */
 } amber_tune_params;
 
 typedef struct {
@@ -430,7 +452,9 @@ typedef int32_t (*amber_fitness_fn)(const amber_tiles *tiles, void *user, double
 /* The default search space for a problem: threads_per_dm {64 .. 1024},
  * samples_per_thread {4 .. 32}, dms_per_block {1 .. 16}, channel_unroll
  * {1 .. 32} (powers of two), dms_per_thread {1, 2}, direct_reads {0, 1},
- * snr_threads {64 .. 1024}, boxcar_step {1, 2, 4, 8} per width.  Invalid
+ * snr_threads {64 .. 1024}, boxcar_step {1, 2, 4, 8} per width, or the
+ * single value 8 when the fused kernel for up to 8 sliding widths of at most
+ * 64 samples serves these widths (it has no step gene).  Invalid
  * combinations stay in the arrays; the searches skip them. */
 amber_status amber_default_space(const amber_delay_info *info, const int32_t *widths, int32_t n_widths,
                                  int64_t n_out, amber_tune_space *space);
@@ -440,7 +464,7 @@ amber_status amber_space_size(const amber_tune_space *space, int64_t *count);
 
 /* Runs the search of p->search over `space` with a caller-supplied fitness
  * (host only; no GPU needed).  log_jsonl_path, if not NULL, receives one JSON
- * line per GA generation (or per 1000 evaluations for the other searches);
+ * line per GA generation (or per 50 evaluations for the other searches);
  * after its last generation the GA adds one line {"final_population": gene
  * values per individual, "fitness": per individual (-1 for failures)}. */
 amber_status amber_search_tiles(const amber_tune_space *space, const amber_tune_params *p, amber_fitness_fn fn,

@@ -19,7 +19,10 @@ Steps (see include/amber.h for the exact contracts):
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import sys
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -532,6 +535,32 @@ def tune_subband(space: SubbandTuneSpace, delay1, delay2, x, n_in: int, params: 
 
 # --- batched beams --------------------------------------------------------------------
 
+# Batch and Server handles still open: closed at interpreter exit, while the
+# HIP runtime and the library are certainly alive (a handle released from
+# __del__ during interpreter shutdown could run after either is torn down).
+_open_handles = weakref.WeakSet()
+
+
+def _close_open_handles():
+    for h in list(_open_handles):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_open_handles)
+
+
+def _release_in_del(obj):
+    if sys.is_finalizing():   # the atexit hook has run; nothing is left to release
+        return
+    try:
+        obj.close()
+    except Exception:
+        pass
+
+
 class Batch:
     """Independent beams of uneven sizes run together.
 
@@ -558,6 +587,7 @@ class Batch:
         h = ctypes.c_void_p()
         check(load().amber_batch_create(arr, len(beams), wp, len(self._w), tarr, ctypes.byref(h)))
         self._h = h
+        _open_handles.add(self)
 
     def launches(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()
@@ -575,14 +605,12 @@ class Batch:
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
+            _open_handles.discard(self)
             check(load().amber_batch_destroy(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _release_in_del(self)
 
 
 def chunk_span(seq: int, chunk: int, max_delay: int):
@@ -630,6 +658,7 @@ class Server:
         h = ctypes.c_void_p()
         check(load().amber_server_create(ctypes.byref(self.config), ctypes.byref(h)))
         self._h = h
+        _open_handles.add(self)
         self._beams = []
 
     def add_beam(self, freqs, t_samp_s: float, n_dm: int, dm_first: float, dm_step: float, chunk: int,
@@ -678,6 +707,7 @@ class Server:
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
+            _open_handles.discard(self)
             check(load().amber_server_destroy(self._h))
             self._h = ctypes.c_void_p()
 
@@ -688,7 +718,4 @@ class Server:
         self.close()
 
     def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        _release_in_del(self)

@@ -94,7 +94,7 @@ class TuneParams(ctypes.Structure):
                 ("crossover", ctypes.c_int32), ("p_cross", ctypes.c_double), ("p_mut", ctypes.c_double),
                 ("pool_frac", ctypes.c_double), ("seed", ctypes.c_uint64), ("warmup", ctypes.c_int32),
                 ("reps", ctypes.c_int32), ("eval_timeout_s", ctypes.c_double), ("max_evals", ctypes.c_int64),
-                ("seed_default", ctypes.c_int32)]
+                ("seed_default", ctypes.c_int32), ("restart_after", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):
@@ -290,6 +290,12 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libamber.so is not built (run __graft_entry__.build() or "
                               "python paper_1811_04165_amd/build.py)")
+        # torch carries its own copy of the HIP runtime under the soname this
+        # library links against.  Loaded after torch, the library binds to that
+        # copy; loaded before it, the process ends up with two HIP runtimes,
+        # each opening the device on its own, and the second one to start has
+        # reported no device.  So torch is always loaded first.
+        import torch  # noqa: F401
         lib = ctypes.CDLL(LIB_PATH)
         for name, res, args in SIGNATURES:
             f = getattr(lib, name)

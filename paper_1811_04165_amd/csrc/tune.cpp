@@ -183,7 +183,7 @@ private:
             best_fit_ = sec;
             best_ = g;
         }
-        if (p_.search != AMBER_SEARCH_GA && log_ && n_evals_ % 1000 == 0) log_line(-1);
+        if (p_.search != AMBER_SEARCH_GA && log_ && n_evals_ % 50 == 0) log_line(-1);
         return sec;
     }
 
@@ -191,9 +191,11 @@ private:
     {
         if (!log_) return;
         const std::string best = best_.empty() ? "null" : pb_.json(best_);
-        fprintf(log_, "{\"generation\":%d,\"evals\":%lld,\"failed\":%lld,\"best_time_s\":%.9g,\"wall_s\":%.6f,\"best\":%s}\n",
-                generation, (long long)n_evals_, (long long)n_failed_, std::isfinite(best_fit_) ? best_fit_ : -1.0,
-                elapsed(), best.c_str());
+        fprintf(log_,
+                "{\"generation\":%d,\"evals\":%lld,\"failed\":%lld,\"restarts\":%d,\"best_time_s\":%.9g,"
+                "\"wall_s\":%.6f,\"best\":%s}\n",
+                generation, (long long)n_evals_, (long long)n_failed_, restarts_,
+                std::isfinite(best_fit_) ? best_fit_ : -1.0, elapsed(), best.c_str());
         fflush(log_);
     }
 
@@ -341,7 +343,21 @@ private:
             fit[i] = evaluate(pop[i]);
         }
         log_line(0);
+        double best = *std::min_element(fit.begin(), fit.end());
+        int stale = 0;  // generations since the best fitness last improved
         for (int gen = 1; gen <= p_.generations; ++gen) {
+            // restart on stagnation (an option, off in the paper's form): all
+            // but the best individual are replaced by fresh random ones
+            if (p_.restart_after > 0 && stale >= p_.restart_after) {
+                const int keep = (int)(std::min_element(fit.begin(), fit.end()) - fit.begin());
+                for (int i = 0; i < n; ++i) {
+                    if (i == keep) continue;
+                    if (!random_genome(pop[i])) return fail(AMBER_E_CONFIG, "no valid configuration found to restart");
+                    fit[i] = evaluate(pop[i]);
+                }
+                stale = 0;
+                ++restarts_;
+            }
             // selection: N_pop tournaments
             std::vector<int> sel(n);
             for (int i = 0; i < n; ++i) sel[i] = tournament(fit);
@@ -382,6 +398,9 @@ private:
             }
             pop.swap(next);
             fit.swap(next_fit);
+            const double b = *std::min_element(fit.begin(), fit.end());
+            stale = b < best ? 0 : stale + 1;
+            best = b < best ? b : best;
             log_line(gen);
         }
         log_population(pop, fit);
@@ -461,6 +480,7 @@ private:
     Genome best_;
     double best_fit_ = kInf;
     int64_t n_evals_ = 0, n_failed_ = 0;
+    int restarts_ = 0;
 };
 
 // The hot path's search: one dedispersion tile and the boxcar / S/N genes,
@@ -801,8 +821,12 @@ amber_status amber_default_space(const amber_delay_info *info, const int32_t *wi
         {64, 128, 256, 512, 1024},  // snr_threads
     };
     sp->n_genes = kGeneBox0 + n_widths;
+    // the kernel for up to 8 sliding widths of at most 64 samples has no
+    // per-width step: those genes keep one value
+    const std::vector<int> steps = span_snr_applies(widths, n_widths, 0, n_out) ? std::vector<int>{8}
+                                                                               : std::vector<int>{1, 2, 4, 8};
     for (int i = 0; i < sp->n_genes; ++i) {
-        const std::vector<int> v = i < kGeneBox0 ? vals[i] : std::vector<int>{1, 2, 4, 8};
+        const std::vector<int> v = i < kGeneBox0 ? vals[i] : steps;
         sp->n_values[i] = (int32_t)v.size();
         for (size_t k = 0; k < v.size(); ++k) sp->values[i][k] = v[k];
     }
@@ -859,6 +883,7 @@ amber_status amber_search_tiles(const amber_tune_space *space, const amber_tune_
     if (!p || !fn || !result) return fail(AMBER_E_ARG, "NULL params, fitness or result");
     if (!(p->p_cross >= 0 && p->p_cross <= 1 && p->p_mut >= 0 && p->p_mut <= 1 && p->pool_frac > 0 && p->pool_frac <= 1))
         return fail(AMBER_E_ARG, "probabilities must lie in [0, 1] and pool_frac in (0, 1]");
+    if (p->restart_after < 0) return fail(AMBER_E_ARG, "restart_after=%d must be >= 0", p->restart_after);
     FILE *log = nullptr;
     if (log_jsonl_path && *log_jsonl_path) {
         log = fopen(log_jsonl_path, "a");
@@ -935,8 +960,10 @@ amber_status amber_default_subband_space(const amber_subband_info *info, const i
         {64, 128, 256, 512, 1024},  // snr_threads
     };
     sp->n_genes = kSbBox0 + n_widths;
+    const std::vector<int> steps = span_snr_applies(widths, n_widths, 0, n_out) ? std::vector<int>{8}
+                                                                               : std::vector<int>{1, 2, 4, 8};
     for (int i = 0; i < sp->n_genes; ++i) {
-        const std::vector<int> v = i < kSbBox0 ? vals[i] : std::vector<int>{1, 2, 4, 8};
+        const std::vector<int> v = i < kSbBox0 ? vals[i] : steps;
         sp->n_values[i] = (int32_t)v.size();
         for (size_t k = 0; k < v.size(); ++k) sp->values[i][k] = v[k];
     }
@@ -983,6 +1010,7 @@ amber_status amber_search_subband_tiles(const amber_subband_tune_space *space, c
     if (!p || !fn || !result) return fail(AMBER_E_ARG, "NULL params, fitness or result");
     if (!(p->p_cross >= 0 && p->p_cross <= 1 && p->p_mut >= 0 && p->p_mut <= 1 && p->pool_frac > 0 && p->pool_frac <= 1))
         return fail(AMBER_E_ARG, "probabilities must lie in [0, 1] and pool_frac in (0, 1]");
+    if (p->restart_after < 0) return fail(AMBER_E_ARG, "restart_after=%d must be >= 0", p->restart_after);
     FILE *log = nullptr;
     if (log_jsonl_path && *log_jsonl_path) {
         log = fopen(log_jsonl_path, "a");

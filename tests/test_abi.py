@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads and
 exports every function include/amber.h declares, the FP64 delay table matches
 the oracle bit for bit, and arguments are validated before any launch."""
+import ast
 import ctypes
 import os
 import re
@@ -24,6 +25,18 @@ def _declared_functions():
             text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
             names += re.findall(r"^[A-Za-z_][\w \*]*?\b(amber_\w+)\s*\(", text, flags=re.M)
     return sorted(set(names))
+
+
+def test_process_holds_one_hip_runtime():
+    """Loading the library first and torch afterwards still leaves a single HIP
+    runtime mapped into the process (the library binds to torch's copy)."""
+    import subprocess
+    code = ("import paper_1811_04165_amd as a; a._lib.load(); import torch; "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    mapped = ast.literal_eval(r.stdout.strip().splitlines()[-1])
+    assert len(mapped) == 1, mapped
 
 
 def test_library_exports_every_declared_symbol():

@@ -41,3 +41,32 @@ def test_bench_json_line():
     assert rec["ga_tune"]["evals"] > 0 and rec["ga_tune"]["wall_s"] > 0
     lat = rec["serve"]["latency_ms"]
     assert 0 < lat["p50"] <= lat["p99"] <= lat["max"]
+
+
+def test_ga_study_two_seeds():
+    """bench.py --ga-study at 2 seeds: both studies (on-device fitness and the
+    table replay) run every setting, and their ratios are consistent."""
+    import math
+    print("[case] bench.py --ga-study --study-seeds 2", flush=True)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--ga-study", "--study-seeds", "2"],
+                       capture_output=True, text=True, timeout=600, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stdout.splitlines() if l.strip()]
+    assert len(lines) == 1, r.stdout
+    rec = json.loads(lines[0])
+    dev, table = rec["ga_study"]["device"], rec["ga_study"]["table_replay"]
+    assert len(dev["settings"]) == len(table["settings"]) == 12
+    bf = dev["brute_force_per_kernel"]
+    assert dev["budget_evals"] == bf["evals"] > 0
+    assert 0 < dev["best_retimed_s"] <= bf["best_s_retimed"]
+    for st in dev["settings"]:
+        ret = st["retimed_over_bf"]
+        assert len(st["retimed_over_bf_all"]) == 2
+        assert 0 < ret["p10"] <= ret["median"] <= ret["p90"] <= ret["worst"] < 10, st["name"]
+        assert st["evals_median"] <= dev["budget_evals"], st["name"]
+        assert set(st["best_gene_histograms"]) == set(dev["genes"])
+        if st["kind"] == "ga":
+            assert all(math.isfinite(v) for v in st["cv_end_population"].values()), st["name"]
+    assert table["brute_force_per_kernel"]["over_optimum"] == pytest.approx(1.0)
+    for st in table["settings"]:
+        assert st["best_over_bf"]["median"] >= 1.0 - 1e-9, st["name"]

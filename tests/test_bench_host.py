@@ -38,9 +38,7 @@ def test_ga_study_replay_on_a_synthetic_table():
     sp.set_gene_values(G.GENE_CHANNEL_UNROLL, [2, 8])
     sp.set_gene_values(G.GENE_DMS_PER_THREAD, [1])
     sp.set_gene_values(G.GENE_DIRECT_READS, [0])
-    sp.set_gene_values(G.GENE_SNR_THREADS, [256])
-    for k in range(len(wl.widths)):
-        sp.set_gene_values(G.GENE_BOXCAR0 + k, [1, 4])
+    sp.set_gene_values(G.GENE_SNR_THREADS, [64, 256, 1024])
     # fitness: a smooth bowl in log2 of every studied gene, separable by kernel
     t_dd = {}
     for tpd, spt, dpb, cu in itertools.product([64, 256], [4, 8], [1, 4], [2, 8]):
@@ -52,13 +50,12 @@ def test_ga_study_replay_on_a_synthetic_table():
             continue
         t_dd[(tpd, spt, dpb, cu)] = 1e-5 * (1 + math.log2(tpd / 64) + abs(math.log2(spt / 8)) + math.log2(dpb)
                                             + abs(math.log2(cu / 8)))
-    t_box = {steps: 1e-5 * (1 + sum(math.log2(s) for s in steps))
-             for steps in itertools.product([1, 4], repeat=len(wl.widths))}
+    t_box = {thr: 1e-6 * abs(math.log2(thr / 256)) for thr in (64, 256, 1024)}
     out = bench.ga_study_replay(sp, wl, t_dd, t_box, seeds=2)["ga_study"]
     assert out["brute_force_per_kernel"]["over_optimum"] == pytest.approx(1.0)
-    names = ["threads_per_dm", "samples_per_thread", "dms_per_block", "channel_unroll"] + \
-        ["boxcar_step_w%d" % w for w in wl.widths]
-    assert len(out["settings"]) == 11
+    names = ["threads_per_dm", "samples_per_thread", "dms_per_block", "channel_unroll", "snr_threads"]
+    assert len(out["settings"]) == 12
+    assert [st["name"] for st in out["settings"]][-1].startswith("restart")
     for st in out["settings"]:
         assert list(st["cv_end_population"]) == names, st["name"]
         assert all(math.isfinite(v) and v >= 0 for v in st["cv_end_population"].values()), st["name"]

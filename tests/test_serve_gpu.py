@@ -168,3 +168,35 @@ def test_server_rejects(amber, streams):
         with pytest.raises(amber.AmberError):
             srv.submit(b + 1, np.zeros((g.n_chan, L), np.uint8))
         assert srv.wait(0.05) is None              # nothing submitted: the wait times out
+
+
+def test_process_exits_cleanly_with_open_handles():
+    """A process that leaves a Server (with a chunk done) and a Batch open
+    exits with status 0: the binding closes them at exit."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = r'''
+import sys
+sys.path.insert(0, %r)
+import numpy as np, torch
+import paper_1811_04165_amd as amber, workloads
+g = workloads.Geometry(n_chan=64, n_dm=16, dm_first=0.0, dm_step=1.0)
+srv = amber.Server(max_inflight=4, max_batch=2, n_streams=2)
+srv.add_beam(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step, 1024, (1, 2, 4))
+srv.submit(0, np.full((64, 1024), 100, np.uint8), tag=0)
+assert srv.wait(30.0) is not None
+d, info = amber.delay_table(g.freqs(), g.t_samp_s, g.n_dm, g.dm_first, g.dm_step)
+n_in = 1000 + info.max_delay
+bm = dict(delays=torch.from_numpy(d).cuda(), info=info, x=torch.zeros((64, (n_in + 127) // 128 * 128), dtype=torch.uint8, device="cuda"),
+          n_in=n_in, n_out=1000, dd=torch.zeros((16, 1000), dtype=torch.int32, device="cuda"),
+          snr=torch.zeros((3, 16), dtype=torch.float32, device="cuda"), peak=torch.zeros((3, 16), dtype=torch.int32, device="cuda"))
+b = amber.Batch([bm], (1, 2, 4))
+b.run()
+torch.cuda.synchronize()
+print("left open", flush=True)
+''' % root
+    say("child process exiting with an open Server and Batch")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, (r.returncode, r.stdout[-2000:], r.stderr[-2000:])
+    assert "left open" in r.stdout

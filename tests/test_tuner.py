@@ -68,6 +68,12 @@ def test_default_space_and_size(amber):
     sp, info, widths = _small_space(amber, reduced=False)
     assert sp.n_genes == 7 + len(widths)
     assert sp.gene_values(1) == [4, 8, 16, 32] and sp.gene_values(4) == [1, 2] and sp.gene_values(5) == [0, 1]
+    # widths up to 64 (at most 8): their fused kernel has no step gene
+    assert sp.gene_values(7) == [8] and sp.gene_values(8) == [8]
+    wide = amber.default_space(info, (1, 128), 8192)
+    assert wide.gene_values(7) == [1, 2, 4, 8] and wide.gene_values(8) == [1, 2, 4, 8]
+    many = amber.default_space(info, tuple(range(1, 10)), 8192)
+    assert all(many.gene_values(7 + k) == [1, 2, 4, 8] for k in range(9))
     n = amber.space_size(sp)
     assert 0 < n <= 5 * 4 * 5 * 6 * 2 * 2 * 5 * 16
     spr, _, _ = _small_space(amber)
@@ -107,6 +113,10 @@ def _smooth(target, n_w):
 
 def test_ga_valid_offspring_deterministic_and_converging(amber, tmp_path):
     sp, info, widths = _small_space(amber, reduced=False)
+    # the operators on a space with step genes (the default space gives the
+    # widths 1 and 4 a single step: their kernel has no such gene)
+    sp.set_gene_values(7, [1, 2, 4, 8])
+    sp.set_gene_values(8, [1, 2, 4, 8])
     target = (64, 8, 16, 16, 2, 1, 256, 4, 2)
     smooth = _smooth(target, len(widths))
 
@@ -210,3 +220,30 @@ def test_ga_seeded_with_the_default(amber):
     spr, _, _ = _small_space(amber)
     r1 = amber.search_tiles(spr, amber.tune_params("ga", pop=4, generations=1, seed_default=1), fit)
     assert r1.n_evals > 0 and r1.best_time_s == pytest.approx(2e-4)
+
+
+def test_ga_restart_on_stagnation(amber, tmp_path):
+    """restart_after: after that many generations without a better best, all
+    but the best individual are replaced by fresh random ones.  Deterministic
+    under its seed, the best never gets worse, the log counts the restarts."""
+    sp, info, widths = _small_space(amber, reduced=False)
+    smooth = _smooth((64, 8, 16, 16, 2, 1, 256, 8, 8), len(widths))
+
+    def fit(t):
+        amber.validate_tiles(t, sp.info, len(widths))
+        return smooth(t)
+
+    with pytest.raises(amber.AmberError):
+        amber.search_tiles(sp, amber.tune_params("ga", seed=3, restart_after=-1), fit)
+    log = tmp_path / "restart.jsonl"
+    p = amber.tune_params("ga", seed=3, restart_after=2, pop=8, generations=30)
+    r1 = amber.search_tiles(sp, p, fit, log_path=str(log))
+    r2 = amber.search_tiles(sp, p, fit)
+    assert _tiles_key(r1.best, 2) == _tiles_key(r2.best, 2) and r1.n_evals == r2.n_evals
+    lines = [json.loads(l) for l in log.read_text().splitlines()][:-1]
+    assert lines[-1]["restarts"] >= 1
+    bests = [l["best_time_s"] for l in lines]
+    assert all(b2 <= b1 for b1, b2 in zip(bests, bests[1:]))
+    # restarts spend evaluations on fresh genomes: more than the paper's form
+    r0 = amber.search_tiles(sp, amber.tune_params("ga", seed=3, pop=8, generations=30), fit)
+    assert r1.n_evals > r0.n_evals
