@@ -217,31 +217,32 @@ def tune_report(seeds: int, log_path=None):
 
     ga = [run("ga", seed=s) for s in range(1, seeds + 1)]
     gas = [run("ga", seed=s, seed_default=1) for s in range(1, seeds + 1)]   # initial population holds the defaults
-    gar = [run("ga", seed=s, restart_after=GA_RESTART_AFTER) for s in range(1, seeds + 1)]
+    gar = {ra: [run("ga", seed=s, restart_after=ra) for s in range(1, seeds + 1)] for ra in GA_RESTART_SWEEP}
     rnd = [run("random", seed=100 + s, max_evals=ga[s - 1].n_evals) for s in range(1, seeds + 1)]
     pk = run("per_kernel")
     ex = run("exhaustive", reps=1, warmup=1)
     finalists = [r.best for r in ga] + [r.best for r in rnd] + [pk.best, ex.best] + [r.best for r in gas] + \
-        [r.best for r in gar]
+        [r.best for ra in GA_RESTART_SWEEP for r in gar[ra]]
     print("[bench] interleaved re-timing of %d finalists" % len(finalists), file=sys.stderr, flush=True)
     t = time_configs(search, x, finalists, reps=100)
     n = seeds
     t_ga, t_rnd, t_pk, t_ex = t[:n], t[n:2 * n], t[2 * n], t[2 * n + 1]
-    t_gas, t_gar = t[2 * n + 2:3 * n + 2], t[3 * n + 2:]
+    t_gas = t[2 * n + 2:3 * n + 2]
+    t_gar = {ra: t[(3 + k) * n + 2:(4 + k) * n + 2] for k, ra in enumerate(GA_RESTART_SWEEP)}
     nw = len(wl.widths)
     out.update({
         "retimed_s": {"ga": t_ga, "random": t_rnd, "per_kernel": t_pk, "exhaustive": t_ex, "ga_seeded": t_gas,
-                      "ga_restart": t_gar},
+                      "ga_restart": {str(ra): t_gar[ra] for ra in GA_RESTART_SWEEP}},
         "ga_median_over_exhaustive": statistics.median(t_ga) / t_ex,
         "ga_worst_over_exhaustive": max(t_ga) / t_ex,
         "ga_seeded_median_over_exhaustive": statistics.median(t_gas) / t_ex,
         "ga_seeded_worst_over_exhaustive": max(t_gas) / t_ex,
         "ga_seeded_evals_median": statistics.median([r.n_evals for r in gas]),
-        "ga_restart": {"restart_after": GA_RESTART_AFTER,
-                       "median_over_exhaustive": statistics.median(t_gar) / t_ex,
-                       "worst_over_exhaustive": max(t_gar) / t_ex,
-                       "evals_median": statistics.median([r.n_evals for r in gar]),
-                       "wall_s_median": statistics.median([r.wall_s for r in gar])},
+        "ga_restart": {str(ra): {"median_over_exhaustive": statistics.median(t_gar[ra]) / t_ex,
+                                 "worst_over_exhaustive": max(t_gar[ra]) / t_ex,
+                                 "evals_median": statistics.median([r.n_evals for r in gar[ra]]),
+                                 "wall_s_median": statistics.median([r.wall_s for r in gar[ra]])}
+                       for ra in GA_RESTART_SWEEP},
         "random_median_over_exhaustive": statistics.median(t_rnd) / t_ex,
         "per_kernel_over_exhaustive": t_pk / t_ex,
         "cost": {"ga_evals_median": statistics.median([r.n_evals for r in ga]),
@@ -527,6 +528,7 @@ def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitter
 
 
 GA_RESTART_AFTER = 5   # generations without a better best before the GA re-draws its population
+GA_RESTART_SWEEP = (3, 5, 8)
 GA_STUDY_BASE = dict(pop=20, p_cross=0.8, p_mut=0.1, crossover=0)
 
 

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+import subband_smearing
 import workloads
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -266,6 +267,46 @@ def test_subband_delay_error_bound_and_impulse():
             assert np.array_equal(dd[j, k], want)
     with pytest.raises(ValueError):
         oracle.subband_delays(f, g.t_samp_s, 7, 2, 0.0, 1.0, 2, 0.0, 0.5)     # 7 does not divide 64
+
+
+@pytest.mark.parametrize("grid_name", sorted(subband_smearing.GRIDS))
+def test_subband_snr_loss_within_smearing_bound(grid_name):
+    """Pulses on the 1536-channel beam under the subband scheme, on the
+    beam's own grid and on Table 2's grid spacing: every channel's shift
+    error lies within the pinned bound (residual +- 3/2); a pulse alone
+    comes out of its subband trial exactly as those shifts smear it; and with
+    noise, the subband / brute-force S/N ratio at the pulse's width is no
+    lower than the fraction of the pulse one boxcar collects after that
+    smearing allows (noise margins in the floor) and no higher than 1 plus
+    the noise margin."""
+    sm = subband_smearing
+    grid, pulses = sm.GRIDS[grid_name]
+    g = workloads.beam().geom
+    f, ts, n_out, amp = g.freqs(), g.t_samp_s, sm.BEAM_N_OUT, sm.PULSE_AMP
+    d1, d2, m1, m2 = oracle.subband_delays(f, ts, *grid)
+    shifts = [sm.pulse_shifts(f, ts, grid, j, k) for j, k, _, _ in pulses]
+    n_in = n_out + max(m1 + m2, max(int(d.max()) for _, _, d in shifts))
+    x = workloads.noise(g.n_chan, n_in, workloads.padded_stride(n_in), seed=77)
+    for (j, k, w, t0), (e, resid, d) in zip(pulses, shifts):
+        assert np.all(np.abs(e - resid) <= 1.5 + 1e-9), (j, k)
+        workloads.inject(x, d, t0=t0, width=w, amp=amp)
+    for (j, k, w, t0), (e, resid, d) in zip(pulses, shifts):
+        one = np.zeros_like(x)
+        workloads.inject(one, d, t0=t0, width=w, amp=amp)
+        sb = oracle.subband_dedisperse(d1[:, [j], :], d2[[j]][:, [k], :], one, n_in, n_out)[0]
+        want = sm.smeared_series(e, t0, w, amp, n_out)
+        assert np.array_equal(sb, want), (j, k)
+        bf = oracle.dedisperse(d[None], one, n_in, n_out)[0]
+        assert bf[t0:t0 + w].tolist() == [amp * g.n_chan] * w and bf.sum() == amp * g.n_chan * w
+        peak_bf = amp * g.n_chan * w
+        frac = sm.best_boxcar(want, w) / peak_bf
+        s_sb, _ = oracle.snr(oracle.boxcar(oracle.subband_dedisperse(d1[:, [j], :], d2[[j]][:, [k], :], x, n_in,
+                                                                     n_out), w))
+        s_bf, _ = oracle.snr(oracle.boxcar(oracle.dedisperse(d[None], x, n_in, n_out), w))
+        ratio = s_sb[0] / s_bf[0]
+        sigma = sm.noise_sigma(g.n_chan, w)
+        floor = sm.snr_ratio_floor(frac, peak_bf, sigma, w, n_out)
+        assert floor <= ratio <= 1.0 + 5.0 * sigma / peak_bf, (j, k, w, frac, floor, ratio)
 
 
 def test_boxcar_identity_doubling_and_convolve():

@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
+import subband_smearing
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -228,3 +229,46 @@ def test_subband_tune_on_device_keeps_parity(amber, torch):
     assert res.n_evals > 0 and res.best_time_s > 0
     got = amber.subband_dedisperse(d1d, d2d, info, xd, n_in, n_out, tiles1=res.step1, tiles2=res.step2).cpu().numpy()
     assert np.array_equal(got, oracle.subband_dedisperse(o1, o2, x, n_in, n_out))
+
+
+@pytest.mark.parametrize("grid_name", sorted(subband_smearing.GRIDS))
+def test_subband_snr_loss_within_smearing_bound(amber, torch, grid_name):
+    """Pulses on the 1536-channel beam through the device's subband path, on
+    the beam's own grid and on Table 2's grid spacing: a pulse alone comes out
+    of its trial exactly as the tables' shift errors smear it, and with noise
+    the device's S/N at the pulse's width, over the oracle's brute-force S/N
+    of the same input, stays between the floor that smearing allows (noise
+    margins included) and 1 plus the noise margin."""
+    sm = subband_smearing
+    grid, pulses = sm.GRIDS[grid_name]
+    g = BEAM
+    f, ts, n_out, amp = g.freqs(), g.t_samp_s, sm.BEAM_N_OUT, sm.PULSE_AMP
+    d1, d2, info = amber.subband_delay_tables(f, ts, *grid)
+    shifts = [sm.pulse_shifts(f, ts, grid, j, k) for j, k, _, _ in pulses]
+    n_in = n_out + max(info.max_delay, max(int(d.max()) for _, _, d in shifts))
+    stride = workloads.padded_stride(n_in)
+    x = workloads.noise(g.n_chan, n_in, stride, seed=77)
+    for (j, k, w, t0), (e, resid, d) in zip(pulses, shifts):
+        workloads.inject(x, d, t0=t0, width=w, amp=amp)
+    d1d, d2d = torch.from_numpy(d1).cuda(), torch.from_numpy(d2).cuda()
+    widths = sorted({p[2] for p in pulses})
+    say("subband smearing", grid_name, info, "n_in", n_in)
+    dd = amber.subband_dedisperse(d1d, d2d, info, torch.from_numpy(x).cuda(), n_in, n_out)
+    s_sb, _ = amber.integrate_snr(dd, n_out, widths)
+    s_sb = s_sb.cpu().numpy()
+    nf = grid[4]
+    for (j, k, w, t0), (e, resid, d) in zip(pulses, shifts):
+        row = j * nf + k
+        one = np.zeros((g.n_chan, stride), np.uint8)
+        workloads.inject(one, d, t0=t0, width=w, amp=amp)
+        got = amber.subband_dedisperse(d1d, d2d, info, torch.from_numpy(one).cuda(), n_in, n_out)[row].cpu().numpy()
+        want = sm.smeared_series(e, t0, w, amp, n_out)
+        assert np.array_equal(got, want), (grid_name, j, k)
+        peak_bf = amp * g.n_chan * w
+        frac = sm.best_boxcar(want, w) / peak_bf
+        s_bf, _ = oracle.snr(oracle.boxcar(oracle.dedisperse(d[None], x, n_in, n_out), w))
+        ratio = float(s_sb[widths.index(w), row]) / s_bf[0]
+        sigma = sm.noise_sigma(g.n_chan, w)
+        floor = sm.snr_ratio_floor(frac, peak_bf, sigma, w, n_out)
+        say("  trial (%d, %d) width %d: collected %.3f, S/N ratio %.3f, floor %.3f" % (j, k, w, frac, ratio, floor))
+        assert floor <= ratio <= 1.0 + 5.0 * sigma / peak_bf, (grid_name, j, k, w, frac, floor, ratio)
