@@ -165,7 +165,8 @@ amber_status amber_validate_tiles(const amber_tiles *tiles, const amber_delay_in
  * frequencies, negative dm_first / dm_step, or delays beyond int32. */
 amber_status amber_delay_table(const amber_geometry *g, int32_t *delays, amber_delay_info *info);
 
-/* Brute-force dedispersion on the device:
+/* Brute-force dedispersion on the device (Section 2: the dedispersion
+ * kernel; Section 5: one-step brute-force dedispersion):
  *     dd[i][t] = sum over c < n_chan of in[c][t + delay[i][c]],  t < n_out
  * integer sums, exact (int32).
  *
@@ -302,7 +303,9 @@ amber_status amber_subband_dedisperse_noalloc(const int32_t *d_delay1, const int
 /* Bytes of the device array amber_subband_dedisperse_noalloc uses. */
 int64_t amber_subband_static_bytes(void);
 
-/* Sliding boxcar integration ("smoothing" of each dedispersed series):
+/* Sliding boxcar integration (the smoothing of each dedispersed series,
+ * Section 2; a sliding window here, the decimation of Table 2 is
+ * amber_downsample):
  *     box[k][i][t] = sum over j < widths[k] of dd[i][t + j],
  *     t < n_out - widths[k] + 1
  * d_dd:  device int32 [n_dm][dd_stride].
@@ -317,7 +320,8 @@ amber_status amber_integrate(const int32_t *d_dd, int32_t n_dm, int64_t dd_strid
                              int32_t *d_box, int64_t box_stride,
                              const amber_tiles *tiles, void *stream);
 
-/* S/N of each boxcar series, over its N = n_out - widths[k] + 1 values:
+/* S/N of each boxcar series (Section 2: the S/N kernel), over its
+ * N = n_out - widths[k] + 1 values:
  *     mean = sum x / N,  std = sqrt(sum (x - mean)^2 / N)   (population)
  *     snr[k][i] = (max x - mean) / std, or 0 when std == 0
  *     peak_t[k][i] = smallest t with x[t] == max x

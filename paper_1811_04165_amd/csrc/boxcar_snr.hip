@@ -366,7 +366,7 @@ __global__ __launch_bounds__(MAXT) void integrate_snr_kernel(BoxJob single, cons
 // row's outputs are cut into blocks of 256 (64 lanes x 4); wavefront v sweeps
 // the blocks [v nb / W, (v + 1) nb / W) in order, on its own (no barrier
 // until the end).  Per step j:
-//  - block j + 1's samples (loaded two steps earlier, 16 B per lane,
+//  - block j + 1's samples (loaded SPAN_NB - 1 steps earlier, 16 B per lane,
 //    coalesced) are centred on c = dd[row][0], prefix-summed across the
 //    wavefront with DPP and written to a two-block LDS ring (slot (j + 1) & 1);
 //    the first entries of slot 0 are repeated after slot 1, so that no read
