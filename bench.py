@@ -1102,7 +1102,8 @@ def peaks_report():
         res["valu"][name] = {"wave_instr_per_s": r.value, "lane_ops_per_s": 64 * r.value,
                              "lanes_per_clk_per_cu": 64 * r.value / (cus * clk)}
     for form, name in enumerate(["ds_read_b32", "ds_read2st64_b32", "ds_read_b64", "ds_read2st64_b64",
-                                 "ds_read_b128"]):
+                                 "ds_read_b128", "ds_read2_b32 (8-byte aligned)", "ds_read2_b32 (4 mod 8)",
+                                 "ds_read_b64 / ds_read2_b32 (4 mod 8) alternating"]):
         r = ctypes.c_double()
         if lib.peaks_lds(form, blocks, 4000, ctypes.c_void_p(out.data_ptr()), ctypes.byref(r)) != 0:
             raise RuntimeError("peaks_lds %s failed" % name)

@@ -29,9 +29,15 @@ COMMON = [
 ]
 
 
+# Per-file flags.  dedisperse.hip: its channel loop branches on wave-uniform
+# conditions only; without this the structurizer turns each 4-way branch into
+# a chain of flow variables and register copies.
+EXTRA = {"dedisperse.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions=true"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + COMMON + EXTRA.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     if src.endswith(".hip"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)

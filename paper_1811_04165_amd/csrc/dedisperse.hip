@@ -16,13 +16,23 @@
 // behind the sums.
 //
 // Accumulation.  Sums of up to 256 channels fit 16 bits, so each dword holds
-// two running sums and one 32-bit add advances both; lane l owns the sample
-// pairs 64k + l of its wave (consecutive lanes read consecutive dwords, so
-// LDS reads are conflict-free and pair up as ds_read2st64).  Every 256
-// channels the packed sums are added into 32-bit totals.  The LDS offset of
-// each channel for the wave's DM is computed once per group by lane j for
-// channel j and broadcast with readlane, so the per-channel cost is one
-// readlane, one address add, the reads and the adds.
+// two running sums and one 32-bit add advances both.  The wave's outputs are
+// cut into blocks of 128 dwords (256 samples); lane l owns dwords 2l and
+// 2l + 1 of each block and reads both with one 8-byte `ds_read_b64`: the LDS
+// serves about 32 lane-addresses per clock, so one 8-byte address per lane
+// moves twice the data of the two-address forms.  Such a read must be 8-byte
+// aligned, which a channel's offset (in dwords) is only when it is even.  For
+// an odd offset m the read starts one dword early, at m - 1: its second
+// dword is the lane's first (added to e0 as for even offsets) and its first
+// dword is lane l - 1's second, so it goes to a third set of sums, od, which
+// is moved one lane down when the packed sums are widened (every 256
+// channels: `wave_shl` DPP, lane 63 taking the next block's lane 0).  The
+// last block's lane 63 has no right neighbour: lane j reads that dword for
+// channel j once per channel group, and the wave's total is added at the end.
+// The offsets' parities are wave-uniform, so each pair of channels takes one
+// of four branches, in which equal targets still share a 3-input add.  The
+// LDS offset of each channel for the wave's DM is computed once per group by
+// lane j for channel j and broadcast with readlane.
 //
 // Subband dedispersion runs on the same kernel.  Step one is a grouped job:
 // every subband is an independent problem over its own channels, and its sums
@@ -39,6 +49,30 @@ namespace {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// acc += a (+ b) as one VALU instruction the compiler cannot merge with
+// others (plain adds in the branches of a switch get their common part moved
+// behind it).
+__device__ __forceinline__ void add_to(uint32_t &acc, uint32_t a)
+{
+    asm("v_add_u32 %0, %1, %0" : "+v"(acc) : "v"(a));
+}
+__device__ __forceinline__ void add3_to(uint32_t &acc, uint32_t a, uint32_t b)
+{
+    asm("v_add3_u32 %0, %1, %2, %0" : "+v"(acc) : "v"(a), "v"(b));
+}
+
+// Sum over the wavefront (every lane gets it): DPP within rows of 16, then
+// across rows through readlane.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, true);   // quad_perm [1,0,3,2]
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, true);   // quad_perm [2,3,0,1]
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, true);  // row_half_mirror
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, true);  // row_mirror
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+}
+
 // The same pointer in the global address space.  Loads through generic
 // pointers become flat loads, which count against the LDS counter too: every
 // wait for an LDS read in the sums would then also wait for the next channel
@@ -50,6 +84,8 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T *global(con
 }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) const u32x2 lds_u2;
 typedef __attribute__((address_space(3))) u32x4 lds_w4;
 typedef __attribute__((address_space(3))) const uint32_t lds_u1;
 
@@ -173,11 +209,25 @@ __device__ __forceinline__ void stage_store(lds_w4 *lds, int win2, int items_per
     }
 }
 
-template <int M, int CU, int MAXI, bool U16, int DPT>
-__global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs,
-                                                          int n_jobs, int tpd, int dpb, int remap)
+// Wavefronts per SIMD the register allocation must allow: 8 (two 1024-item
+// work-groups per CU, at most 64 registers) where the kernel then spills at
+// most a few registers outside the channel loop (the tiles of 4 and 8
+// samples per work-item with shallow staging); elsewhere 1, i.e. no limit
+// (a 1024-item work-group then has a CU to itself).
+template <int M, int MAXI, bool U16, int DPT>
+constexpr int waves_per_simd()
 {
-    static_assert(CU <= 64, "one lane per channel of a group");
+    if (U16) return 1;
+    if (M == 2) return (MAXI <= 2 || (MAXI == 3 && DPT == 1)) ? 8 : 1;
+    if (M == 4) return (MAXI == 1 || (MAXI == 2 && DPT == 1)) ? 8 : 1;
+    return 1;
+}
+
+template <int M, int CU, int MAXI, bool U16, int DPT>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(waves_per_simd<M, MAXI, U16, DPT>())))
+void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int n_jobs, int tpd, int dpb, int remap)
+{
+    static_assert(CU <= 32, "one lane per channel of a group, channel bits in 32-bit masks");
     extern __shared__ u32x4 lds_raw[];
     lds_w4 *lds = (lds_w4 *)lds_raw;
 
@@ -235,11 +285,24 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
 #pragma unroll
     for (int r = 0; r < DPT; ++r) dmine[r] = delays + (size_t)(i + r < n_dm ? i + r : i0) * n_chan;
 
-    uint32_t acc[DPT][M], lo[DPT][M], hi[DPT][M];
+    // Packed 16-bit sums per DM and 128-dword block k of the wave's outputs
+    // (lane l owns dwords 2l and 2l + 1 of each block): e0 / e1 the block's
+    // first / second dword of the lane from even-aligned reads, od the first
+    // dword of odd-aligned reads (it belongs to lane l - 1's second dword).
+    // lo0/hi0/lo1/hi1: the widened 32-bit totals of the lane's four samples.
+    constexpr int K = M / 2;
+    static_assert(M % 2 == 0, "whole 8-byte reads per lane");
+    uint32_t e0[DPT][K], e1[DPT][K], od[DPT][K];
+    uint32_t lo0[DPT][K], hi0[DPT][K], lo1[DPT][K], hi1[DPT][K];
+    // the last block's lane 63 second dword from odd-aligned reads: summed
+    // per channel by lane j (widened at once), reduced after the last group
+    uint32_t fx_lo[DPT], fx_hi[DPT];
 #pragma unroll
-    for (int r = 0; r < DPT; ++r)
+    for (int r = 0; r < DPT; ++r) {
+        fx_lo[r] = fx_hi[r] = 0u;
 #pragma unroll
-        for (int k = 0; k < M; ++k) acc[r][k] = lo[r][k] = hi[r][k] = 0u;
+        for (int k = 0; k < K; ++k) e0[r][k] = e1[r][k] = od[r][k] = lo0[r][k] = hi0[r][k] = lo1[r][k] = hi1[r][k] = 0u;
+    }
 
     // Prefetch of the first channel group: input items, and on lane j < CU the
     // delays of channel j for this wave's DM and for the group's first DM.
@@ -269,7 +332,29 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
         k_next = global(kp)[keep ? c : 0];
     }
 
-    const uint32_t lane_off = 4u * (uint32_t)lane;
+    const uint32_t lane_off = 8u * (uint32_t)lane;
+    const __attribute__((address_space(3))) char *ldsb = (const __attribute__((address_space(3))) char *)lds;
+
+    // Moves the packed sums into the 32-bit totals.  A lane's second dword
+    // from odd-aligned reads is its right neighbour's od (lane 63: the next
+    // block's lane 0; for the last block it is the fx term).
+    auto widen = [&]() {
+#pragma unroll
+        for (int r = 0; r < DPT; ++r)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t nxt = k + 1 < K ? (uint32_t)__builtin_amdgcn_readlane((int)od[r][k + 1], 0) : 0u;
+                // wave_shl:1, lane 63 keeps `nxt`
+                const uint32_t os = (uint32_t)__builtin_amdgcn_update_dpp((int)nxt, (int)od[r][k], 0x130, 0xf, 0xf,
+                                                                          false);
+                lo0[r][k] += e0[r][k] & 0xffffu;
+                hi0[r][k] += e0[r][k] >> 16;
+                lo1[r][k] += (e1[r][k] & 0xffffu) + (os & 0xffffu);
+                hi1[r][k] += (e1[r][k] >> 16) + (os >> 16);
+                e0[r][k] = e1[r][k] = od[r][k] = 0u;
+            }
+    };
+
     int since_flush = 0;
     const int flush_every = U16 ? uniform(job.flush_every) : 256;
     int left = flush_every;  // channels the packed sums may still take (uint16 input)
@@ -277,14 +362,21 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
 #pragma unroll
         for (int m = 0; m < MAXI; ++m)
             stage_store<CU, U16>(lds, win2, sa.items_per_row, sa.n_items, tid + m * nthreads, pre[m], pre_shift[m]);
-        // LDS byte offset of channel `cl` for each of this wave's DMs
-        uint32_t chan_off[DPT];
+        // LDS byte offset of channel `cl` for each of this wave's DMs, rounded
+        // down to 8 bytes, and whether it was odd in dwords (the wave's reads
+        // then start one dword early)
+        uint32_t chan_al[DPT];
+        uint32_t par[DPT];   // bit j: channel j is odd (CU <= 32 on this path's instantiations)
+        bool odd_l[DPT];     // this lane's channel is odd
 #pragma unroll
         for (int r = 0; r < DPT; ++r) {
             int o = d_next[r] - f_next + (f_next & (U16 ? 1 : 3));
             o = o < 0 ? 0 : (o > omax ? omax : o);
-            chan_off[r] = 4u * (uint32_t)(((o & 1) * CU + cl) * win2 + (o >> 1) + (wave_t >> 1));
-            if (keep && k_next == 0) chan_off[r] = zero_off;
+            const uint32_t off = 4u * (uint32_t)(((o & 1) * CU + cl) * win2 + (o >> 1) + (wave_t >> 1));
+            const bool zap = keep && k_next == 0;
+            chan_al[r] = zap ? zero_off : (off & ~7u);
+            odd_l[r] = !zap && (off & 4u) && lane < CU;
+            par[r] = (uint32_t)__builtin_amdgcn_ballot_w64(odd_l[r]);
         }
         __syncthreads();
         // Prefetch of the next group, also after the last one (its items are
@@ -301,39 +393,104 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
         }
 
         if (active) {
-            // channels past n_chan were staged as zeros; their offsets are in range
+            // the last block's lane 63 second dword of the odd channels: lane j
+            // reads it for channel j (the dword after the wave's reads)
 #pragma unroll
-            for (int j = 0; j < CU; ++j) {
+            for (int r = 0; r < DPT; ++r) {
+                const bool odd = odd_l[r];
+                const uint32_t v = *(lds_u1 *)(ldsb + (odd ? chan_al[r] + 512u * K : 0u));
+                fx_lo[r] += odd ? (v & 0xffffu) : 0u;
+                fx_hi[r] += odd ? (v >> 16) : 0u;
+            }
+            if constexpr (!U16 && CU >= 2) {
+                // channel pairs: one branch on both channels' alignment, so
+                // that equal targets still take one 3-input add
 #pragma unroll
-                for (int r = 0; r < DPT; ++r) {
-                    const uint32_t base = __builtin_amdgcn_readlane(chan_off[r], j);
-                    lds_u1 *src =
-                        (lds_u1 *)((__attribute__((address_space(3))) const char *)lds + (base + lane_off));
+                for (int j = 0; j < CU; j += 2) {
 #pragma unroll
-                    for (int k = 0; k < M; ++k) acc[r][k] += src[64 * k];
-                }
-                if (U16 && --left == 0) {
+                    for (int r = 0; r < DPT; ++r) {
+                        const uint32_t ba = (uint32_t)__builtin_amdgcn_readlane((int)chan_al[r], j);
+                        const uint32_t bb = (uint32_t)__builtin_amdgcn_readlane((int)chan_al[r], j + 1);
+                        lds_u2 *pa = (lds_u2 *)(ldsb + (ba + lane_off));
+                        lds_u2 *pb = (lds_u2 *)(ldsb + (bb + lane_off));
+                        u32x2 xa[K], xb[K];
 #pragma unroll
-                    for (int r = 0; r < DPT; ++r)
-#pragma unroll
-                        for (int k = 0; k < M; ++k) {
-                            lo[r][k] += acc[r][k] & 0xffffu;
-                            hi[r][k] += acc[r][k] >> 16;
-                            acc[r][k] = 0u;
+                        for (int k = 0; k < K; ++k) {
+                            // one 8-byte address per lane and read: kept apart, the
+                            // compiler would pair the blocks into a two-address read
+                            xa[k] = pa[64 * k];
+                            xb[k] = pb[64 * k];
+                            asm volatile("" ::: "memory");
                         }
-                    left = flush_every;
+                        // (the adds are written as single instructions so that
+                        // the compiler cannot move the cases' common "e0 +="
+                        // behind the branch, which would cost one more add)
+                        const uint32_t cls = uniform((int)((par[r] >> j) & 3u));
+                        if (cls == 0u) {
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                add3_to(e0[r][k], xa[k].x, xb[k].x);
+                                add3_to(e1[r][k], xa[k].y, xb[k].y);
+                            }
+                        } else if (cls == 3u) {
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                add3_to(e0[r][k], xa[k].y, xb[k].y);
+                                add3_to(od[r][k], xa[k].x, xb[k].x);
+                            }
+                        } else if (cls == 1u) {
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                add3_to(e0[r][k], xa[k].y, xb[k].x);
+                                add_to(e1[r][k], xb[k].y);
+                                add_to(od[r][k], xa[k].x);
+                            }
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                add3_to(e0[r][k], xa[k].x, xb[k].y);
+                                add_to(e1[r][k], xa[k].y);
+                                add_to(od[r][k], xb[k].x);
+                            }
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < CU; ++j) {
+#pragma unroll
+                    for (int r = 0; r < DPT; ++r) {
+                        const uint32_t ba = (uint32_t)__builtin_amdgcn_readlane((int)chan_al[r], j);
+                        lds_u2 *pa = (lds_u2 *)(ldsb + (ba + lane_off));
+                        u32x2 xa[K];
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            xa[k] = pa[64 * k];
+                            asm volatile("" ::: "memory");
+                        }
+                        if (uniform((int)((par[r] >> j) & 1u)) == 0) {
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                add_to(e0[r][k], xa[k].x);
+                                add_to(e1[r][k], xa[k].y);
+                            }
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                add_to(e0[r][k], xa[k].y);
+                                add_to(od[r][k], xa[k].x);
+                            }
+                        }
+                    }
+                    if (U16 && --left == 0) {
+                        widen();
+                        left = flush_every;
+                    }
                 }
             }
             since_flush += CU;
             if ((!U16 && since_flush >= 256) || c0 + CU >= n_chan) {
-#pragma unroll
-                for (int r = 0; r < DPT; ++r)
-#pragma unroll
-                    for (int k = 0; k < M; ++k) {
-                        lo[r][k] += acc[r][k] & 0xffffu;
-                        hi[r][k] += acc[r][k] >> 16;
-                        acc[r][k] = 0u;
-                    }
+                widen();
                 since_flush = 0;
             }
         }
@@ -341,6 +498,15 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
     }
 
     if (!active) return;
+    // the fx terms: summed over the wave, added to lane 63's last block
+#pragma unroll
+    for (int r = 0; r < DPT; ++r) {
+        const uint32_t slo = wave_sum_u32(fx_lo[r]), shi = wave_sum_u32(fx_hi[r]);
+        if (lane == 63) {
+            lo1[r][K - 1] += slo;
+            hi1[r][K - 1] += shi;
+        }
+    }
     const int store_vec = job.store_vec;
 #pragma unroll
     for (int r = 0; r < DPT; ++r) {
@@ -349,25 +515,35 @@ __global__ __launch_bounds__(1024) void dedisperse_kernel(DedispJob single, cons
             uint16_t *__restrict__ out =
                 reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(job.dd) + (size_t)(i + r) * dd_stride * 2);
 #pragma unroll
-            for (int k = 0; k < M; ++k) {
-                const int64_t t = t0 + wave_t + 128 * k + 2 * lane;
-                if (store_vec && t + 2 <= n_out) {
-                    *reinterpret_cast<uint32_t *>(out + t) = lo[r][k] | (hi[r][k] << 16);
-                } else {
-                    if (t < n_out) out[t] = (uint16_t)lo[r][k];
-                    if (t + 1 < n_out) out[t + 1] = (uint16_t)hi[r][k];
+            for (int k = 0; k < K; ++k) {
+                const int64_t t = t0 + wave_t + 256 * k + 4 * lane;
+                const uint32_t v[4] = {lo0[r][k], hi0[r][k], lo1[r][k], hi1[r][k]};
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int64_t th = t + 2 * h;
+                    if (store_vec && th + 2 <= n_out) {
+                        *reinterpret_cast<uint32_t *>(out + th) = v[2 * h] | (v[2 * h + 1] << 16);
+                    } else {
+                        if (th < n_out) out[th] = (uint16_t)v[2 * h];
+                        if (th + 1 < n_out) out[th + 1] = (uint16_t)v[2 * h + 1];
+                    }
                 }
             }
         } else {
             int32_t *__restrict__ out = job.dd + (size_t)(i + r) * dd_stride;
 #pragma unroll
-            for (int k = 0; k < M; ++k) {
-                const int64_t t = t0 + wave_t + 128 * k + 2 * lane;
-                if (store_vec && t + 2 <= n_out) {
-                    *reinterpret_cast<int2 *>(out + t) = make_int2((int)lo[r][k], (int)hi[r][k]);
-                } else {
-                    if (t < n_out) out[t] = (int32_t)lo[r][k];
-                    if (t + 1 < n_out) out[t + 1] = (int32_t)hi[r][k];
+            for (int k = 0; k < K; ++k) {
+                const int64_t t = t0 + wave_t + 256 * k + 4 * lane;
+                const uint32_t v[4] = {lo0[r][k], hi0[r][k], lo1[r][k], hi1[r][k]};
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int64_t th = t + 2 * h;
+                    if (store_vec && th + 2 <= n_out) {
+                        *reinterpret_cast<int2 *>(out + th) = make_int2((int)v[2 * h], (int)v[2 * h + 1]);
+                    } else {
+                        if (th < n_out) out[th] = (int32_t)v[2 * h];
+                        if (th + 1 < n_out) out[th + 1] = (int32_t)v[2 * h + 1];
+                    }
                 }
             }
         }

@@ -59,23 +59,29 @@ __global__ __launch_bounds__(256) void valu_kernel(uint32_t *out, uint32_t seed,
 }
 
 // LDS reads of one form per kernel: 0 ds_read_b32, 1 ds_read2st64_b32,
-// 2 ds_read_b64, 3 ds_read2st64_b64, 4 ds_read_b128.  One asm block per loop
-// trip issues reads of 64 bytes per lane in total (16 x b32, 8 x
-// read2st64_b32, 8 x b64, 4 x read2st64_b64 or 4 x b128) and waits for them
+// 2 ds_read_b64, 3 ds_read2st64_b64, 4 ds_read_b128, 5 ds_read2_b32 of two
+// adjacent dwords at an 8-byte-aligned address, 6 the same 4 bytes further
+// (dwords 1 and 2 of the lane's 8-byte slot, so the pair straddles two
+// slots), 7 forms 2 and 6 alternating.  One asm block per loop trip issues
+// reads of 64 bytes per lane in total (16 x b32, 8 x read2st64_b32, 8 x
+// b64, 4 x read2st64_b64, 4 x b128 or 8 x read2_b32) and waits for them
 // before its outputs are used; lane l reads the words at byte 4 W l of each
 // 256 W-byte block (W = dwords per read), so consecutive lanes touch
 // consecutive words.  The 4 KiB a wave reads per trip move with the trip
-// inside a 16 KiB array (small enough for 32 waves per CU).
+// inside a 16 KiB window of the array; forms 6 and 7 read up to 4 bytes past
+// the window, which the array's 16 extra bytes hold (small enough for 32
+// waves per CU).
 template <int FORM>
 __global__ __launch_bounds__(256) void lds_kernel(uint32_t *out, int iters)
 {
-    constexpr int N = 4096;  // dwords, 16 KiB
-    __shared__ __attribute__((aligned(16))) uint32_t s[N];
-    for (int i = threadIdx.x; i < N; i += blockDim.x) s[i] = (uint32_t)i * 2654435761u;
+    constexpr int N = 4096;  // dwords, 16 KiB read window
+    __shared__ __attribute__((aligned(16))) uint32_t s[N + 4];
+    for (int i = threadIdx.x; i < N + 4; i += blockDim.x) s[i] = (uint32_t)i * 2654435761u;
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t lds0 = (uint32_t)reinterpret_cast<uintptr_t>(s);
     constexpr int W = (FORM == 0 || FORM == 1) ? 1 : (FORM == 4 ? 4 : 2);
+    static_assert(FORM >= 0 && FORM <= 7, "read form");
     uint32_t acc = 0;
     for (int i = 0; i < iters; ++i) {
         const uint32_t addr = lds0 + ((((uint32_t)(i + wave) * 4096u) & (uint32_t)(4 * N - 1)) + 4u * W * lane);
@@ -113,6 +119,26 @@ __global__ __launch_bounds__(256) void lds_kernel(uint32_t *out, int iters)
                          : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
                          : "v"(addr));
             acc ^= (r0.x + r0.y + r0.z + r0.w) ^ (r1.x + r1.y + r1.z + r1.w) ^ (r2.x + r2.y + r2.z + r2.w) ^ (r3.x + r3.y + r3.z + r3.w);
+        }
+        if (FORM >= 5) {
+            // read2_b32 offsets are in dwords (at most 255), so each read
+            // gets its own address register
+            const uint32_t a0 = addr, a1 = addr + 512, a2 = addr + 1024, a3 = addr + 1536, a4 = addr + 2048,
+                           a5 = addr + 2560, a6 = addr + 3072, a7 = addr + 3584;
+            uint2 r0, r1, r2, r3, r4, r5, r6, r7;
+            if (FORM == 5)
+                asm volatile("ds_read2_b32 %0, %8 offset0:0 offset1:1\n\tds_read2_b32 %1, %9 offset0:0 offset1:1\n\tds_read2_b32 %2, %10 offset0:0 offset1:1\n\tds_read2_b32 %3, %11 offset0:0 offset1:1\n\tds_read2_b32 %4, %12 offset0:0 offset1:1\n\tds_read2_b32 %5, %13 offset0:0 offset1:1\n\tds_read2_b32 %6, %14 offset0:0 offset1:1\n\tds_read2_b32 %7, %15 offset0:0 offset1:1\n\ts_waitcnt lgkmcnt(0)"
+                             : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&v"(r4), "=&v"(r5), "=&v"(r6), "=&v"(r7)
+                             : "v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(a4), "v"(a5), "v"(a6), "v"(a7));
+            if (FORM == 6)
+                asm volatile("ds_read2_b32 %0, %8 offset0:1 offset1:2\n\tds_read2_b32 %1, %9 offset0:1 offset1:2\n\tds_read2_b32 %2, %10 offset0:1 offset1:2\n\tds_read2_b32 %3, %11 offset0:1 offset1:2\n\tds_read2_b32 %4, %12 offset0:1 offset1:2\n\tds_read2_b32 %5, %13 offset0:1 offset1:2\n\tds_read2_b32 %6, %14 offset0:1 offset1:2\n\tds_read2_b32 %7, %15 offset0:1 offset1:2\n\ts_waitcnt lgkmcnt(0)"
+                             : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&v"(r4), "=&v"(r5), "=&v"(r6), "=&v"(r7)
+                             : "v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(a4), "v"(a5), "v"(a6), "v"(a7));
+            if (FORM == 7)
+                asm volatile("ds_read_b64 %0, %8\n\tds_read2_b32 %1, %9 offset0:1 offset1:2\n\tds_read_b64 %2, %10\n\tds_read2_b32 %3, %11 offset0:1 offset1:2\n\tds_read_b64 %4, %12\n\tds_read2_b32 %5, %13 offset0:1 offset1:2\n\tds_read_b64 %6, %14\n\tds_read2_b32 %7, %15 offset0:1 offset1:2\n\ts_waitcnt lgkmcnt(0)"
+                             : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&v"(r4), "=&v"(r5), "=&v"(r6), "=&v"(r7)
+                             : "v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(a4), "v"(a5), "v"(a6), "v"(a7));
+            acc ^= (r0.x + r0.y) ^ (r1.x + r1.y) ^ (r2.x + r2.y) ^ (r3.x + r3.y) ^ (r4.x + r4.y) ^ (r5.x + r5.y) ^ (r6.x + r6.y) ^ (r7.x + r7.y);
         }
     }
     if (acc == 0x9e3779b9u) out[blockIdx.x * blockDim.x + threadIdx.x] = acc;
@@ -180,7 +206,8 @@ int peaks_valu(int kind, int blocks, int iters, uint32_t *out, double *winst_per
 }
 
 // LDS read bytes per second of one read form (see lds_kernel: 0 b32,
-// 1 read2st64_b32, 2 b64, 3 read2st64_b64, 4 b128).  `out` is a device
+// 1 read2st64_b32, 2 b64, 3 read2st64_b64, 4 b128, 5 read2_b32 aligned,
+// 6 read2_b32 straddling, 7 b64 and straddling read2_b32 alternating).  `out` is a device
 // buffer of >= blocks * 256 uint32.
 int peaks_lds(int form, int blocks, int iters, uint32_t *out, double *bytes_per_s)
 {
@@ -195,6 +222,9 @@ int peaks_lds(int form, int blocks, int iters, uint32_t *out, double *bytes_per_
     case 2: go(lds_kernel<2>); break;
     case 3: go(lds_kernel<3>); break;
     case 4: go(lds_kernel<4>); break;
+    case 5: go(lds_kernel<5>); break;
+    case 6: go(lds_kernel<6>); break;
+    case 7: go(lds_kernel<7>); break;
     default: return -1;
     }
     if (rc) return rc;
