@@ -178,6 +178,11 @@ amber_status amber_delay_table(const amber_geometry *g, int32_t *delays, amber_d
  *            >= n_out are not written.  n_out = 0 is valid: the arguments
  *            are checked, nothing is launched, and d_dd may be NULL.
  * tiles:     NULL = amber_auto_tiles(info, n_out).
+ * Errors: AMBER_E_SHAPE also when channel_unroll * in_stride >= 2^32 - 64
+ * bytes (the staged kernel addresses a channel group's rows with 32-bit
+ * offsets; tiles with direct_reads have no such limit).  The same limit holds
+ * for amber_dedisperse_masked, the batch and the server's beams, and for both
+ * subband steps (step two's slices of coarse DMs are cut to fit it).
  * Reads stay inside the n_chan * in_stride input bytes and the LDS tile even
  * if the table does not match info; results are then meaningless but the call
  * cannot fault. */

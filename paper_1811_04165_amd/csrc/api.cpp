@@ -382,6 +382,7 @@ amber_status dedisperse_common(const int32_t *d_delays, const amber_delay_info *
     DedispPlan plan;
     s = plan_dedisperse(tiles ? *tiles : chosen, *info, &plan);
     if (s != AMBER_OK) return s;
+    if ((s = check_stage_stride(plan, in_stride)) != AMBER_OK) return s;
     if (n_out == 0) return AMBER_OK;
     if (plan.direct) {
         DedispJob j = make_dedisp_job(plan, d_delays, info->n_dm, info->n_chan, d_in, in_stride, d_dd, dd_stride,

@@ -86,6 +86,7 @@ amber_status amber_batch_create(const amber_beam *beams, int32_t n_beams, const 
         DedispPlan dp;
         BoxcarPlan bp;
         if (s == AMBER_OK) s = plan_dedisperse(t, bm.info, &dp);
+        if (s == AMBER_OK) s = check_stage_stride(dp, bm.in_stride);
         if (s == AMBER_OK) s = plan_boxcar(t, widths, n_widths, bm.n_out, &bp);
         if (s != AMBER_OK) {
             delete b;

@@ -85,6 +85,7 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T *global(con
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef int32_t i32x4v __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) const u32x2 lds_u2;
 typedef __attribute__((address_space(3))) u32x4 lds_w4;
 typedef __attribute__((address_space(3))) const uint32_t lds_u1;
@@ -129,46 +130,59 @@ struct Item {
 };
 
 // Issues the loads of staging items tid + m * nthreads (m < MAXI) of the
-// channel group starting at c0: 16 samples + lookahead each.  No load sits
-// under a branch and nothing here reads a loaded value except the delays, so
-// the input loads stay in flight through the group's sums; stage_store
-// applies what the addresses could not.  An item past the last channel reads
-// channel 0 and is zeroed (shift = dwords).  An item that would end past the
-// buffer is read from the buffer's last whole item and shifted down by
-// `shift` dwords; the dwords past the end become zero (they lie past the last
-// row's samples, so no output < n_out depends on them).  The host guarantees
-// at least one whole item of input (in_bytes >= 4 * dwords).
+// channel group starting at c0: 16 samples + lookahead each.  The loads are
+// buffer loads over the rows from the group's first to the job's last
+// channel, so the hardware range check turns every dword past them (past the
+// last row's samples, or an item past the last channel) into zero; no load sits under a
+// branch and nothing here reads a loaded value except the delays, so the
+// input loads stay in flight through the group's sums.  Offsets are 32-bit
+// from the group's first row: the host keeps channel_unroll * in_stride
+// below 2^32.  An item starting before the buffer (only a table that breaks
+// its contract) reads past its end instead.
 template <bool U16, int MAXI>
 __device__ __forceinline__ void stage_load(const StageArgs &a, int c0, int tid, int nthreads,
-                                           uint32_t (&w)[MAXI][Item<U16>::dwords], int (&shift)[MAXI])
+                                           uint32_t (&w)[MAXI][Item<U16>::dwords])
 {
-    constexpr int NW = Item<U16>::dwords;
-    int df[MAXI], cc[MAXI], itm[MAXI];
-    bool valid[MAXI];
+    int df[MAXI], jj[MAXI], itm[MAXI];
 #pragma unroll
     for (int m = 0; m < MAXI; ++m) {
         const int q = tid + m * nthreads;
         const int j = q / a.items_per_row;
-        const int c = c0 + j;
-        valid[m] = q < a.n_items && c < a.n_chan;
-        cc[m] = valid[m] ? c : 0;
-        itm[m] = valid[m] ? q - j * a.items_per_row : 0;
-        df[m] = global(a.dfirst)[cc[m]];
+        const bool valid = q < a.n_items && c0 + j < a.n_chan;
+        jj[m] = j;
+        itm[m] = q - j * a.items_per_row;
+        df[m] = global(a.dfirst)[valid ? c0 + j : 0];
     }
-    const int64_t last = a.in_bytes - 4 * NW;  // host guarantees >= 0
+    // the range: the group's rows up to the last channel (in a grouped job the
+    // next group's rows follow) and not past the buffer
+    const int64_t start = (int64_t)c0 * a.in_stride;  // wave-uniform
+    int64_t rest = a.in_bytes - start;
+    const int64_t rows = (int64_t)(a.n_chan - c0) * a.in_stride;
+    rest = rest < rows ? rest : rows;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t *>(a.in) + (rest > 0 ? start : 0), 0,
+        (int)(uint32_t)(rest <= 0 ? 0 : (rest > 0xffffffffll ? 0xffffffffll : rest)), 0x00020000);
 #pragma unroll
     for (int m = 0; m < MAXI; ++m) {
         // first sample of the window, rounded down to a dword boundary
         const int64_t g0 = (a.t0 + df[m]) & (U16 ? ~(int64_t)1 : ~(int64_t)3);
-        const int64_t off = (int64_t)cc[m] * a.in_stride + (U16 ? 2 : 1) * (g0 + 16 * (int64_t)itm[m]);
-        // the read stays inside the buffer whatever the delays hold; an item
-        // starting before it (only a table that breaks its contract) is zero
-        const int64_t base = off < 0 ? 0 : (off < last ? off : last);
-        const auto *p = global(reinterpret_cast<const uint32_t *>(a.in + base));
-#pragma unroll
-        for (int k = 0; k < NW; ++k) w[m][k] = p[k];
-        const int64_t sh = (off - base) >> 2;
-        shift[m] = (valid[m] && off >= 0) ? (int)(sh < NW ? sh : NW) : NW;
+        const int64_t off = (int64_t)jj[m] * a.in_stride + (U16 ? 2 : 1) * (g0 + 16 * (int64_t)itm[m]);
+        const uint32_t o = (off < 0 || off > 0xffffffefll) ? 0xffffffefu : (uint32_t)off;
+        const i32x4v v0 = __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0);
+        w[m][0] = v0.x;
+        w[m][1] = v0.y;
+        w[m][2] = v0.z;
+        w[m][3] = v0.w;
+        if constexpr (U16) {
+            const i32x4v v1 = __builtin_amdgcn_raw_buffer_load_b128(rs, o + 16u, 0, 0);
+            w[m][4] = v1.x;
+            w[m][5] = v1.y;
+            w[m][6] = v1.z;
+            w[m][7] = v1.w;
+            w[m][8] = __builtin_amdgcn_raw_buffer_load_b32(rs, o + 32u, 0, 0);
+        } else {
+            w[m][4] = __builtin_amdgcn_raw_buffer_load_b32(rs, o + 16u, 0, 0);
+        }
     }
 }
 
@@ -176,19 +190,9 @@ __device__ __forceinline__ void stage_load(const StageArgs &a, int c0, int tid, 
 // copy s, dword m of the item holds samples 2m + s and 2m + s + 1.
 template <int CU, bool U16>
 __device__ __forceinline__ void stage_store(lds_w4 *lds, int win2, int items_per_row, int n_items, int q,
-                                            uint32_t (&w)[Item<U16>::dwords], int shift)
+                                            uint32_t (&w)[Item<U16>::dwords])
 {
-    constexpr int NW = Item<U16>::dwords;
     if (q >= n_items) return;
-    if (shift != 0) {  // rare: past the last channel, or the buffer's tail
-#pragma unroll
-        for (int k = 0; k < NW; ++k) {
-            uint32_t v = 0u;
-#pragma unroll
-            for (int r = 1; r < NW; ++r) v = (k + r < NW && shift == r) ? w[k + r] : v;
-            w[k] = v;
-        }
-    }
     const int j = q / items_per_row;
     const int it = q - j * items_per_row;
 #pragma unroll
@@ -307,8 +311,7 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
     // Prefetch of the first channel group: input items, and on lane j < CU the
     // delays of channel j for this wave's DM and for the group's first DM.
     uint32_t pre[MAXI][Item<U16>::dwords];
-    int pre_shift[MAXI];
-    stage_load<U16, MAXI>(sa, 0, tid, nthreads, pre, pre_shift);
+    stage_load<U16, MAXI>(sa, 0, tid, nthreads, pre);
     const int cl = lane < CU ? lane : CU - 1;
     // Zapped channels (keep flag 0) are staged like any other; their offsets
     // are redirected to a zeroed LDS region of 64 * M dwords after the two
@@ -361,7 +364,7 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
     for (int c0 = 0; c0 < n_chan; c0 += CU) {
 #pragma unroll
         for (int m = 0; m < MAXI; ++m)
-            stage_store<CU, U16>(lds, win2, sa.items_per_row, sa.n_items, tid + m * nthreads, pre[m], pre_shift[m]);
+            stage_store<CU, U16>(lds, win2, sa.items_per_row, sa.n_items, tid + m * nthreads, pre[m]);
         // LDS byte offset of channel `cl` for each of this wave's DMs, rounded
         // down to 8 bytes, and whether it was odd in dwords (the wave's reads
         // then start one dword early)
@@ -383,7 +386,7 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
         // all invalid and read one shared address): a branch here would make
         // the compiler copy the loaded registers at its join and so wait for
         // the loads before the sums.
-        stage_load<U16, MAXI>(sa, c0 + CU, tid, nthreads, pre, pre_shift);
+        stage_load<U16, MAXI>(sa, c0 + CU, tid, nthreads, pre);
         {
             const int c = c0 + CU + cl < n_chan ? c0 + CU + cl : n_chan - 1;
 #pragma unroll
@@ -631,6 +634,14 @@ int xcd_remap_setting()
 }
 
 }  // namespace
+
+amber_status check_stage_stride(const DedispPlan &p, int64_t in_stride)
+{
+    if (!p.direct && (int64_t)p.cu * in_stride > kMaxStageSpan)
+        return fail(AMBER_E_SHAPE, "channel_unroll %d x input row stride %lld bytes exceeds 2^32 (the staged "
+                    "kernel's offsets within a channel group)", p.cu, (long long)in_stride);
+    return AMBER_OK;
+}
 
 DedispJob make_dedisp_job(const DedispPlan &p, const int32_t *d_delays, int n_dm, int n_chan, const uint8_t *d_in,
                           int64_t in_stride, int32_t *d_dd, int64_t dd_stride, int64_t n_out)

@@ -47,6 +47,12 @@ struct DedispPlan {
 };
 
 amber_status plan_dedisperse(const amber_tiles &t, const amber_delay_info &info, DedispPlan *out, int in_u16 = 0);
+// The staged kernel addresses a channel group's input with 32-bit offsets
+// from its first row: channel_unroll * in_stride (bytes) must stay below
+// kMaxStageSpan.  AMBER_E_SHAPE otherwise (the direct-read kernel has no
+// such limit).
+constexpr int64_t kMaxStageSpan = 0xffffffffll - 64;
+amber_status check_stage_stride(const DedispPlan &p, int64_t in_stride);
 // LDS a launch with keep flags adds: the zeroed region zapped channels read
 // (64 lanes x samples_per_thread / 2 dwords).
 inline int64_t mask_lds_bytes(const DedispPlan &p) { return (int64_t)kWave * (p.spt / 2) * 4; }

@@ -583,6 +583,7 @@ amber_status amber_server_add_beam(amber_server *s, const amber_stream_beam *bm,
     b->L = bm->chunk;
     b->D = b->info.max_delay;
     b->stride = round_up(b->D + b->L, 128);
+    if ((st = check_stage_stride(b->dp, b->stride)) != AMBER_OK) return st;
     b->dd_stride = round_up(b->L, 64);
     b->res_off = round_up((int64_t)b->info.n_dm * b->dd_stride * 4, 256);
     b->res_bytes = (int64_t)n_widths * b->info.n_dm * 8;

@@ -207,6 +207,14 @@ amber_status subband_run(const int32_t *d_delay1, const int32_t *d_delay2, const
     if (lds1 > kMaxLdsBytes)
         return fail(AMBER_E_CONFIG, "masked step-one tile needs %lld B of LDS (limit %lld)", (long long)lds1,
                     (long long)kMaxLdsBytes);
+    if ((s = check_stage_stride(p1, in_stride)) != AMBER_OK) return s;
+    // step two's channels are the subband rows of the slice, jn * work_stride
+    // uint16 apart: slices small enough for the staged kernel's offsets
+    if (!p2.direct) {
+        const int64_t most = kMaxStageSpan / ((int64_t)p2.cu * work_stride * 2);
+        if (most < 1) return check_stage_stride(p2, work_stride * 2);
+        if (slice > most) slice = most;
+    }
     if (n_out == 0) return AMBER_OK;
 
     // Both steps over the coarse DMs [j0, j0 + jn): step one's sums of those

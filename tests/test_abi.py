@@ -116,6 +116,7 @@ def test_tile_validation():
 def test_device_calls_validate_before_launch():
     """Invalid arguments are refused on the host, so these never reach a GPU."""
     from paper_1811_04165_amd import _lib
+    from paper_1811_04165_amd import make_tiles as amber_tiles
     lib = _lib.load()
     info = _lib.DelayInfo(n_dm=4, n_chan=8, max_delay=10, max_step=2)
     fake = ctypes.c_void_p(0x1000)
@@ -128,6 +129,14 @@ def test_device_calls_validate_before_launch():
     # NULL input
     rc = lib.amber_dedisperse(fake, ctypes.byref(info), None, 128, 120, fake, 100, 100, None, None)
     assert rc == -1
+    # channel_unroll x row stride past 2^32: the staged kernel's 32-bit offsets within a channel group
+    t = amber_tiles(channel_unroll=16)
+    big = (1 << 28) + 128
+    rc = lib.amber_dedisperse(fake, ctypes.byref(info), fake, big, 120, fake, 100, 100, ctypes.byref(t), None)
+    assert rc == -2 and b"2^32" in lib.amber_last_error()
+    t_direct = amber_tiles(channel_unroll=16, direct_reads=1, dms_per_thread=1)
+    rc = lib.amber_dedisperse(fake, ctypes.byref(info), fake, big, 120, fake, 100, 0, ctypes.byref(t_direct), None)
+    assert rc == 0       # n_out = 0: checked, nothing launched; the direct kernel has no such limit
     # masked: NULL keep flags, and the plain checks still apply
     rc = lib.amber_dedisperse_masked(fake, ctypes.byref(info), fake, 128, 120, fake, 100, 100, None, None, None)
     assert rc == -1 and b"d_keep" in lib.amber_last_error()
