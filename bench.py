@@ -132,13 +132,15 @@ def _point_space(search, tiles):
 def time_configs(search, x, configs, reps: int):
     """Median GPU time of dedisperse + fused boxcar/S/N for each configuration,
     measured as the searches measure fitness (the library's timer: HIP events
-    around the two launches made from native code, after one untimed run),
-    one run per configuration per round, round robin, so drifts hit all alike.
+    around the two launches made from native code; one measurement is the
+    median of 3 back-to-back runs after an untimed one, so the configuration
+    runs with its own code and data warm, as in a pipeline), `reps` rounds,
+    the configurations round robin within a round so drifts hit all alike.
     (Events around launches made from Python would add the interpreter's
     per-call time, which is larger than these kernels.)"""
     import paper_1811_04165_amd as amber
     spaces = [_point_space(search, t) for t in configs]
-    params = amber.tune_params("exhaustive", warmup=1, reps=1)
+    params = amber.tune_params("exhaustive", warmup=1, reps=3)
     bufs = (search.dd, search.snr, search.peak)
     times = [[] for _ in configs]
     gc.collect()
@@ -218,21 +220,36 @@ def tune_report(seeds: int, log_path=None):
     ga = [run("ga", seed=s) for s in range(1, seeds + 1)]
     gas = [run("ga", seed=s, seed_default=1) for s in range(1, seeds + 1)]   # initial population holds the defaults
     gar = {ra: [run("ga", seed=s, restart_after=ra) for s in range(1, seeds + 1)] for ra in GA_RESTART_SWEEP}
+    # the search's best GA_RETIME[0] configurations re-timed GA_RETIME[1] times each at its end
+    gat = [run("ga", seed=s, retime_top=GA_RETIME[0], retime_runs=GA_RETIME[1]) for s in range(1, seeds + 1)]
+    gart = [run("ga", seed=s, restart_after=GA_RESTART_AFTER, retime_top=GA_RETIME[0], retime_runs=GA_RETIME[1])
+            for s in range(1, seeds + 1)]
     rnd = [run("random", seed=100 + s, max_evals=ga[s - 1].n_evals) for s in range(1, seeds + 1)]
     pk = run("per_kernel")
-    ex = run("exhaustive", reps=1, warmup=1)
+    ex = run("exhaustive")
     finalists = [r.best for r in ga] + [r.best for r in rnd] + [pk.best, ex.best] + [r.best for r in gas] + \
-        [r.best for ra in GA_RESTART_SWEEP for r in gar[ra]]
+        [r.best for ra in GA_RESTART_SWEEP for r in gar[ra]] + [r.best for r in gat] + [r.best for r in gart]
     print("[bench] interleaved re-timing of %d finalists" % len(finalists), file=sys.stderr, flush=True)
     t = time_configs(search, x, finalists, reps=100)
     n = seeds
     t_ga, t_rnd, t_pk, t_ex = t[:n], t[n:2 * n], t[2 * n], t[2 * n + 1]
     t_gas = t[2 * n + 2:3 * n + 2]
     t_gar = {ra: t[(3 + k) * n + 2:(4 + k) * n + 2] for k, ra in enumerate(GA_RESTART_SWEEP)}
+    k0 = (3 + len(GA_RESTART_SWEEP)) * n + 2
+    t_gat, t_gart = t[k0:k0 + n], t[k0 + n:k0 + 2 * n]
     nw = len(wl.widths)
     out.update({
         "retimed_s": {"ga": t_ga, "random": t_rnd, "per_kernel": t_pk, "exhaustive": t_ex, "ga_seeded": t_gas,
-                      "ga_restart": {str(ra): t_gar[ra] for ra in GA_RESTART_SWEEP}},
+                      "ga_restart": {str(ra): t_gar[ra] for ra in GA_RESTART_SWEEP}, "ga_retime": t_gat,
+                      "ga_restart_retime": t_gart},
+        "ga_retime": {"retime_top": GA_RETIME[0], "retime_runs": GA_RETIME[1],
+                      "median_over_exhaustive": statistics.median(t_gat) / t_ex, "worst_over_exhaustive": max(t_gat) / t_ex,
+                      "evals_median": statistics.median([r.n_evals for r in gat]),
+                      "wall_s_median": statistics.median([r.wall_s for r in gat]),
+                      "with_restart_after": GA_RESTART_AFTER,
+                      "with_restart_median_over_exhaustive": statistics.median(t_gart) / t_ex,
+                      "with_restart_worst_over_exhaustive": max(t_gart) / t_ex,
+                      "with_restart_evals_median": statistics.median([r.n_evals for r in gart])},
         "ga_median_over_exhaustive": statistics.median(t_ga) / t_ex,
         "ga_worst_over_exhaustive": max(t_ga) / t_ex,
         "ga_seeded_median_over_exhaustive": statistics.median(t_gas) / t_ex,
@@ -529,6 +546,7 @@ def serve_report(n_beams: int, seconds: float, warmup_s: float, rates, submitter
 
 GA_RESTART_AFTER = 5   # generations without a better best before the GA re-draws its population
 GA_RESTART_SWEEP = (3, 5, 8)
+GA_RETIME = (8, 5)     # (configurations, runs each) re-timed at the end of a search
 GA_STUDY_BASE = dict(pop=20, p_cross=0.8, p_mut=0.1, crossover=0)
 
 

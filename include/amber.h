@@ -443,6 +443,14 @@ typedef struct {
                               fitness has not improved for n generations, every
                               individual but the best is replaced by a fresh random
                               valid one (an addition for robustness across seeds) */
+    int32_t retime_top;   /* any search: 0 (the paper's form) = off; n > 0 = after the
+                             search, the n distinct configurations with the best
+                             measured fitness are evaluated retime_runs more times
+                             each, round robin, and the one with the lowest median is
+                             returned (its median as best_time_s); these runs count
+                             in n_evals.  A search otherwise ends on its luckiest
+                             measurement, which need not be the fastest configuration. */
+    int32_t retime_runs;  /* runs per configuration when retime_top > 0, 1 ..= 64 */
 } amber_tune_params;
 
 typedef struct {

@@ -94,7 +94,8 @@ class TuneParams(ctypes.Structure):
                 ("crossover", ctypes.c_int32), ("p_cross", ctypes.c_double), ("p_mut", ctypes.c_double),
                 ("pool_frac", ctypes.c_double), ("seed", ctypes.c_uint64), ("warmup", ctypes.c_int32),
                 ("reps", ctypes.c_int32), ("eval_timeout_s", ctypes.c_double), ("max_evals", ctypes.c_int64),
-                ("seed_default", ctypes.c_int32), ("restart_after", ctypes.c_int32)]
+                ("seed_default", ctypes.c_int32), ("restart_after", ctypes.c_int32),
+                ("retime_top", ctypes.c_int32), ("retime_runs", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):

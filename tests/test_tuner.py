@@ -247,3 +247,33 @@ def test_ga_restart_on_stagnation(amber, tmp_path):
     # restarts spend evaluations on fresh genomes: more than the paper's form
     r0 = amber.search_tiles(sp, amber.tune_params("ga", seed=3, pop=8, generations=30), fit)
     assert r1.n_evals > r0.n_evals
+
+
+def test_retime_top_corrects_a_lucky_measurement(amber, tmp_path):
+    """retime_top: a configuration whose first measurement was lucky (0.9 of
+    its true time) wins the search; re-timing the best few picks the truly
+    fastest one instead, logs the re-timed medians and counts the runs."""
+    sp, info, widths = _small_space(amber)
+    valid = _all_valid(amber, sp, widths)
+    truth = {c: 1e-4 * (1.0 + 0.01 * k) for k, c in enumerate(valid)}   # valid[0] is the fastest
+    lucky = valid[1]
+    calls = {}
+
+    def fit(t):
+        c = _tiles_key(t, len(widths))
+        calls[c] = calls.get(c, 0) + 1
+        v = truth[c]
+        return 0.9 * v if (c == lucky and calls[c] == 1) else v
+
+    plain = amber.search_tiles(sp, amber.tune_params("exhaustive"), fit)
+    assert _tiles_key(plain.best, len(widths)) == lucky
+    calls.clear()
+    log = tmp_path / "retime.jsonl"
+    r = amber.search_tiles(sp, amber.tune_params("exhaustive", retime_top=4, retime_runs=3), fit, log_path=str(log))
+    assert _tiles_key(r.best, len(widths)) == valid[0]
+    assert r.best_time_s == pytest.approx(truth[valid[0]])
+    assert r.n_evals == len(valid) + 4 * 3
+    rec = [json.loads(l) for l in log.read_text().splitlines() if "retime" in l][-1]["retime"]
+    assert len(rec) == 4 and rec[0]["search_s"] == pytest.approx(0.9 * truth[lucky])
+    with pytest.raises(amber.AmberError):
+        amber.search_tiles(sp, amber.tune_params("ga", retime_top=2, retime_runs=0), fit)
