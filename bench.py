@@ -40,8 +40,8 @@ VALU_LANES_PER_CLK = 64
 ALU_PEAK_TOPS = 256 * VALU_LANES_PER_CLK * 2.4e9 * 2 / 1e12
 
 # LDS reads: 256 B/clk/CU (CDNA4 doubled CDNA3's 128) = 157.3 TB/s; measured
-# ds_read_b128 209 B/clk/CU, ds_read_b64 194, and the 32-bit forms the
-# dedispersion kernel issues (ds_read_b32, ds_read2st64_b32) 113-120
+# ds_read_b128 209 B/clk/CU, ds_read_b64 (the dedispersion kernel's sums) 194,
+# the 32-bit forms (ds_read_b32, ds_read2st64_b32) 113-120
 LDS_PEAK_TBS = 256 * 256 * 2.4e9 / 1e12
 
 METRIC = "DM-trial·samples/s per GPU + % HBM roofline; GA tune time; p99 chunk latency"
