@@ -11,9 +11,11 @@
 // DMs read at most (dpb - 1) * max_step samples further in).  Samples are
 // widened from uint8 to 16 bits and stored twice, the second copy shifted by
 // one sample, so the two samples at any offset are one aligned dword of one of
-// the copies.  The global loads of the next channel group (input and delays)
-// are issued before the current group is summed, so their latency hides
-// behind the sums.
+// the copies.  A work-item stages two 8-sample chunks half a row apart, so
+// that each write instruction covers consecutive 16-byte lines across the
+// lanes (all LDS banks).  The global loads of the next channel group (input
+// and delays, as range-checked buffer loads with 32-bit offsets) are issued
+// before the current group is summed, so their latency hides behind the sums.
 //
 // Accumulation.  Sums of up to 256 channels fit 16 bits, so each dword holds
 // two running sums and one 32-bit add advances both.  The wave's outputs are
@@ -73,16 +75,6 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
            (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
 }
 
-// The same pointer in the global address space.  Loads through generic
-// pointers become flat loads, which count against the LDS counter too: every
-// wait for an LDS read in the sums would then also wait for the next channel
-// group's prefetch, and the two could never overlap.
-template <class T>
-__device__ __forceinline__ const __attribute__((address_space(1))) T *global(const T *p)
-{
-    return (const __attribute__((address_space(1))) T *)p;
-}
-
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef int32_t i32x4v __attribute__((ext_vector_type(4)));
@@ -123,71 +115,91 @@ struct StageArgs {
     int n_chan, items_per_row, n_items;
 };
 
-// Dwords one staging item loads: 16 samples and one dword of lookahead.
+// A staging item is two chunks of 8 samples half a row apart (chunks it and
+// it + items_per_row of its row), each loaded with one dword of lookahead:
+// the item's writes of one chunk and copy then cover consecutive 16-byte
+// lines across the lanes, which reach every LDS bank.
 template <bool U16>
 struct Item {
-    static constexpr int dwords = U16 ? 9 : 5;
+    static constexpr int chunk = U16 ? 5 : 3;  // dwords per chunk
+    static constexpr int dwords = 2 * chunk;
+};
+
+// A buffer resource over n bytes from p: loads past the end read zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t range_rsrc(const void *p, uint32_t n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)n, 0x00020000);
+}
+
+// Per-item constants of the staging loads: byte offset of the item's first
+// sample within the group's rows, apart from the first DM's delay, and the
+// byte offset of the item's channel in a delay row (from the group's first).
+template <bool U16, int MAXI>
+struct ItemBase {
+    uint32_t off[MAXI], dch[MAXI];
 };
 
 // Issues the loads of staging items tid + m * nthreads (m < MAXI) of the
-// channel group starting at c0: 16 samples + lookahead each.  The loads are
-// buffer loads over the rows from the group's first to the job's last
-// channel, so the hardware range check turns every dword past them (past the
-// last row's samples, or an item past the last channel) into zero; no load sits under a
-// branch and nothing here reads a loaded value except the delays, so the
-// input loads stay in flight through the group's sums.  Offsets are 32-bit
-// from the group's first row: the host keeps channel_unroll * in_stride
-// below 2^32.  An item starting before the buffer (only a table that breaks
-// its contract) reads past its end instead.
-template <bool U16, int MAXI>
-__device__ __forceinline__ void stage_load(const StageArgs &a, int c0, int tid, int nthreads,
+// channel group starting at c0: two chunks of 8 samples + lookahead each.
+// The loads are buffer loads over the group's rows up to the job's last
+// channel (and the delays of those channels), so the hardware range check
+// turns every dword past them (past the last row's samples, or an item past
+// the last channel) into zero; no load sits under a branch and nothing here
+// reads a loaded value except the delays, so the input loads stay in flight
+// through the group's sums (buffer loads count against the vector-memory
+// counter only: flat loads through generic pointers would also count against
+// the LDS one, and every wait for a sum's LDS read would wait for them).  Offsets are 32-bit from the group's first row:
+// the host keeps channel_unroll * in_stride below 2^32, and a window that
+// runs past its row's end (or wraps, or starts before the buffer for a table
+// that breaks its contract) only feeds outputs at or past n_out.
+template <int CU, bool U16, int MAXI>
+__device__ __forceinline__ void stage_load(const StageArgs &a, int c0, const ItemBase<U16, MAXI> &ib,
                                            uint32_t (&w)[MAXI][Item<U16>::dwords])
 {
-    int df[MAXI], jj[MAXI], itm[MAXI];
+    const int left = a.n_chan - c0;  // channels from c0 to the job's last one
+    const __amdgpu_buffer_rsrc_t rd = range_rsrc(a.dfirst + c0, left > 0 ? 4u * (uint32_t)left : 0u);
+    int df[MAXI];
 #pragma unroll
-    for (int m = 0; m < MAXI; ++m) {
-        const int q = tid + m * nthreads;
-        const int j = q / a.items_per_row;
-        const bool valid = q < a.n_items && c0 + j < a.n_chan;
-        jj[m] = j;
-        itm[m] = q - j * a.items_per_row;
-        df[m] = global(a.dfirst)[valid ? c0 + j : 0];
-    }
-    // the range: the group's rows up to the last channel (in a grouped job the
-    // next group's rows follow) and not past the buffer
+    for (int m = 0; m < MAXI; ++m) df[m] = __builtin_amdgcn_raw_buffer_load_b32(rd, ib.dch[m], 0, 0);
+    // the range: the group's rows, not past the job's last channel (in a
+    // grouped job the next group's rows follow) nor past the buffer; in 32
+    // bits, as CU rows are below 2^32 bytes
     const int64_t start = (int64_t)c0 * a.in_stride;  // wave-uniform
-    int64_t rest = a.in_bytes - start;
-    const int64_t rows = (int64_t)(a.n_chan - c0) * a.in_stride;
-    rest = rest < rows ? rest : rows;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<uint8_t *>(a.in) + (rest > 0 ? start : 0), 0,
-        (int)(uint32_t)(rest <= 0 ? 0 : (rest > 0xffffffffll ? 0xffffffffll : rest)), 0x00020000);
+    const int64_t rest = a.in_bytes - start;
+    const uint32_t rows = left <= 0 ? 0u : (uint32_t)(left < CU ? left : CU) * (uint32_t)a.in_stride;
+    const int rest_hi = (int)(rest >> 32);
+    const uint32_t n = rest_hi < 0 ? 0u : (rest_hi > 0 ? rows : min((uint32_t)rest, rows));
+    const __amdgpu_buffer_rsrc_t rs = range_rsrc(a.in + (n ? start : 0), n);
+    const uint32_t half = (U16 ? 16u : 8u) * (uint32_t)a.items_per_row;  // bytes between the chunks
 #pragma unroll
     for (int m = 0; m < MAXI; ++m) {
-        // first sample of the window, rounded down to a dword boundary
-        const int64_t g0 = (a.t0 + df[m]) & (U16 ? ~(int64_t)1 : ~(int64_t)3);
-        const int64_t off = (int64_t)jj[m] * a.in_stride + (U16 ? 2 : 1) * (g0 + 16 * (int64_t)itm[m]);
-        const uint32_t o = (off < 0 || off > 0xffffffefll) ? 0xffffffefu : (uint32_t)off;
-        const i32x4v v0 = __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0);
-        w[m][0] = v0.x;
-        w[m][1] = v0.y;
-        w[m][2] = v0.z;
-        w[m][3] = v0.w;
-        if constexpr (U16) {
-            const i32x4v v1 = __builtin_amdgcn_raw_buffer_load_b128(rs, o + 16u, 0, 0);
-            w[m][4] = v1.x;
-            w[m][5] = v1.y;
-            w[m][6] = v1.z;
-            w[m][7] = v1.w;
-            w[m][8] = __builtin_amdgcn_raw_buffer_load_b32(rs, o + 32u, 0, 0);
-        } else {
-            w[m][4] = __builtin_amdgcn_raw_buffer_load_b32(rs, o + 16u, 0, 0);
+        // first sample of the window, rounded down to a dword boundary (t0 is
+        // a multiple of 4)
+        const uint32_t o = ib.off[m] + (U16 ? ((uint32_t)df[m] << 1) & ~3u : (uint32_t)df[m] & ~3u);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t oh = o + (h ? half : 0u);
+            uint32_t *d = &w[m][h * Item<U16>::chunk];
+            if constexpr (U16) {
+                const i32x4v v = __builtin_amdgcn_raw_buffer_load_b128(rs, oh, 0, 0);
+                d[0] = v.x;
+                d[1] = v.y;
+                d[2] = v.z;
+                d[3] = v.w;
+                d[4] = __builtin_amdgcn_raw_buffer_load_b32(rs, oh + 16u, 0, 0);
+            } else {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, oh, 0, 0);
+                d[0] = v[0];
+                d[1] = v[1];
+                d[2] = v[2];
+            }
         }
     }
 }
 
-// Writes staging item q (16 samples) as 16-bit values into the two copies:
-// copy s, dword m of the item holds samples 2m + s and 2m + s + 1.
+// Writes staging item q (two chunks of 8 samples) as 16-bit values into the
+// two copies: copy s, dword m of a chunk holds its samples 2m + s and
+// 2m + s + 1.
 template <int CU, bool U16>
 __device__ __forceinline__ void stage_store(lds_w4 *lds, int win2, int items_per_row, int n_items, int q,
                                             uint32_t (&w)[Item<U16>::dwords])
@@ -195,21 +207,30 @@ __device__ __forceinline__ void stage_store(lds_w4 *lds, int win2, int items_per
     if (q >= n_items) return;
     const int j = q / items_per_row;
     const int it = q - j * items_per_row;
+    // the copy and chunk distances pass through an SGPR move the compiler
+    // cannot hoist, so that the four write addresses are formed here from one
+    // base instead of living in registers (or scratch) across the loop
+    int copy_w4 = (CU * win2) >> 2, half_w4 = items_per_row;
+    asm volatile("s_mov_b32 %0, %0" : "+s"(copy_w4));
+    asm volatile("s_mov_b32 %0, %0" : "+s"(half_w4));
+    lds = lds + ((j * win2) >> 2) + it;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        uint32_t d[8];
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t *c = &w[h * Item<U16>::chunk];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            if (U16) {  // samples 2m + s, 2m + s + 1 of the item's dwords
-                d[m] = s == 0 ? w[m] : __builtin_amdgcn_alignbyte(w[m + 1], w[m], 2);
-            } else {
-                const int p = 2 * m + s;  // first byte of the pair within the 20 bytes
-                d[m] = __builtin_amdgcn_perm(w[(p >> 2) + 1], w[p >> 2], widen_sel(p & 3));
+        for (int s = 0; s < 2; ++s) {
+            uint32_t d[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                if (U16) {  // samples 2m + s, 2m + s + 1 of the chunk's dwords
+                    d[m] = s == 0 ? c[m] : __builtin_amdgcn_alignbyte(c[m + 1], c[m], 2);
+                } else {
+                    const int p = 2 * m + s;  // first byte of the pair within the 12 bytes
+                    d[m] = __builtin_amdgcn_perm(c[(p >> 2) + 1], c[p >> 2], widen_sel(p & 3));
+                }
             }
+            lds[s * copy_w4 + h * half_w4] = u32x4{d[0], d[1], d[2], d[3]};
         }
-        lds_w4 *dst = lds + (((s * CU + j) * win2) >> 2) + 2 * it;
-        dst[0] = u32x4{d[0], d[1], d[2], d[3]};
-        dst[1] = u32x4{d[4], d[5], d[6], d[7]};
     }
 }
 
@@ -299,19 +320,31 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
     uint32_t e0[DPT][K], e1[DPT][K], od[DPT][K];
     uint32_t lo0[DPT][K], hi0[DPT][K], lo1[DPT][K], hi1[DPT][K];
     // the last block's lane 63 second dword from odd-aligned reads: summed
-    // per channel by lane j (widened at once), reduced after the last group
-    uint32_t fx_lo[DPT], fx_hi[DPT];
+    // per channel by lane j into packed sums fx, which each widening sums
+    // over the wave into lane 63's totals
+    uint32_t fx[DPT];
 #pragma unroll
     for (int r = 0; r < DPT; ++r) {
-        fx_lo[r] = fx_hi[r] = 0u;
+        fx[r] = 0u;
 #pragma unroll
         for (int k = 0; k < K; ++k) e0[r][k] = e1[r][k] = od[r][k] = lo0[r][k] = hi0[r][k] = lo1[r][k] = hi1[r][k] = 0u;
     }
 
     // Prefetch of the first channel group: input items, and on lane j < CU the
     // delays of channel j for this wave's DM and for the group's first DM.
+    ItemBase<U16, MAXI> ib;
+#pragma unroll
+    for (int m = 0; m < MAXI; ++m) {
+        const int q = tid + m * nthreads;
+        const int j = q / sa.items_per_row;
+        const int it = q - j * sa.items_per_row;
+        // (an item past the last one, never stored, may wrap: its loads stay
+        // range-checked)
+        ib.off[m] = (uint32_t)j * (uint32_t)sa.in_stride + (U16 ? 2u : 1u) * ((uint32_t)t0 + 8u * (uint32_t)it);
+        ib.dch[m] = 4u * (uint32_t)j;
+    }
     uint32_t pre[MAXI][Item<U16>::dwords];
-    stage_load<U16, MAXI>(sa, 0, tid, nthreads, pre);
+    stage_load<CU, U16, MAXI>(sa, 0, ib, pre);
     const int cl = lane < CU ? lane : CU - 1;
     // Zapped channels (keep flag 0) are staged like any other; their offsets
     // are redirected to a zeroed LDS region of 64 * M dwords after the two
@@ -325,17 +358,27 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
     }
     // keep flags are read unconditionally (from the delay table when there
     // are none) so that no load sits under a branch
+    // Delays (and keep flags) of channel c0 + lane for the group at c0:
+    // buffer loads over the rest of each row, zero past the last channel (a
+    // channel there is staged from zeros, so any offset in range adds nothing).
     const uint8_t *kp = keep ? keep : reinterpret_cast<const uint8_t *>(delays);
     int d_next[DPT], f_next = 0, k_next = 1;
-    {
-        const int c = cl < n_chan ? cl : n_chan - 1;
-#pragma unroll
-        for (int r = 0; r < DPT; ++r) d_next[r] = global(dmine[r])[c];
-        f_next = global(sa.dfirst)[c];
-        k_next = global(kp)[keep ? c : 0];
-    }
-
     const uint32_t lane_off = 8u * (uint32_t)lane;
+    auto load_delays = [&](int c) {
+        const uint32_t lane4 = lane_off >> 1;
+        const uint32_t rest = c < n_chan ? (uint32_t)(n_chan - c) : 0u;
+#pragma unroll
+        for (int r = 0; r < DPT; ++r)
+            d_next[r] = __builtin_amdgcn_raw_buffer_load_b32(range_rsrc(dmine[r] + c, 4u * rest), lane4, 0, 0);
+        f_next = __builtin_amdgcn_raw_buffer_load_b32(range_rsrc(sa.dfirst + c, 4u * rest), lane4, 0, 0);
+        k_next = __builtin_amdgcn_raw_buffer_load_b8(range_rsrc(kp + c, keep ? rest : 0u), (uint32_t)lane, 0, 0);
+    };
+    load_delays(0);
+    // LDS byte offset of channel cl's window at offset 0 in copy 0 for this
+    // wave, and the distance to copy 1 (its dword count is a multiple of 8)
+    const uint32_t lane_base = 4u * (uint32_t)(cl * win2 + (wave_t >> 1));
+    const uint32_t copy1 = 4u * (uint32_t)(CU * win2);
+
     const __attribute__((address_space(3))) char *ldsb = (const __attribute__((address_space(3))) char *)lds;
 
     // Moves the packed sums into the 32-bit totals.  A lane's second dword
@@ -356,6 +399,15 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
                 hi1[r][k] += (e1[r][k] >> 16) + (os >> 16);
                 e0[r][k] = e1[r][k] = od[r][k] = 0u;
             }
+#pragma unroll
+        for (int r = 0; r < DPT; ++r) {
+            const uint32_t slo = wave_sum_u32(fx[r] & 0xffffu), shi = wave_sum_u32(fx[r] >> 16);
+            if (lane == 63) {
+                lo1[r][K - 1] += slo;
+                hi1[r][K - 1] += shi;
+            }
+            fx[r] = 0u;
+        }
     };
 
     int since_flush = 0;
@@ -371,14 +423,19 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
         uint32_t chan_al[DPT];
         uint32_t par[DPT];   // bit j: channel j is odd (CU <= 32 on this path's instantiations)
         bool odd_l[DPT];     // this lane's channel is odd
+        const int fa = (f_next & (U16 ? 1 : 3)) - f_next;
+        const bool zap = keep && k_next == 0;
+        const bool mine = !zap && lane < CU;
 #pragma unroll
         for (int r = 0; r < DPT; ++r) {
-            int o = d_next[r] - f_next + (f_next & (U16 ? 1 : 3));
-            o = o < 0 ? 0 : (o > omax ? omax : o);
-            const uint32_t off = 4u * (uint32_t)(((o & 1) * CU + cl) * win2 + (o >> 1) + (wave_t >> 1));
-            const bool zap = keep && k_next == 0;
-            chan_al[r] = zap ? zero_off : (off & ~7u);
-            odd_l[r] = !zap && (off & 4u) && lane < CU;
+            const int oo = d_next[r] + fa;
+            const int o = min(max(oo, 0), omax);
+            // copy o & 1, dword o >> 1: rounded down to 8 bytes, and whether
+            // the dword was odd
+            const uint32_t h = (uint32_t)o >> 1;
+            const uint32_t cb = lane_base + ((uint32_t)o & 1u) * copy1;
+            chan_al[r] = zap ? zero_off : cb + 4u * (h & ~1u);
+            odd_l[r] = mine && (h & 1u);
             par[r] = (uint32_t)__builtin_amdgcn_ballot_w64(odd_l[r]);
         }
         __syncthreads();
@@ -386,24 +443,19 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
         // all invalid and read one shared address): a branch here would make
         // the compiler copy the loaded registers at its join and so wait for
         // the loads before the sums.
-        stage_load<U16, MAXI>(sa, c0 + CU, tid, nthreads, pre);
-        {
-            const int c = c0 + CU + cl < n_chan ? c0 + CU + cl : n_chan - 1;
-#pragma unroll
-            for (int r = 0; r < DPT; ++r) d_next[r] = global(dmine[r])[c];
-            f_next = global(sa.dfirst)[c];
-            k_next = global(kp)[keep ? c : 0];
-        }
+        stage_load<CU, U16, MAXI>(sa, c0 + CU, ib, pre);
+        load_delays(c0 + CU);
 
         if (active) {
             // the last block's lane 63 second dword of the odd channels: lane j
             // reads it for channel j (the dword after the wave's reads)
 #pragma unroll
             for (int r = 0; r < DPT; ++r) {
+                // (even lanes read a dword of the window they never use: the
+                // address stays in range)
                 const bool odd = odd_l[r];
-                const uint32_t v = *(lds_u1 *)(ldsb + (odd ? chan_al[r] + 512u * K : 0u));
-                fx_lo[r] += odd ? (v & 0xffffu) : 0u;
-                fx_hi[r] += odd ? (v >> 16) : 0u;
+                const uint32_t v = *(lds_u1 *)(ldsb + (odd ? chan_al[r] : 0u) + 512u * K);
+                fx[r] += odd ? v : 0u;
             }
             if constexpr (!U16 && CU >= 2) {
                 // channel pairs: one branch on both channels' alignment, so
@@ -501,15 +553,6 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
     }
 
     if (!active) return;
-    // the fx terms: summed over the wave, added to lane 63's last block
-#pragma unroll
-    for (int r = 0; r < DPT; ++r) {
-        const uint32_t slo = wave_sum_u32(fx_lo[r]), shi = wave_sum_u32(fx_hi[r]);
-        if (lane == 63) {
-            lo1[r][K - 1] += slo;
-            hi1[r][K - 1] += shi;
-        }
-    }
     const int store_vec = job.store_vec;
 #pragma unroll
     for (int r = 0; r < DPT; ++r) {
