@@ -152,6 +152,35 @@ def test_dedisperse_odd_shapes(amber, torch, case):
         assert np.array_equal(out.cpu().numpy(), ref), kw
 
 
+@pytest.mark.parametrize("case", [(37, 13, 1000, 3.0, 4), (300, 7, 4097, 0.7, 0)], ids=lambda c: "ch%d" % c[0])
+def test_dedisperse_reads_only_its_rows(amber, torch, case):
+    """The input is a view of rows inside a larger buffer whose other rows hold
+    255 everywhere: the staging loads are bounded by the problem's own rows
+    (channel groups that run past the last channel read zeros, not the next
+    row), so every tile matches the oracle on the view's rows alone."""
+    n_chan, n_dm, n_out, step, pad = case
+    rng = np.random.default_rng(n_chan * 1000 + n_dm + 2)
+    freqs = odd_freqs(n_chan, n_dm)
+    d, info = amber.delay_table(freqs, 81.92e-6, n_dm, 1.5, step)
+    do, mx = oracle.delay_table(freqs, 81.92e-6, n_dm, 1.5, step)
+    n_in = n_out + mx
+    stride = (n_in + 3) // 4 * 4 + pad
+    big = np.full((n_chan + 7, stride), 255, dtype=np.uint8)
+    big[3:3 + n_chan] = rng.integers(0, 256, size=(n_chan, stride)).astype(np.uint8)
+    ref = oracle.dedisperse(do, big[3:3 + n_chan], n_in, n_out)
+    dev, bd = torch.from_numpy(d).cuda(), torch.from_numpy(big).cuda()
+    xd = bd[3:3 + n_chan]
+    # the ODD tiles and the beam's default tiles, whose 16-channel groups end
+    # 5 (37 channels) or 12 (300) channels into the last group
+    for kw in ODD_TILES + [dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=16, channel_unroll=16,
+                                dms_per_thread=2)]:
+        say("dedisperse rows of a larger buffer", case, kw)
+        out = amber.dedisperse(dev, info, xd, n_in, n_out,
+                               tiles=amber.make_tiles(**{"dms_per_thread": 1, **kw}) if kw else None)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref), kw
+
+
 @pytest.mark.parametrize("widths", [(1, 2, 4, 8, 16, 32, 64), (1, 1024)], ids=["w1-64", "w1-1024"])
 def test_integrate_snr_automatic_tiles_many_rows(amber, torch, widths):
     """tiles = None with 4096 rows or more: single-wave work-groups, or (width
