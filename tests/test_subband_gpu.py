@@ -185,6 +185,26 @@ def test_subband_edge_lengths_and_repeat(amber, torch):
     assert (out.cpu().numpy() == -7).all()
 
 
+def test_subband_wide_subbands_saturated(amber, torch):
+    """8 subbands of 192 channels over saturated input: step one's sums reach
+    192 * 255 = 48960 (the 16-bit intermediates' range) and step two widens
+    its packed sums after every subband (one more would overflow 16 bits),
+    on several step-two tiles; bit-exact against the oracle."""
+    n_out = 3000
+    grid = (8, 12, 0.0, 16.0, 4, 0.0, 4.0)
+    d1, d2, info, o1, o2, x, n_in = _setup(amber, BEAM, grid, n_out, seed=74)
+    x[:, 500:2600] = 255
+    x[::3, 2600:] = 255
+    ref = oracle.subband_dedisperse(o1, o2, x, n_in, n_out)
+    assert ref.max() == 1536 * 255
+    for t2 in (None, dict(threads_per_dm=64, samples_per_thread=8, dms_per_block=4, channel_unroll=4),
+               dict(threads_per_dm=64, samples_per_thread=16, dms_per_block=8, channel_unroll=4)):
+        say("wide subbands saturated", info, t2)
+        got = _run(amber, torch, d1, d2, info, x, n_in, n_out,
+                   tiles2=amber.make_tiles(dms_per_thread=1, **t2) if t2 else None).cpu().numpy()
+        assert np.array_equal(got, ref), t2
+
+
 def test_subband_masked(amber, torch):
     n_out = 2500
     d1, d2, info, o1, o2, x, n_in = _setup(amber, SMALL, SMALL_GRID, n_out, seed=71, pulse=(80.0, 1000, 2))
