@@ -115,14 +115,19 @@ struct StageArgs {
     int n_chan, items_per_row, n_items;
 };
 
-// A staging item is two chunks of 8 samples half a row apart (chunks it and
-// it + items_per_row of its row), each loaded with one dword of lookahead:
-// the item's writes of one chunk and copy then cover consecutive 16-byte
-// lines across the lanes, which reach every LDS bank.
+// A staging item is two chunks of 8 samples.  uint8 input: the chunks lie
+// half a row apart (chunks it and it + items_per_row of its row), each loaded
+// with one dword of lookahead, so that the item's writes of one chunk and
+// copy cover consecutive 16-byte lines across the lanes, which reach every
+// LDS bank.  uint16 input (subband step two): the chunks are adjacent (chunks
+// 2 it and 2 it + 1), loaded as one piece of 16 samples and a dword of
+// lookahead, the first chunk's lookahead being the second's first dword:
+// three loads instead of four, which measured faster there than covering
+// every bank.  `at` is the first dword of chunk 1 in the item's registers.
 template <bool U16>
 struct Item {
-    static constexpr int chunk = U16 ? 5 : 3;  // dwords per chunk
-    static constexpr int dwords = 2 * chunk;
+    static constexpr int at = U16 ? 4 : 3;
+    static constexpr int dwords = U16 ? 9 : 6;
 };
 
 // A buffer resource over n bytes from p: loads past the end read zero.
@@ -170,28 +175,32 @@ __device__ __forceinline__ void stage_load(const StageArgs &a, int c0, const Ite
     const int rest_hi = (int)(rest >> 32);
     const uint32_t n = rest_hi < 0 ? 0u : (rest_hi > 0 ? rows : min((uint32_t)rest, rows));
     const __amdgpu_buffer_rsrc_t rs = range_rsrc(a.in + (n ? start : 0), n);
-    const uint32_t half = (U16 ? 16u : 8u) * (uint32_t)a.items_per_row;  // bytes between the chunks
+    const uint32_t half = 8u * (uint32_t)a.items_per_row;  // bytes between the chunks of a uint8 item
 #pragma unroll
     for (int m = 0; m < MAXI; ++m) {
         // first sample of the window, rounded down to a dword boundary (t0 is
         // a multiple of 4)
         const uint32_t o = ib.off[m] + (U16 ? ((uint32_t)df[m] << 1) & ~3u : (uint32_t)df[m] & ~3u);
+        uint32_t *d = w[m];
+        if constexpr (U16) {
+            const i32x4v v0 = __builtin_amdgcn_raw_buffer_load_b128(rs, o, 0, 0);
+            const i32x4v v1 = __builtin_amdgcn_raw_buffer_load_b128(rs, o + 16u, 0, 0);
+            d[0] = v0.x;
+            d[1] = v0.y;
+            d[2] = v0.z;
+            d[3] = v0.w;
+            d[4] = v1.x;
+            d[5] = v1.y;
+            d[6] = v1.z;
+            d[7] = v1.w;
+            d[8] = __builtin_amdgcn_raw_buffer_load_b32(rs, o + 32u, 0, 0);
+        } else {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const uint32_t oh = o + (h ? half : 0u);
-            uint32_t *d = &w[m][h * Item<U16>::chunk];
-            if constexpr (U16) {
-                const i32x4v v = __builtin_amdgcn_raw_buffer_load_b128(rs, oh, 0, 0);
-                d[0] = v.x;
-                d[1] = v.y;
-                d[2] = v.z;
-                d[3] = v.w;
-                d[4] = __builtin_amdgcn_raw_buffer_load_b32(rs, oh + 16u, 0, 0);
-            } else {
-                const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, oh, 0, 0);
-                d[0] = v[0];
-                d[1] = v[1];
-                d[2] = v[2];
+            for (int h = 0; h < 2; ++h) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, o + (h ? half : 0u), 0, 0);
+                d[3 * h] = v[0];
+                d[3 * h + 1] = v[1];
+                d[3 * h + 2] = v[2];
             }
         }
     }
@@ -213,10 +222,11 @@ __device__ __forceinline__ void stage_store(lds_w4 *lds, int win2, int items_per
     int copy_w4 = (CU * win2) >> 2, half_w4 = items_per_row;
     asm volatile("s_mov_b32 %0, %0" : "+s"(copy_w4));
     asm volatile("s_mov_b32 %0, %0" : "+s"(half_w4));
-    lds = lds + ((j * win2) >> 2) + it;
+    if (U16) half_w4 = 1;  // adjacent chunks
+    lds = lds + ((j * win2) >> 2) + (U16 ? 2 * it : it);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const uint32_t *c = &w[h * Item<U16>::chunk];
+        const uint32_t *c = &w[h * Item<U16>::at];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             uint32_t d[4];
@@ -340,7 +350,8 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
         const int it = q - j * sa.items_per_row;
         // (an item past the last one, never stored, may wrap: its loads stay
         // range-checked)
-        ib.off[m] = (uint32_t)j * (uint32_t)sa.in_stride + (U16 ? 2u : 1u) * ((uint32_t)t0 + 8u * (uint32_t)it);
+        ib.off[m] = (uint32_t)j * (uint32_t)sa.in_stride + (U16 ? 2u * ((uint32_t)t0 + 16u * (uint32_t)it)
+                                                               : (uint32_t)t0 + 8u * (uint32_t)it);
         ib.dch[m] = 4u * (uint32_t)j;
     }
     uint32_t pre[MAXI][Item<U16>::dwords];
