@@ -145,18 +145,20 @@ struct ItemBase {
 };
 
 // Issues the loads of staging items tid + m * nthreads (m < MAXI) of the
-// channel group starting at c0: two chunks of 8 samples + lookahead each.
-// The loads are buffer loads over the group's rows up to the job's last
-// channel (and the delays of those channels), so the hardware range check
-// turns every dword past them (past the last row's samples, or an item past
-// the last channel) into zero; no load sits under a branch and nothing here
-// reads a loaded value except the delays, so the input loads stay in flight
-// through the group's sums (buffer loads count against the vector-memory
-// counter only: flat loads through generic pointers would also count against
-// the LDS one, and every wait for a sum's LDS read would wait for them).  Offsets are 32-bit from the group's first row:
-// the host keeps channel_unroll * in_stride below 2^32, and a window that
-// runs past its row's end (or wraps, or starts before the buffer for a table
-// that breaks its contract) only feeds outputs at or past n_out.
+// channel group starting at c0: two chunks of 8 samples + lookahead each
+// (one piece of 16 for 16-bit input).  The loads are buffer loads over the
+// group's rows up to the job's last channel (and the delays of those
+// channels), so the hardware range check turns every dword past them (past
+// the last row's samples, or an item past the last channel) into zero; no
+// load sits under a branch and nothing here reads a loaded value except the
+// delays, so the input loads stay in flight through the group's sums (buffer
+// loads count against the vector-memory counter only: flat loads through
+// generic pointers would also count against the LDS one, and every wait for
+// a sum's LDS read would wait for them).  Offsets are 32-bit from the
+// group's first row: the host keeps channel_unroll * in_stride below 2^32,
+// and a window that runs past its row's end (or wraps, or starts before the
+// buffer for a table that breaks its contract) only feeds outputs at or past
+// n_out.
 template <int CU, bool U16, int MAXI>
 __device__ __forceinline__ void stage_load(const StageArgs &a, int c0, const ItemBase<U16, MAXI> &ib,
                                            uint32_t (&w)[MAXI][Item<U16>::dwords])
@@ -208,7 +210,7 @@ __device__ __forceinline__ void stage_load(const StageArgs &a, int c0, const Ite
 
 // Writes staging item q (two chunks of 8 samples) as 16-bit values into the
 // two copies: copy s, dword m of a chunk holds its samples 2m + s and
-// 2m + s + 1.
+// 2m + s + 1.  A chunk and copy is one 16-byte line.
 template <int CU, bool U16>
 __device__ __forceinline__ void stage_store(lds_w4 *lds, int win2, int items_per_row, int n_items, int q,
                                             uint32_t (&w)[Item<U16>::dwords])
