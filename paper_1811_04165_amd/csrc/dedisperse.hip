@@ -332,12 +332,19 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
     uint32_t e0[DPT][K], e1[DPT][K], od[DPT][K];
     uint32_t lo0[DPT][K], hi0[DPT][K], lo1[DPT][K], hi1[DPT][K];
     // the last block's lane 63 second dword from odd-aligned reads: summed
-    // per channel by lane j into packed sums fx, which each widening sums
-    // over the wave into lane 63's totals
-    uint32_t fx[DPT];
+    // per channel by lane j, and added to lane 63's totals over the wave.
+    // uint8 input: packed sums fx, summed over the wave at each widening
+    // (every 256 channels).  uint16 input, whose packed sums are widened
+    // every few channels: 32-bit halves fxl / fxh summed over the wave once
+    // at the end, and likewise the od sums widened in place (odl / odh) and
+    // moved one lane down once at the end, not at every widening.
+    uint32_t fx[DPT], fxl[DPT], fxh[DPT];
+    uint32_t odl[DPT][K], odh[DPT][K];
 #pragma unroll
     for (int r = 0; r < DPT; ++r) {
-        fx[r] = 0u;
+        fx[r] = fxl[r] = fxh[r] = 0u;
+#pragma unroll
+        for (int k = 0; k < K; ++k) odl[r][k] = odh[r][k] = 0u;
 #pragma unroll
         for (int k = 0; k < K; ++k) e0[r][k] = e1[r][k] = od[r][k] = lo0[r][k] = hi0[r][k] = lo1[r][k] = hi1[r][k] = 0u;
     }
@@ -398,6 +405,21 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
     // from odd-aligned reads is its right neighbour's od (lane 63: the next
     // block's lane 0; for the last block it is the fx term).
     auto widen = [&]() {
+        if constexpr (U16) {
+#pragma unroll
+            for (int r = 0; r < DPT; ++r)
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    lo0[r][k] += e0[r][k] & 0xffffu;
+                    hi0[r][k] += e0[r][k] >> 16;
+                    lo1[r][k] += e1[r][k] & 0xffffu;
+                    hi1[r][k] += e1[r][k] >> 16;
+                    odl[r][k] += od[r][k] & 0xffffu;
+                    odh[r][k] += od[r][k] >> 16;
+                    e0[r][k] = e1[r][k] = od[r][k] = 0u;
+                }
+            return;
+        }
 #pragma unroll
         for (int r = 0; r < DPT; ++r)
 #pragma unroll
@@ -468,7 +490,12 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
                 // address stays in range)
                 const bool odd = odd_l[r];
                 const uint32_t v = *(lds_u1 *)(ldsb + (odd ? chan_al[r] : 0u) + 512u * K);
-                fx[r] += odd ? v : 0u;
+                if constexpr (U16) {
+                    fxl[r] += odd ? (v & 0xffffu) : 0u;
+                    fxh[r] += odd ? (v >> 16) : 0u;
+                } else {
+                    fx[r] += odd ? v : 0u;
+                }
             }
             if constexpr (!U16 && CU >= 2) {
                 // channel pairs: one branch on both channels' alignment, so
@@ -566,6 +593,21 @@ void dedisperse_kernel(DedispJob single, const DedispJob *__restrict__ jobs, int
     }
 
     if (!active) return;
+    if constexpr (U16) {
+        // the od totals one lane down (lane 63: the next block's lane 0; for
+        // the last block the fx terms summed over the wave)
+#pragma unroll
+        for (int r = 0; r < DPT; ++r) {
+            const uint32_t slo = wave_sum_u32(fxl[r]), shi = wave_sum_u32(fxh[r]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t nl = k + 1 < K ? (uint32_t)__builtin_amdgcn_readlane((int)odl[r][k + 1], 0) : slo;
+                const uint32_t nh = k + 1 < K ? (uint32_t)__builtin_amdgcn_readlane((int)odh[r][k + 1], 0) : shi;
+                lo1[r][k] += (uint32_t)__builtin_amdgcn_update_dpp((int)nl, (int)odl[r][k], 0x130, 0xf, 0xf, false);
+                hi1[r][k] += (uint32_t)__builtin_amdgcn_update_dpp((int)nh, (int)odh[r][k], 0x130, 0xf, 0xf, false);
+            }
+        }
+    }
     const int store_vec = job.store_vec;
 #pragma unroll
     for (int r = 0; r < DPT; ++r) {
