@@ -61,3 +61,25 @@ def test_ga_study_replay_on_a_synthetic_table():
         assert all(math.isfinite(v) and v >= 0 for v in st["cv_end_population"].values()), st["name"]
         assert st["best_over_bf"]["median"] >= 1.0 - 1e-9
         assert set(st["best_gene_histograms"]) == set(names)
+
+
+def test_traffic_is_reported_only_for_the_profiled_kernel_source(tmp_path, monkeypatch):
+    """roofline.traffic comes from the committed counter record while its
+    kernel hash is the dedispersion source's, and is null for any other
+    source (the counters describe a kernel that no longer exists)."""
+    import json
+    import bench
+    rec = json.load(open(bench.PMC_FILE))
+    for k in ("kernel_sha", "fetch_size_kib", "write_size_kib", "hbm_bytes_per_launch", "copy_calibration",
+              "commands"):
+        assert k in rec
+    assert rec["hbm_bytes_per_launch"] == pytest.approx(
+        rec["fetch_size_kib"] * 1024 * rec["copy_calibration"]["fetch_factor"] +
+        rec["write_size_kib"] * 1024 * rec["copy_calibration"]["write_factor"], rel=1e-3)
+    # the committed record belongs to the committed kernel source
+    assert rec["kernel_sha"] == bench.kernel_hash()
+    assert bench.measured_traffic(1.0) == rec["hbm_bytes_per_launch"]
+    other = tmp_path / "dedisperse.hip"
+    other.write_bytes(open(bench.KERNEL_SRC, "rb").read() + b"\n// changed\n")
+    monkeypatch.setattr(bench, "KERNEL_SRC", str(other))
+    assert bench.measured_traffic(1.0) is None
